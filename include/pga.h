@@ -1,0 +1,189 @@
+/*
+ * pga.h -- C ABI of libpga, the gfx950 (MI355X) library for the master-slave
+ * parallel genetic algorithm that maximises the Giada-Marsili cluster
+ * likelihood (Hendricks, Gebbie & Wilcox, arXiv 1403.4099).
+ *
+ * Problem statement followed (Section 2.2.3; Section 4.2.1; Section 5.2.2):
+ * the input is the Pearson correlation matrix C of N stocks (Eq. 7); the
+ * output is a cluster configuration, one integer label per stock, with the
+ * number of clusters left free (labels range over N values, Eq. 9). Fitness
+ * is the likelihood L_c of Eq. 8 built from n_s (Eq. 5) and c_s (Eq. 6).
+ * The GA follows Algorithm 1 (Section 4.2.3) with every step on the GPU.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller unless marked
+ *     "host". The library keeps no pointer after the call returns, except
+ *     that work enqueued on `stream` reads and writes them until it runs.
+ *   - Matrices are row-major and 0-based. Labels are int32 in [0, N).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls are asynchronous on that stream unless marked SYNC.
+ *   - Return value: PGA_OK, or a negative PGA_ERR_* code detected on the
+ *     host from the arguments alone, in which case nothing was enqueued.
+ *   - `status` (nullable) is int32[PGA_STATUS_WORDS] on the device. Kernels
+ *     add counts to it with integer atomics; the caller zeroes it and reads
+ *     it after synchronising the stream. Words:
+ *       [PGA_ST_LABEL]     individuals holding a label outside [0, N)
+ *       [PGA_ST_DOMAIN]    clusters with n_s > 1 and c_s outside (0, n_s^2)
+ *       [PGA_ST_ZEROVAR]   stocks with zero variance (correlation)
+ *       [PGA_ST_NONFINITE] individuals whose fitness was set to -inf
+ *     An individual counted in LABEL or DOMAIN gets fitness -inf, so it
+ *     ranks last and never wins a tournament against a valid one.
+ *   - Workspace: entry points that need scratch device memory take
+ *     (ws, ws_bytes); the matching *_ws_bytes() function gives the size.
+ *     The library allocates no device memory in any of these calls.
+ */
+#ifndef PGA_H
+#define PGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PGA_OK 0
+#define PGA_ERR_ARG (-1)          /* invalid argument (null pointer, size, form, parameter) */
+#define PGA_ERR_WORKSPACE (-2)    /* ws null or smaller than the *_ws_bytes() figure */
+#define PGA_ERR_HIP (-3)          /* a HIP runtime call failed; see pga_last_hip_error() */
+#define PGA_ERR_UNSUPPORTED (-4)  /* size beyond a documented limit (e.g. N > PGA_N_MAX) */
+
+#define PGA_FORM_FP64 0           /* c_s by FP64 masked pair sums on the vector ALUs */
+#define PGA_FORM_BF16X2 1         /* c_s by BF16 hi+lo one-hot contraction on MFMA, FP32 accumulate */
+
+#define PGA_STATUS_WORDS 8
+#define PGA_ST_LABEL 0
+#define PGA_ST_DOMAIN 1
+#define PGA_ST_ZEROVAR 2
+#define PGA_ST_NONFINITE 3
+
+#define PGA_N_MAX 4096            /* largest number of stocks per instance */
+#define PGA_E_MAX 64              /* largest elite count */
+
+#define PGA_EVOLVE_INIT 1         /* fill pop with the initial population at gen0 first */
+#define PGA_EVOLVE_EAGER 2        /* launch kernels one by one instead of replaying a HIP graph */
+
+/* Opaque per-thread context: holds captured HIP graphs and a pinned staging
+ * buffer for instance descriptors. Not thread-safe; one per host thread. */
+typedef struct pga_ctx pga_ctx;
+
+/* GA parameters of one instance (Table 3 of Section 5.2.1 lists the paper's
+ * own; this build uses tournament selection of size 2, uniform crossover and
+ * per-gene random-replacement mutation). */
+typedef struct {
+    int32_t elites;        /* E, 0 <= E < P, E <= PGA_E_MAX (elitism, Section 3.1) */
+    int32_t tournament;    /* tournament size; must be 2 */
+    uint32_t p_cross_thr;  /* crossover when a uniform u32 is below this (0.9 -> 3865470566) */
+    uint32_t p_mut_thr;    /* per-gene mutation when a uniform u32 is below this (1/N -> floor(2^32/N)) */
+    uint64_t seed;         /* Philox4x32-10 key: (seed & 0xffffffff, seed >> 32) */
+    uint32_t instance_id;  /* goes into every Philox counter; < 2^28 */
+    uint32_t gen0;         /* absolute generation index of the population in `pop` on entry */
+} pga_params;
+
+/* One GA instance. Host struct holding device pointers. */
+typedef struct {
+    int32_t N;             /* stocks, 1 <= N <= PGA_N_MAX */
+    int32_t P;             /* population size, P >= 2 */
+    const double *C;       /* N x N correlation, symmetric; the kernels read the diagonal and i < j */
+    const uint16_t *C_hi;  /* bf16 hi part, pga_split_ld(N)^2 layout; PGA_FORM_BF16X2 only */
+    const uint16_t *C_lo;  /* bf16 lo part, same layout */
+    int32_t *pop;          /* P x N labels: generation gen0 on entry, gen0 + G on return */
+    int32_t *pop_tmp;      /* P x N scratch, ping-pong partner of pop */
+    double *fitness;       /* P: on return, the fitness of the final population */
+    double *stats;         /* nullable; (G + 1) x 4 rows {best, mean of finite, #-inf, argbest} */
+    pga_params prm;
+} pga_instance;
+
+/* ---- context and errors ------------------------------------------------ */
+int pga_ctx_create(pga_ctx **out);
+int pga_ctx_destroy(pga_ctx *ctx);
+const char *pga_strerror(int code);
+int pga_last_hip_error(void);     /* hipError_t of the last PGA_ERR_HIP on this thread */
+
+/* ---- correlation (Eq. 7) ---------------------------------------------- */
+/* C_ij = sum_t x_it x_jt / sqrt(s_i s_j) with x_it = R_it - mean_t R_it and
+ * s_i = sum_t x_it^2 (zero-mean data as in Eq. 2; the norm in Eq. 7 is the
+ * sum of squares). R: N x T FP64, row stride ld_r >= T. C: N x N FP64 out.
+ * C_ii = 1 exactly; off-diagonal values are clamped to [-1, 1]; a stock with
+ * s_i = 0 gets 0 off the diagonal and is counted in status[PGA_ST_ZEROVAR].
+ * C_hi / C_lo (nullable, both or neither): also write the BF16 split of C
+ * (as pga_split). Requires 1 <= N <= PGA_N_MAX, T >= 2. */
+size_t pga_correlate_ws_bytes(int32_t N);   /* 2N doubles: row means and sums of squares */
+int pga_correlate(const double *R, int32_t N, int32_t T, int64_t ld_r, double *C,
+                  uint16_t *C_hi, uint16_t *C_lo, int32_t *status, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* ---- BF16 hi + lo split of C (mixed-precision form) ------------------- */
+/* Leading dimension (and row count) of the split arrays: N rounded up to 32.
+ * Entries outside the N x N corner are written as zero. */
+int32_t pga_split_ld(int32_t N);
+/* C_hi = bf16(C), C_lo = bf16(C - C_hi), each rounded to nearest, ties to
+ * even, from the FP64 value (C - C_hi is exact in FP64). Arrays are
+ * pga_split_ld(N) x pga_split_ld(N) uint16 bit patterns. */
+int pga_split(const double *C, int32_t N, uint16_t *C_hi, uint16_t *C_lo, void *stream);
+
+/* ---- fitness (Eqs. 5, 6, 8) -------------------------------------------- */
+/* For each of the P labelings (labels: P x N int32):
+ *   n_s = #{i : s_i = s}, c_s = sum_{i,j} C_ij [s_i = s][s_j = s] (diagonal
+ *   included, computed as sum_i C_ii + 2 sum_{i<j} for symmetric C),
+ *   fitness = 1/2 sum_{s: n_s > 1} [log(n_s/c_s) + (n_s-1) log((n_s^2-n_s)/(n_s^2-c_s))]
+ * in natural log, literal also when c_s < n_s. n_s (P x N int32) and c_s
+ * (P x N FP64), nullable, receive the per-label values (index = label); for
+ * an individual with an out-of-range label both rows are zero.
+ * form PGA_FORM_FP64: FP64 throughout. form PGA_FORM_BF16X2: the pair sums
+ * use C_hi + C_lo on MFMA with FP32 accumulation (flushed to FP64 every 256
+ * stocks); diagonal, c_s, logs and the sum over clusters stay FP64.
+ * C_hi/C_lo may be NULL for PGA_FORM_FP64. P = 0 is a no-op. */
+size_t pga_fitness_ws_bytes(int32_t N, int32_t P, int32_t form);
+int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
+                const int32_t *labels, int32_t P, int32_t form, double *fitness,
+                int32_t *n_s, double *c_s, int32_t *status, void *ws, size_t ws_bytes,
+                void *stream);
+
+/* ---- evolution (Algorithm 1) ------------------------------------------- */
+/* Runs `generations` (G >= 0) generations on each of the n_inst instances
+ * (inst is a HOST array; the descriptors are copied before return, the
+ * buffers they point to are used asynchronously). Per generation g (absolute
+ * index gen0 + k): fitness of pop_g; statistics row k; the E fittest copied
+ * unchanged to slots 0..E-1 (ties: lower index first); each child slot
+ * c >= E gets parents A and B from two tournaments of two (higher fitness
+ * wins, ties to the lower index), uniform crossover with probability
+ * p_cross, then per-gene mutation to a uniform label. After G generations
+ * the final population is evaluated into `fitness` and stats row G.
+ * Random draws come from Philox4x32-10 with counter
+ *   (block, individual or child, generation, tag | instance_id << 4),
+ * tags INIT=0, SELECT=1, CROSSOVER=2, MUTATION=3, so a run is a pure
+ * function of (pop at gen0, seed, instance_id, gen0, G): evolving 0->g then
+ * g->G equals 0->G bit for bit, alone or batched with other instances.
+ * flags: PGA_EVOLVE_INIT fills pop at gen0 first; PGA_EVOLVE_EAGER skips the
+ * HIP graph. All instances use the same `form`. */
+size_t pga_evolve_ws_bytes(const pga_instance *inst, int32_t n_inst, int32_t form);
+int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t generations,
+               int32_t form, int32_t flags, void *ws, size_t ws_bytes, int32_t *status,
+               void *stream);
+
+/* ---- result (Algorithm 1 "report on results"; Section 4.2.6) ----------- */
+/* SYNC. Picks the fittest of P labelings (lowest index among ties), relabels
+ * it in first-occurrence order (first stock's cluster -> 0, next new cluster
+ * -> 1, ...; out-of-range labels are copied unchanged), and copies to HOST
+ * memory: out_labels (N int32), out_fitness, out_index (each nullable). */
+size_t pga_best_ws_bytes(int32_t N);
+int pga_best(const double *fitness, const int32_t *labels, int32_t P, int32_t N,
+             int32_t *out_labels, double *out_fitness, int32_t *out_index, void *ws,
+             size_t ws_bytes, void *stream);
+
+/* ---- kernel timing (measurement support) -------------------------------- */
+/* When enabled, every launch of a timed kernel is bracketed by HIP events on
+ * the stream it runs on (graph replay is then replaced by eager launches).
+ * pga_timing_read synchronises the recorded events and returns the summed
+ * elapsed milliseconds and launch count for kernel id
+ *   0 pair-sum FP64, 1 pair-sum BF16x2 MFMA, 2 finish (n_s, c_s, L_c),
+ *   3 rank/stats, 4 breed, 5 correlate, 6 split, 7 init. */
+int pga_timing_enable(int on);
+int pga_timing_reset(void);
+int pga_timing_read(int kernel_id, double *total_ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PGA_H */

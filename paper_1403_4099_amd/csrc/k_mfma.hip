@@ -1,0 +1,143 @@
+// BF16x2 pair-sum on MFMA: w_pj = sum_{i<j} [s_pi = s_pj] (hi_ji + lo_ji)
+// as the diagonal of a one-hot contraction (c_s = diag(Y^T C Y), Eq. 6).
+//
+// One wave owns 16 stocks j = jt0 .. jt0+15 and walks the rows i < j in
+// chunks of 32 with v_mfma_f32_16x16x32_bf16:
+//   A[m][k] = C[jt0 + m][i0 + k]           (hi, then lo: two MFMAs)
+//   B[k][n] = [s_{i0+k} = s_{jt0+n}] [i0 + k < jt0 + n]   (0 or bf16 1.0)
+//   D[m][n] += sum_k A[m][k] B[k][n];  D[n][n] = partial w_{jt0+n}
+// Lane l supplies row m = l%16 of A and column n = l%16 of B over the same
+// eight k = 8(l/16)..+7, so its A row and B column are both stock jt0 + l%16:
+// the lane needs only its own stock's label and the 8 row labels of its k
+// block. The one-hot column costs 3 packed 16-bit ALU ops per 2 rows (xor,
+// saturating 1 - x, multiply by the bf16 pattern of 1.0); A is loaded once
+// per (wave, chunk) and reused by the 16 individuals of the workgroup.
+// FP32 accumulation is flushed into FP64 every 256 rows (the LDS label
+// chunk), bounding its rounding to 256 terms.
+#include "pga_internal.hpp"
+
+namespace pga {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t onehot2(uint32_t labs, uint32_t lj2) {
+    const u16x2 x = __builtin_bit_cast(u16x2, labs ^ lj2);
+    const u16x2 one = {1, 1};
+    const u16x2 t = __builtin_elementwise_sub_sat(one, x);   // 1 where equal, else 0
+    const u16x2 bf1 = {0x3F80, 0x3F80};                        // bf16 1.0
+    return __builtin_bit_cast(uint32_t, t * bf1);
+}
+
+__global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
+    constexpr int B = kMfmaB;
+    constexpr int RC = kMfmaRowChunk;
+    __shared__ __align__(16) uint16_t lab_s[B][RC];
+
+    const int tile = blockIdx.x;
+    const int k = find_inst(t.tiles_mfma, t.n_inst, tile);
+    const InstDesc &d = t.desc[k];
+    const int N = d.N, P = d.P, ld = d.ld_h;
+    const int local = tile - t.tiles_mfma[k];
+    const int n_jb = (N + kMfmaCols - 1) / kMfmaCols;
+    const int jb = n_jb - 1 - (local % n_jb);            // heaviest column blocks first
+    const int pb = local / n_jb;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = lane & 15, g = lane >> 4;
+    const int jt0 = jb * kMfmaCols + 16 * wave;
+    const int j = jt0 + n;
+    const int pbase = pb * B;
+    const int32_t *__restrict__ labels = d.pop[parity];
+    const uint16_t *__restrict__ hi = d.hi;
+    const uint16_t *__restrict__ lo = d.lo;
+
+    uint32_t lj2[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int p = pbase + b;
+        const uint32_t l = (j < N && p < P) ? (uint32_t)labels[(size_t)p * N + j] & 0xFFFFu : 0xFFFEu;
+        lj2[b] = l | (l << 16);
+    }
+    floatx4 acc[B];
+    double acc64[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc64[b] = 0.0;
+    }
+
+    const int wg_iend = min(jb * kMfmaCols + kMfmaCols, N);   // rows any wave of the group needs
+    const int my_iend = min(jt0 + 16, N);                     // rows this wave needs (i < j <= jt0+15)
+    const bool diag_lane = (n >> 2) == g;                     // lane holds D[n][n] in register n & 3
+    const int dreg = n & 3;
+
+    for (int c0 = 0; c0 < wg_iend; c0 += RC) {
+        // stage labels of rows c0 .. c0+RC-1 for the B individuals (16-bit)
+        for (int e = threadIdx.x; e < B * RC; e += 256) {
+            const int b = e / RC, r = e % RC;
+            const int i = c0 + r, p = pbase + b;
+            lab_s[b][r] = (i < N && p < P) ? (uint16_t)labels[(size_t)p * N + i] : (uint16_t)0xFFFFu;
+        }
+        __syncthreads();
+        const int cend = min(c0 + RC, my_iend);
+        for (int i0 = c0; i0 < cend; i0 += 32) {
+            const int ik = i0 + 8 * g;                        // first of this lane's 8 rows
+            uint4 ah = make_uint4(0, 0, 0, 0), al = make_uint4(0, 0, 0, 0);
+            if (j < ld) {
+                ah = *(const uint4 *)(hi + (size_t)j * ld + ik);
+                al = *(const uint4 *)(lo + (size_t)j * ld + ik);
+            }
+            const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah);
+            const bf16x8 Al = __builtin_bit_cast(bf16x8, al);
+            // mask for rows i >= j (only the chunk that reaches the diagonal)
+            uint32_t m0 = 0xFFFFFFFFu, m1 = 0xFFFFFFFFu, m2 = 0xFFFFFFFFu, m3 = 0xFFFFFFFFu;
+            if (i0 + 32 > jt0) {
+                auto pm = [&](int r) -> uint32_t {
+                    const uint32_t lo16 = (ik + r < j) ? 0xFFFFu : 0u;
+                    const uint32_t hi16 = (ik + r + 1 < j) ? 0xFFFF0000u : 0u;
+                    return lo16 | hi16;
+                };
+                m0 = pm(0);
+                m1 = pm(2);
+                m2 = pm(4);
+                m3 = pm(6);
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const uint4 lv = *(const uint4 *)&lab_s[b][ik - c0];
+                uint4 bv;
+                bv.x = onehot2(lv.x, lj2[b]) & m0;
+                bv.y = onehot2(lv.y, lj2[b]) & m1;
+                bv.z = onehot2(lv.z, lj2[b]) & m2;
+                bv.w = onehot2(lv.w, lj2[b]) & m3;
+                const bf16x8 Bv = __builtin_bit_cast(bf16x8, bv);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bv, acc[b], 0, 0, 0);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bv, acc[b], 0, 0, 0);
+            }
+        }
+        // flush the FP32 diagonal into FP64
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const float v = dreg == 0 ? acc[b][0] : dreg == 1 ? acc[b][1] : dreg == 2 ? acc[b][2] : acc[b][3];
+            acc64[b] += (double)v;
+            acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        __syncthreads();
+    }
+    if (diag_lane && j < N) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int p = pbase + b;
+            if (p < P) d.wsum[(size_t)p * N + j] = acc64[b];
+        }
+    }
+}
+
+hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pairsum_mfma, dim3(total_tiles), dim3(256), 0, s, t, parity);
+    return hipGetLastError();
+}
+
+}  // namespace pga

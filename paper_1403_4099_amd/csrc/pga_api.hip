@@ -1,0 +1,491 @@
+// Host runtime of libpga: the C ABI declared in include/pga.h.
+//
+// Responsibilities: argument checks (errors are returned before anything is
+// enqueued), workspace carving, descriptor upload, the generation schedule
+// of Algorithm 1 (fitness -> rank/statistics -> breed, repeated, then a
+// final fitness), its capture into a HIP graph that is replayed on later
+// calls with the same shapes, and optional per-kernel event timing.
+#include "pga_internal.hpp"
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+using namespace pga;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+#define HIP_TRY(expr)                                 \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) {                       \
+            g_last_hip = (int)e_;                     \
+            return PGA_ERR_HIP;                       \
+        }                                             \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---- kernel timing -----------------------------------------------------------
+struct TimedLaunch {
+    int id;
+    hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_tl;
+double g_tsum[8] = {0};
+int64_t g_tcnt[8] = {0};
+
+template <class F>
+hipError_t timed(int id, hipStream_t s, F &&launch) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        on = g_timing;
+    }
+    if (!on) return launch();
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_tl.push_back(TimedLaunch{id, a, b});
+    return hipSuccess;
+}
+
+bool timing_on() {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    return g_timing;
+}
+
+// ---- workspace layout ----------------------------------------------------------
+// [InstDesc x n][prefix fp64 n+1][prefix mfma n+1][prefix inds n+1]
+// then per instance: [wsum P x N doubles][elite PGA_E_MAX int32]
+struct Layout {
+    size_t desc_off, pre_off, inst_off;
+    std::vector<size_t> wsum_off, elite_off;
+    size_t total;
+};
+
+Layout make_layout(const int32_t *Ns, const int32_t *Ps, int n) {
+    Layout L;
+    L.desc_off = 0;
+    L.pre_off = align_up(sizeof(InstDesc) * (size_t)n, 256);
+    L.inst_off = align_up(L.pre_off + sizeof(int32_t) * 3 * ((size_t)n + 1), 256);
+    size_t off = L.inst_off;
+    for (int k = 0; k < n; ++k) {
+        L.wsum_off.push_back(off);
+        off = align_up(off + sizeof(double) * (size_t)Ns[k] * (size_t)Ps[k], 256);
+        L.elite_off.push_back(off);
+        off = align_up(off + sizeof(int32_t) * PGA_E_MAX, 256);
+    }
+    L.total = off;
+    return L;
+}
+
+Tables tables_at(void *ws, const Layout &L, int n) {
+    char *b = (char *)ws;
+    Tables t;
+    t.desc = (const InstDesc *)(b + L.desc_off);
+    t.tiles_fp64 = (const int32_t *)(b + L.pre_off);
+    t.tiles_mfma = t.tiles_fp64 + (n + 1);
+    t.inds = t.tiles_mfma + (n + 1);
+    t.n_inst = n;
+    return t;
+}
+
+// ---- the schedule ----------------------------------------------------------------
+struct Shape {
+    int n_inst, tiles_fp64, tiles_mfma, inds, max_n;
+};
+
+hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, int32_t *status,
+                       hipStream_t s) {
+    hipError_t e;
+    if (form == PGA_FORM_FP64)
+        e = timed(0, s, [&] { return launch_pairsum_fp64(t, sh.tiles_fp64, parity, s); });
+    else
+        e = timed(1, s, [&] { return launch_pairsum_mfma(t, sh.tiles_mfma, parity, s); });
+    if (e != hipSuccess) return e;
+    return timed(2, s, [&] { return launch_finish(t, sh.inds, sh.max_n, parity, status, s); });
+}
+
+hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, int32_t *status,
+                           hipStream_t s) {
+    hipError_t e;
+    for (int k = 0; k < G; ++k) {
+        const int parity = k & 1;
+        if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
+        if ((e = timed(3, s, [&] { return launch_rank(t, k, s); })) != hipSuccess) return e;
+        if ((e = timed(4, s, [&] { return launch_breed(t, sh.inds, parity, k, s); })) != hipSuccess) return e;
+    }
+    const int parity = G & 1;
+    if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
+    if ((e = timed(3, s, [&] { return launch_rank(t, G, s); })) != hipSuccess) return e;
+    if (G & 1) {
+        if ((e = launch_copy_back(t, sh.inds, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+// ---- context ---------------------------------------------------------------------
+struct GraphKey {
+    void *ws;
+    int32_t *status;
+    int n_inst, form, G, tiles_fp64, tiles_mfma, inds, max_n;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(ws, status, n_inst, form, G, tiles_fp64, tiles_mfma, inds, max_n) <
+               std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles_fp64, o.tiles_mfma, o.inds, o.max_n);
+    }
+};
+
+struct pga_ctx {
+    hipStream_t cap = nullptr;
+    void *staging = nullptr;
+    size_t staging_bytes = 0;
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+};
+
+extern "C" {
+
+int pga_ctx_create(pga_ctx **out) {
+    if (!out) return PGA_ERR_ARG;
+    pga_ctx *c = new pga_ctx();
+    hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        delete c;
+        return PGA_ERR_HIP;
+    }
+    *out = c;
+    return PGA_OK;
+}
+
+int pga_ctx_destroy(pga_ctx *c) {
+    if (!c) return PGA_ERR_ARG;
+    for (auto &kv : c->graphs) {
+        hipGraphExecDestroy(kv.second.second);
+        hipGraphDestroy(kv.second.first);
+    }
+    if (c->upload_pending) hipEventSynchronize(c->upload_done);
+    if (c->staging) hipHostFree(c->staging);
+    if (c->upload_done) hipEventDestroy(c->upload_done);
+    if (c->cap) hipStreamDestroy(c->cap);
+    delete c;
+    return PGA_OK;
+}
+
+const char *pga_strerror(int code) {
+    switch (code) {
+        case PGA_OK: return "ok";
+        case PGA_ERR_ARG: return "invalid argument";
+        case PGA_ERR_WORKSPACE: return "workspace missing or too small";
+        case PGA_ERR_HIP: return "HIP runtime error";
+        case PGA_ERR_UNSUPPORTED: return "size beyond a documented limit";
+        default: return "unknown error";
+    }
+}
+
+int pga_last_hip_error(void) { return g_last_hip; }
+
+// ---- correlation and split ----------------------------------------------------------
+int32_t pga_split_ld(int32_t N) { return N < 1 ? 0 : split_ld(N); }
+
+size_t pga_correlate_ws_bytes(int32_t N) {
+    if (N < 1) return 0;
+    return align_up(sizeof(double) * 2 * (size_t)N, 256);
+}
+
+int pga_correlate(const double *R, int32_t N, int32_t T, int64_t ld_r, double *C, uint16_t *C_hi,
+                  uint16_t *C_lo, int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+    if (!R || !C || N < 1 || T < 2 || ld_r < T) return PGA_ERR_ARG;
+    if ((C_hi == nullptr) != (C_lo == nullptr)) return PGA_ERR_ARG;
+    if (N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < pga_correlate_ws_bytes(N)) return PGA_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    double *mu = (double *)ws, *ss = mu + N;
+    HIP_TRY(timed(5, s, [&] {
+        hipError_t e = launch_row_stats(R, N, T, ld_r, mu, ss, status, s);
+        if (e != hipSuccess) return e;
+        return launch_corr(R, N, T, ld_r, mu, ss, C, s);
+    }));
+    if (C_hi) HIP_TRY(timed(6, s, [&] { return launch_split(C, N, C_hi, C_lo, s); }));
+    return PGA_OK;
+}
+
+int pga_split(const double *C, int32_t N, uint16_t *C_hi, uint16_t *C_lo, void *stream) {
+    if (!C || !C_hi || !C_lo || N < 1) return PGA_ERR_ARG;
+    if (N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(timed(6, s, [&] { return launch_split(C, N, C_hi, C_lo, s); }));
+    return PGA_OK;
+}
+
+// ---- fitness -----------------------------------------------------------------------------
+size_t pga_fitness_ws_bytes(int32_t N, int32_t P, int32_t form) {
+    (void)form;
+    if (N < 1 || P < 0) return 0;
+    const Layout L = make_layout(&N, &P, 1);
+    return L.total;
+}
+
+int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
+                const int32_t *labels, int32_t P, int32_t form, double *fitness, int32_t *n_s,
+                double *c_s, int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+    if (N < 1 || P < 0) return PGA_ERR_ARG;
+    if (form != PGA_FORM_FP64 && form != PGA_FORM_BF16X2) return PGA_ERR_ARG;
+    if (N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
+    if (P == 0) return PGA_OK;
+    if (!C || !labels || !fitness) return PGA_ERR_ARG;
+    if (form == PGA_FORM_BF16X2 && (!C_hi || !C_lo)) return PGA_ERR_ARG;
+    const Layout L = make_layout(&N, &P, 1);
+    if (!ws || ws_bytes < L.total) return PGA_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+
+    InstDesc d{};
+    d.N = N;
+    d.P = P;
+    d.E = 0;
+    d.ld_h = split_ld(N);
+    d.C = C;
+    d.hi = C_hi;
+    d.lo = C_lo;
+    d.pop[0] = const_cast<int32_t *>(labels);
+    d.pop[1] = nullptr;
+    d.fitness = fitness;
+    d.wsum = (double *)((char *)ws + L.wsum_off[0]);
+    d.elite = (int32_t *)((char *)ws + L.elite_off[0]);
+    d.n_s_out = n_s;
+    d.c_s_out = c_s;
+    Tables t = tables_at(ws, L, 1);
+    HIP_TRY(launch_write_desc(d, (InstDesc *)t.desc, (int32_t *)t.tiles_fp64, s));
+    Shape sh{1, fp64_tiles(N, P), mfma_tiles(N, P), P, N};
+    HIP_TRY(run_fitness(t, sh, form, 0, status, s));
+    return PGA_OK;
+}
+
+// ---- evolution ----------------------------------------------------------------------------
+static int check_instances(const pga_instance *inst, int32_t n, int32_t form) {
+    if (!inst || n < 1) return PGA_ERR_ARG;
+    for (int k = 0; k < n; ++k) {
+        const pga_instance &I = inst[k];
+        if (I.N < 1 || I.P < 2) return PGA_ERR_ARG;
+        if (I.N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
+        if (!I.C || !I.pop || !I.pop_tmp || !I.fitness) return PGA_ERR_ARG;
+        if (form == PGA_FORM_BF16X2 && (!I.C_hi || !I.C_lo)) return PGA_ERR_ARG;
+        if (I.prm.elites < 0 || I.prm.elites >= I.P || I.prm.elites > PGA_E_MAX) return PGA_ERR_ARG;
+        if (I.prm.tournament != 2) return PGA_ERR_ARG;
+        if (I.prm.instance_id >= (1u << 28)) return PGA_ERR_ARG;
+    }
+    return PGA_OK;
+}
+
+size_t pga_evolve_ws_bytes(const pga_instance *inst, int32_t n_inst, int32_t form) {
+    if (check_instances(inst, n_inst, form) != PGA_OK) return 0;
+    std::vector<int32_t> Ns(n_inst), Ps(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        Ns[k] = inst[k].N;
+        Ps[k] = inst[k].P;
+    }
+    return make_layout(Ns.data(), Ps.data(), n_inst).total;
+}
+
+int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t generations,
+               int32_t form, int32_t flags, void *ws, size_t ws_bytes, int32_t *status, void *stream) {
+    if (!ctx || generations < 0) return PGA_ERR_ARG;
+    if (form != PGA_FORM_FP64 && form != PGA_FORM_BF16X2) return PGA_ERR_ARG;
+    int rc = check_instances(inst, n_inst, form);
+    if (rc != PGA_OK) return rc;
+    std::vector<int32_t> Ns(n_inst), Ps(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        Ns[k] = inst[k].N;
+        Ps[k] = inst[k].P;
+    }
+    const Layout L = make_layout(Ns.data(), Ps.data(), n_inst);
+    if (!ws || ws_bytes < L.total) return PGA_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+
+    // host image of the descriptor table and prefix arrays
+    const size_t head = L.inst_off;
+    if (ctx->upload_pending) {
+        HIP_TRY(hipEventSynchronize(ctx->upload_done));
+        ctx->upload_pending = false;
+    }
+    if (ctx->staging_bytes < head) {
+        if (ctx->staging) HIP_TRY(hipHostFree(ctx->staging));
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+        HIP_TRY(hipHostMalloc(&ctx->staging, head, hipHostMallocDefault));
+        ctx->staging_bytes = head;
+    }
+    char *hb = (char *)ctx->staging;
+    InstDesc *hd = (InstDesc *)(hb + L.desc_off);
+    int32_t *pf = (int32_t *)(hb + L.pre_off);
+    int32_t *pm = pf + (n_inst + 1);
+    int32_t *pi = pm + (n_inst + 1);
+    pf[0] = pm[0] = pi[0] = 0;
+    Shape sh{n_inst, 0, 0, 0, 0};
+    for (int k = 0; k < n_inst; ++k) {
+        const pga_instance &I = inst[k];
+        InstDesc d{};
+        d.N = I.N;
+        d.P = I.P;
+        d.E = I.prm.elites;
+        d.ld_h = split_ld(I.N);
+        d.C = I.C;
+        d.hi = I.C_hi;
+        d.lo = I.C_lo;
+        d.pop[0] = I.pop;
+        d.pop[1] = I.pop_tmp;
+        d.fitness = I.fitness;
+        d.stats = I.stats;
+        d.wsum = (double *)((char *)ws + L.wsum_off[k]);
+        d.elite = (int32_t *)((char *)ws + L.elite_off[k]);
+        d.p_cross = I.prm.p_cross_thr;
+        d.p_mut = I.prm.p_mut_thr;
+        d.seed = I.prm.seed;
+        d.inst_id = I.prm.instance_id;
+        d.gen0 = I.prm.gen0;
+        d.tile0_fp64 = pf[k];
+        d.tile0_mfma = pm[k];
+        d.ind0 = pi[k];
+        hd[k] = d;
+        pf[k + 1] = pf[k] + fp64_tiles(I.N, I.P);
+        pm[k + 1] = pm[k] + mfma_tiles(I.N, I.P);
+        pi[k + 1] = pi[k] + I.P;
+        if (I.N > sh.max_n) sh.max_n = I.N;
+    }
+    sh.tiles_fp64 = pf[n_inst];
+    sh.tiles_mfma = pm[n_inst];
+    sh.inds = pi[n_inst];
+    HIP_TRY(hipMemcpyAsync(ws, ctx->staging, head, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ctx->upload_done, s));
+    ctx->upload_pending = true;
+
+    Tables t = tables_at(ws, L, n_inst);
+    if (flags & PGA_EVOLVE_INIT) HIP_TRY(timed(7, s, [&] { return launch_init(t, sh.inds, s); }));
+
+    const bool eager = (flags & PGA_EVOLVE_EAGER) || timing_on();
+    if (eager) {
+        HIP_TRY(run_generations(t, sh, form, generations, status, s));
+        return PGA_OK;
+    }
+    GraphKey key{ws, status, n_inst, form, generations, sh.tiles_fp64, sh.tiles_mfma, sh.inds, sh.max_n};
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+        hipError_t e = run_generations(t, sh, form, generations, status, ctx->cap);
+        hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            g_last_hip = (int)(e != hipSuccess ? e : e2);
+            return PGA_ERR_HIP;
+        }
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            g_last_hip = (int)e;
+            return PGA_ERR_HIP;
+        }
+        it = ctx->graphs.emplace(key, std::make_pair(g, ge)).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second.second, s));
+    return PGA_OK;
+}
+
+// ---- best ------------------------------------------------------------------------------------
+size_t pga_best_ws_bytes(int32_t N) {
+    if (N < 1) return 0;
+    return align_up(sizeof(int32_t) * ((size_t)N + 1), 256) + 256;
+}
+
+int pga_best(const double *fitness, const int32_t *labels, int32_t P, int32_t N, int32_t *out_labels,
+             double *out_fitness, int32_t *out_index, void *ws, size_t ws_bytes, void *stream) {
+    if (!fitness || !labels || P < 1 || N < 1) return PGA_ERR_ARG;
+    if (N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
+    const size_t need = pga_best_ws_bytes(N);
+    if (!ws || ws_bytes < need) return PGA_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *dl = (int32_t *)ws;
+    double *df = (double *)((char *)ws + align_up(sizeof(int32_t) * ((size_t)N + 1), 256));
+    HIP_TRY(launch_best(fitness, labels, P, N, dl, df, s));
+    std::vector<int32_t> hl((size_t)N + 1);
+    double hf = 0.0;
+    HIP_TRY(hipMemcpyAsync(hl.data(), dl, sizeof(int32_t) * ((size_t)N + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hf, df, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (out_labels) for (int i = 0; i < N; ++i) out_labels[i] = hl[i];
+    if (out_fitness) *out_fitness = hf;
+    if (out_index) *out_index = hl[N];
+    return PGA_OK;
+}
+
+// ---- timing ----------------------------------------------------------------------------------
+int pga_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+    return PGA_OK;
+}
+
+static int drain_timing() {
+    std::vector<TimedLaunch> v;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        v.swap(g_tl);
+    }
+    for (auto &x : v) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(x.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, x.a, x.b);
+        hipEventDestroy(x.a);
+        hipEventDestroy(x.b);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            return PGA_ERR_HIP;
+        }
+        std::lock_guard<std::mutex> lk(g_tmu);
+        g_tsum[x.id] += ms;
+        g_tcnt[x.id] += 1;
+    }
+    return PGA_OK;
+}
+
+int pga_timing_reset(void) {
+    int rc = drain_timing();
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (int i = 0; i < 8; ++i) {
+        g_tsum[i] = 0.0;
+        g_tcnt[i] = 0;
+    }
+    return rc;
+}
+
+int pga_timing_read(int kernel_id, double *total_ms, int64_t *count) {
+    if (kernel_id < 0 || kernel_id >= 8) return PGA_ERR_ARG;
+    int rc = drain_timing();
+    if (rc != PGA_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (total_ms) *total_ms = g_tsum[kernel_id];
+    if (count) *count = g_tcnt[kernel_id];
+    return PGA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Internal declarations shared by the libpga translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pga.h"
+
+namespace pga {
+
+// Device-side descriptor of one GA instance (or of one pga_fitness call).
+// Written into the workspace before the kernels run; every kernel finds its
+// instance through it, so the same kernels serve one instance or a ragged
+// batch, and a captured HIP graph stays valid when pointers change.
+struct InstDesc {
+    int32_t N, P, E, ld_h;
+    const double *C;
+    const uint16_t *hi, *lo;
+    int32_t *pop[2];            // ping-pong population buffers
+    double *fitness;            // P
+    double *stats;              // (G + 1) x 4 or null
+    double *wsum;               // P x N pair-sum scratch
+    int32_t *elite;             // PGA_E_MAX
+    int32_t *n_s_out;           // P x N or null
+    double *c_s_out;            // P x N or null
+    uint32_t p_cross, p_mut;
+    uint64_t seed;
+    uint32_t inst_id, gen0;
+    int32_t tile0_fp64;         // first pair-sum tile (FP64 kernel) of this instance
+    int32_t tile0_mfma;         // first pair-sum tile (MFMA kernel)
+    int32_t ind0;               // first global individual index
+    int32_t pad_;
+};
+
+// Prefix tables: for n instances, arrays of n + 1 exclusive prefix sums.
+struct Tables {
+    const InstDesc *desc;
+    const int32_t *tiles_fp64;  // prefix of FP64 pair-sum tiles
+    const int32_t *tiles_mfma;  // prefix of MFMA pair-sum tiles
+    const int32_t *inds;        // prefix of individuals
+    int32_t n_inst;
+};
+
+// ---- geometry of the pair-sum kernels --------------------------------------
+constexpr int kFp64Waves = 4;                      // waves per workgroup
+constexpr int kFp64B = 16;                         // individuals per wave
+constexpr int kFp64Cols = 64;                      // columns (stocks j) per workgroup
+constexpr int kFp64Inds = kFp64Waves * kFp64B;     // individuals per workgroup
+
+constexpr int kMfmaWaves = 4;                      // waves per workgroup, 16 columns each
+constexpr int kMfmaCols = 16 * kMfmaWaves;         // columns per workgroup
+constexpr int kMfmaB = 16;                         // individuals per workgroup
+constexpr int kMfmaRowChunk = 256;                 // rows staged in LDS at a time (and FP32 flush period)
+
+inline int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
+inline int32_t fp64_tiles(int32_t N, int32_t P) { return ceil_div(N, kFp64Cols) * ceil_div(P, kFp64Inds); }
+inline int32_t mfma_tiles(int32_t N, int32_t P) { return ceil_div(N, kMfmaCols) * ceil_div(P, kMfmaB); }
+inline int32_t split_ld(int32_t N) { return (int32_t)(((int64_t)N + 31) / 32 * 32); }
+
+// ---- Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) ---------------------
+enum : uint32_t { kTagInit = 0, kTagSel = 1, kTagXov = 2, kTagMut = 3 };
+
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 draw(uint32_t blk, uint32_t who, uint32_t gen, uint32_t tag,
+                                   uint32_t inst, uint64_t seed) {
+    return philox4x32_10(blk, who, gen, tag | (inst << 4), (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// floor(w * m / 2^32)
+__device__ __forceinline__ uint32_t scale_u32(uint32_t w, uint32_t m) { return __umulhi(w, m); }
+
+// Instance lookup: largest k with prefix[k] <= t (prefix is exclusive, n + 1 entries).
+__device__ __forceinline__ int find_inst(const int32_t *prefix, int n, int t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Total order used for ranking, elites and tournaments: higher fitness first,
+// then lower index. -inf compares equal to -inf, so ties among invalid
+// individuals also go to the lower index.
+__device__ __forceinline__ bool ranks_before(double fa, int a, double fb, int b) {
+    return fa > fb || (fa == fb && a < b);
+}
+
+// ---- launchers (defined in the kernel translation units) ---------------------
+hipError_t launch_row_stats(const double *R, int N, int T, int64_t ld, double *mu, double *ss,
+                            int32_t *status, hipStream_t s);
+hipError_t launch_corr(const double *R, int N, int T, int64_t ld, const double *mu, const double *ss,
+                       double *C, hipStream_t s);
+hipError_t launch_split(const double *C, int N, uint16_t *hi, uint16_t *lo, hipStream_t s);
+
+hipError_t launch_write_desc(const InstDesc &d, InstDesc *dst, int32_t *prefix3, hipStream_t s);
+hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, hipStream_t s);
+hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, hipStream_t s);
+hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status, hipStream_t s);
+
+hipError_t launch_init(Tables t, int total_inds, hipStream_t s);
+hipError_t launch_rank(Tables t, int gen_off, hipStream_t s);
+hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, hipStream_t s);
+hipError_t launch_copy_back(Tables t, int total_inds, hipStream_t s);
+hipError_t launch_best(const double *fitness, const int32_t *labels, int P, int N, int32_t *out,
+                       double *out_f, hipStream_t s);
+
+}  // namespace pga

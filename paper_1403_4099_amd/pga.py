@@ -1,0 +1,311 @@
+"""Python binding of libpga (ctypes). Argument marshalling only.
+
+Every step of the path runs in the HIP kernels of libpga.so; this module
+passes device pointers of torch tensors and the current HIP stream through
+the C ABI declared in include/pga.h, and allocates device buffers with
+torch. There is no CPU fallback: if libpga.so is missing or no GPU is
+present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpga.so")
+
+PGA_OK = 0
+FORM_FP64 = 0
+FORM_BF16X2 = 1
+FORMS = {"fp64": FORM_FP64, "bf16x2": FORM_BF16X2}
+STATUS_WORDS = 8
+ST_LABEL, ST_DOMAIN, ST_ZEROVAR, ST_NONFINITE = 0, 1, 2, 3
+N_MAX = 4096
+E_MAX = 64
+EVOLVE_INIT = 1
+EVOLVE_EAGER = 2
+P_CROSS_DEFAULT = int(0.9 * 2**32)
+KERNELS = {"pairsum_fp64": 0, "pairsum_mfma": 1, "finish": 2, "rank": 3, "breed": 4,
+           "correlate": 5, "split": 6, "init": 7}
+
+SYMBOLS = [
+    "pga_ctx_create", "pga_ctx_destroy", "pga_strerror", "pga_last_hip_error",
+    "pga_correlate_ws_bytes", "pga_correlate", "pga_split_ld", "pga_split",
+    "pga_fitness_ws_bytes", "pga_fitness", "pga_evolve_ws_bytes", "pga_evolve",
+    "pga_best_ws_bytes", "pga_best", "pga_timing_enable", "pga_timing_reset", "pga_timing_read",
+]
+
+
+class PgaError(RuntimeError):
+    pass
+
+
+class Params(ct.Structure):
+    _fields_ = [("elites", ct.c_int32), ("tournament", ct.c_int32), ("p_cross_thr", ct.c_uint32),
+                ("p_mut_thr", ct.c_uint32), ("seed", ct.c_uint64), ("instance_id", ct.c_uint32),
+                ("gen0", ct.c_uint32)]
+
+
+class InstanceC(ct.Structure):
+    _fields_ = [("N", ct.c_int32), ("P", ct.c_int32), ("C", ct.c_void_p), ("C_hi", ct.c_void_p),
+                ("C_lo", ct.c_void_p), ("pop", ct.c_void_p), ("pop_tmp", ct.c_void_p),
+                ("fitness", ct.c_void_p), ("stats", ct.c_void_p), ("prm", Params)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpga.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise PgaError(f"{path} not found: build it with paper_1403_4099_amd/build.py")
+    L = ct.CDLL(path)
+    vp, i32, i64, sz = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_size_t
+    sig = {
+        "pga_ctx_create": ([ct.POINTER(vp)], ct.c_int),
+        "pga_ctx_destroy": ([vp], ct.c_int),
+        "pga_strerror": ([ct.c_int], ct.c_char_p),
+        "pga_last_hip_error": ([], ct.c_int),
+        "pga_correlate_ws_bytes": ([i32], sz),
+        "pga_correlate": ([vp, i32, i32, i64, vp, vp, vp, vp, vp, sz, vp], ct.c_int),
+        "pga_split_ld": ([i32], i32),
+        "pga_split": ([vp, i32, vp, vp, vp], ct.c_int),
+        "pga_fitness_ws_bytes": ([i32, i32, i32], sz),
+        "pga_fitness": ([vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp], ct.c_int),
+        "pga_evolve_ws_bytes": ([ct.POINTER(InstanceC), i32, i32], sz),
+        "pga_evolve": ([vp, ct.POINTER(InstanceC), i32, i32, i32, i32, vp, sz, vp, vp], ct.c_int),
+        "pga_best_ws_bytes": ([i32], sz),
+        "pga_best": ([vp, vp, i32, i32, vp, vp, vp, vp, sz, vp], ct.c_int),
+        "pga_timing_enable": ([ct.c_int], ct.c_int),
+        "pga_timing_reset": ([], ct.c_int),
+        "pga_timing_read": ([ct.c_int, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)], ct.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != PGA_OK:
+        L = load()
+        msg = L.pga_strerror(rc).decode()
+        hip = L.pga_last_hip_error() if rc == -3 else None
+        raise PgaError(f"{what}: {msg} (rc={rc}{', hip=' + str(hip) if hip is not None else ''})")
+
+
+def _ptr(t):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    return ct.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        raise PgaError("no GPU visible: libpga needs an MI355X (gfx950)")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def new_status(device=None) -> torch.Tensor:
+    return torch.zeros(STATUS_WORDS, dtype=torch.int32, device=device or _dev())
+
+
+def split_ld(N: int) -> int:
+    return int(load().pga_split_ld(N))
+
+
+def mut_thr(N: int) -> int:
+    return (2**32) // N if N > 1 else 2**32 - 1
+
+
+# ---------------------------------------------------------------- correlation and split
+def correlate(R: torch.Tensor, split: bool = False, status: torch.Tensor | None = None):
+    """Pearson correlation of the rows of R (N x T, float64, on the GPU). Returns C or (C, hi, lo)."""
+    L = load()
+    dev = _dev()
+    assert R.is_cuda and R.dtype == torch.float64 and R.dim() == 2 and R.stride(1) == 1
+    N, T = R.shape
+    C = torch.empty((N, N), dtype=torch.float64, device=dev)
+    hi = lo = None
+    if split:
+        ld = split_ld(N)
+        hi = torch.empty((ld, ld), dtype=torch.int16, device=dev)
+        lo = torch.empty((ld, ld), dtype=torch.int16, device=dev)
+    ws = _workspace(L.pga_correlate_ws_bytes(N), dev)
+    rc = L.pga_correlate(_ptr(R), N, T, R.stride(0), _ptr(C), _ptr(hi), _ptr(lo), _ptr(status),
+                         _ptr(ws), ws.numel(), _stream())
+    _check(rc, "pga_correlate")
+    return (C, hi, lo) if split else C
+
+
+def split(C: torch.Tensor):
+    """BF16 hi + lo split of C (N x N float64) into split_ld(N)^2 int16 bit-pattern arrays."""
+    L = load()
+    dev = _dev()
+    N = C.shape[0]
+    ld = split_ld(N)
+    hi = torch.empty((ld, ld), dtype=torch.int16, device=dev)
+    lo = torch.empty((ld, ld), dtype=torch.int16, device=dev)
+    _check(L.pga_split(_ptr(C), N, _ptr(hi), _ptr(lo), _stream()), "pga_split")
+    return hi, lo
+
+
+# ---------------------------------------------------------------- fitness
+def fitness(C: torch.Tensor, labels: torch.Tensor, form: str = "fp64", hi=None, lo=None,
+            want_ns: bool = False, want_cs: bool = False, status: torch.Tensor | None = None,
+            out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """L_c of every row of labels (P x N int32). Returns fitness (P,) [, n_s (P x N), c_s (P x N)]."""
+    L = load()
+    dev = _dev()
+    P, N = labels.shape
+    assert labels.dtype == torch.int32 and labels.is_contiguous()
+    f = out if out is not None else torch.empty(P, dtype=torch.float64, device=dev)
+    ns = torch.empty((P, N), dtype=torch.int32, device=dev) if want_ns else None
+    cs = torch.empty((P, N), dtype=torch.float64, device=dev) if want_cs else None
+    need = L.pga_fitness_ws_bytes(N, P, FORMS[form])
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    rc = L.pga_fitness(_ptr(C), _ptr(hi), _ptr(lo), N, _ptr(labels), P, FORMS[form], _ptr(f),
+                       _ptr(ns), _ptr(cs), _ptr(status), _ptr(ws), ws.numel(), _stream())
+    _check(rc, "pga_fitness")
+    res = [f]
+    if want_ns:
+        res.append(ns)
+    if want_cs:
+        res.append(cs)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def fitness_ws_bytes(N: int, P: int, form: str = "fp64") -> int:
+    return int(load().pga_fitness_ws_bytes(N, P, FORMS[form]))
+
+
+# ---------------------------------------------------------------- evolution
+@dataclass
+class Instance:
+    """One GA instance: device buffers plus parameters (Algorithm 1 state)."""
+    C: torch.Tensor
+    pop: torch.Tensor
+    pop_tmp: torch.Tensor
+    fitness: torch.Tensor
+    hi: torch.Tensor | None = None
+    lo: torch.Tensor | None = None
+    stats: torch.Tensor | None = None
+    elites: int = 2
+    p_cross_thr: int = P_CROSS_DEFAULT
+    p_mut_thr: int | None = None
+    seed: int = 0
+    instance_id: int = 0
+    gen0: int = 0
+
+    @property
+    def N(self) -> int:
+        return self.pop.shape[1]
+
+    @property
+    def P(self) -> int:
+        return self.pop.shape[0]
+
+    def to_c(self) -> InstanceC:
+        pm = self.p_mut_thr if self.p_mut_thr is not None else mut_thr(self.N)
+        prm = Params(self.elites, 2, self.p_cross_thr, pm, self.seed, self.instance_id, self.gen0)
+        return InstanceC(self.N, self.P, self.C.data_ptr(),
+                         self.hi.data_ptr() if self.hi is not None else None,
+                         self.lo.data_ptr() if self.lo is not None else None,
+                         self.pop.data_ptr(), self.pop_tmp.data_ptr(), self.fitness.data_ptr(),
+                         self.stats.data_ptr() if self.stats is not None else None, prm)
+
+
+def make_instance(C, P, hi=None, lo=None, pop=None, stats_rows=0, **kw) -> Instance:
+    dev = _dev()
+    N = C.shape[0]
+    if pop is None:
+        pop = torch.empty((P, N), dtype=torch.int32, device=dev)
+    st = torch.empty((stats_rows, 4), dtype=torch.float64, device=dev) if stats_rows else None
+    return Instance(C=C, hi=hi, lo=lo, pop=pop, pop_tmp=torch.empty_like(pop),
+                    fitness=torch.empty(P, dtype=torch.float64, device=dev), stats=st, **kw)
+
+
+class Context:
+    """Owns a pga_ctx (captured HIP graphs, descriptor staging) and a reusable workspace."""
+
+    def __init__(self):
+        L = load()
+        h = ct.c_void_p()
+        _check(L.pga_ctx_create(ct.byref(h)), "pga_ctx_create")
+        self.h = h
+        self.ws = None
+
+    def close(self):
+        if self.h:
+            load().pga_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def evolve(self, insts, generations: int, form: str = "fp64", init: bool = False,
+               eager: bool = False, status: torch.Tensor | None = None):
+        """Run `generations` generations on every instance (pga_evolve)."""
+        L = load()
+        dev = _dev()
+        arr = (InstanceC * len(insts))(*[i.to_c() for i in insts])
+        need = L.pga_evolve_ws_bytes(arr, len(insts), FORMS[form])
+        if need == 0:
+            raise PgaError("pga_evolve_ws_bytes: invalid instances")
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = _workspace(need, dev)
+        flags = (EVOLVE_INIT if init else 0) | (EVOLVE_EAGER if eager else 0)
+        rc = L.pga_evolve(self.h, arr, len(insts), generations, FORMS[form], flags,
+                          _ptr(self.ws), self.ws.numel(), _ptr(status), _stream())
+        _check(rc, "pga_evolve")
+
+
+# ---------------------------------------------------------------- result
+def best(fitness_t: torch.Tensor, labels: torch.Tensor):
+    """SYNC. (canonical labels as numpy int32, fitness, index) of the fittest labeling."""
+    L = load()
+    dev = _dev()
+    P, N = labels.shape
+    ws = _workspace(L.pga_best_ws_bytes(N), dev)
+    out = np.empty(N, dtype=np.int32)
+    f = ct.c_double()
+    idx = ct.c_int32()
+    rc = L.pga_best(_ptr(fitness_t), _ptr(labels), P, N, out.ctypes.data_as(ct.c_void_p),
+                    ct.byref(f), ct.byref(idx), _ptr(ws), ws.numel(), _stream())
+    _check(rc, "pga_best")
+    return out, f.value, idx.value
+
+
+# ---------------------------------------------------------------- timing
+def timing_enable(on: bool = True):
+    _check(load().pga_timing_enable(1 if on else 0), "pga_timing_enable")
+
+
+def timing_reset():
+    _check(load().pga_timing_reset(), "pga_timing_reset")
+
+
+def timing_read(kernel: str):
+    ms = ct.c_double()
+    n = ct.c_int64()
+    _check(load().pga_timing_read(KERNELS[kernel], ct.byref(ms), ct.byref(n)), "pga_timing_read")
+    return ms.value, n.value

@@ -1,0 +1,82 @@
+"""Shared inputs and comparison helpers for the GPU parity tests.
+
+Every input here comes from the seeded generators or from the CPU oracle;
+nothing is taken from the HIP path.
+"""
+import functools
+import sys
+
+import numpy as np
+
+import oracle as O
+from paper_1403_4099_amd import synth
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=None)
+def corr(N, T=256, seed=0, n_clusters=None):
+    """Oracle correlation of one-factor synthetic returns with a handful of planted clusters."""
+    rng = np.random.default_rng(1000 + seed)
+    k = n_clusters if n_clusters is not None else max(1, min(8, N // 6))
+    sizes = []
+    left = int(0.8 * N)
+    for _ in range(k):
+        if left < 2:
+            break
+        s = int(rng.integers(2, max(3, left // 2 + 1)))
+        s = min(s, left)
+        sizes.append(s)
+        left -= s
+    g = rng.uniform(0.2, 0.7, size=len(sizes))
+    R, planted = synth.one_factor_returns(sizes, g, N - sum(sizes), T, rng)
+    C = O.correlate(R)
+    C.setflags(write=False)
+    planted.setflags(write=False)
+    return C, planted
+
+
+def fitness_tol(mag, rel=1e-9):
+    """Parity bound |L_gpu - L_oracle| <= rel * M, M the sum of |log terms| (exact when M = 0)."""
+    return rel * mag
+
+
+def bf16_emulated(C, hi, lo):
+    """FP64 matrix that the BF16x2 form contracts: hi + lo off the diagonal, C on it."""
+    Ce = O.bf16_to_f64(hi) + O.bf16_to_f64(lo)
+    np.fill_diagonal(Ce, np.diag(C))
+    return Ce
+
+
+def cs_bound_fp32(Ce, pop, flush=256):
+    """Rigorous bound on |c_s(BF16x2 GPU) - c_s(oracle on Ce)| per (individual, label).
+
+    The GPU sums 2 * sum_{i<j} products in FP32 over chunks of at most `flush`
+    rows (FP32 recursive-sum bound (k-1) 2^-24 sum|terms| per chunk, plus one
+    FP32 rounding of the chunk result), then in FP64. Bound used:
+    2 * (flush + 1) * 2^-24 * sum_{i<j in s} |Ce_ij| + 1e-12 * n_s^2.
+    """
+    P, N = pop.shape
+    A = np.abs(np.triu(Ce, 1))
+    out = np.zeros((P, N))
+    for p in range(P):
+        lab = pop[p]
+        same = lab[:, None] == lab[None, :]
+        row_sum = np.sum(np.where(same, A, 0.0), axis=1)      # sum over j > i in the same cluster
+        s_abs = np.bincount(lab, weights=row_sum, minlength=N)
+        n = np.bincount(lab, minlength=N).astype(np.float64)
+        out[p] = 2.0 * (flush + 1) * 2.0**-24 * s_abs + 1e-12 * n * n
+    return out
+
+
+def l_bound_from_cs(ns, cs, dcs):
+    """First-order bound on |dL| from per-cluster bounds dcs: 1/2 sum_s |f'(c_s)| dcs_s (+ second-order slack)."""
+    n = ns.astype(np.float64)
+    m = n > 1
+    c = np.where(m, cs, 1.0)
+    n2 = n * n
+    fp = np.abs(-1.0 / c + (n - 1.0) / np.where(m, n2 - c, 1.0))
+    return 0.5 * np.sum(np.where(m, fp * dcs, 0.0), axis=1) * 1.01 + 1e-13
