@@ -1,0 +1,280 @@
+"""Benchmark: fitness evaluations/s and GA generations/s at N = 1024, BF16x2 vs FP64 form.
+
+One step = the whole path for one correlation window of the precision-form
+workload (N = 1024 stocks, T = 4096 returns, 32 planted clusters, P = 4096,
+G = 300 generations): pga_correlate (+ BF16 split) -> pga_evolve (initial
+population, 300 x [fitness, rank/statistics, breed], final fitness, one HIP
+graph launch) -> pga_best. Inputs are synthetic (one-factor returns) and
+resident in HBM before the timed region.
+
+Prints one JSON line. `value` is fitness evaluations per second of the chosen
+form over whole steps ((G + 1) * P per step); the FP64 form is timed the same
+way for the speed-up. `roofline` is for the dominant kernel (the pair-sum of
+the chosen form), its average duration measured with HIP events on the
+launching stream. `cpu_baseline` is the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_MFMA_BF16 = 2500.0          # TFLOP/s, dense bf16 MFMA (MI355X published)
+PEAK_HBM = 8000.0                # GB/s
+CU, SIMD, LANES, CLOCK = 256, 4, 16, 2.4e9
+PEAK_ALU = CU * SIMD * LANES * CLOCK / 1e12   # Tops/s: one 32/64-bit VALU lane-op per lane per clock
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", choices=["bf16x2", "fp64"], default="bf16x2")
+    ap.add_argument("--generations", type=int, default=300)
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=256,
+                    help="size of the plain device copy run once for counter calibration")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------- launch geometry (issued work)
+def mfma_issued_flops(N: int, P: int) -> float:
+    """MFMA flops the BF16x2 pair-sum kernel issues for one launch (all tiles, padding included)."""
+    cols, B = 64, 16
+    n_jb = -(-N // cols)
+    n_pb = -(-P // B)
+    mfmas = 0
+    for jb in range(n_jb):
+        for w in range(4):
+            jt0 = jb * cols + 16 * w
+            my_iend = min(jt0 + 16, N) if jt0 < N else 0
+            if my_iend > 0:
+                mfmas += -(-my_iend // 32) * 2 * B
+    return float(mfmas) * n_pb * 16 * 16 * 32 * 2
+
+
+def pair_visits(N: int, P: int) -> float:
+    """Unordered pairs i < j times individuals: the work the method must do per population evaluation."""
+    return float(N) * (N - 1) / 2 * P
+
+
+def source_sha(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def recorded_traffic(kernel_src: str, N: int, P: int):
+    """HBM bytes per launch from the committed counter summary, if it was taken on this kernel source."""
+    fn = os.path.join(ROOT, "profiles", "traffic_per_launch.txt")
+    if not os.path.exists(fn):
+        return None
+    sha = source_sha(kernel_src)
+    for line in open(fn):
+        f = line.split()
+        if len(f) >= 5 and not line.startswith("#") and f[0] == sha and int(f[1]) == N and int(f[2]) == P:
+            return float(f[3]) + float(f[4])
+    return None
+
+
+# ---------------------------------------------------------------- CPU baseline (oracle)
+def cpu_baseline(w, P, seed):
+    import numpy as np
+
+    import oracle as O
+    from paper_1403_4099_amd import synth
+
+    threads = 1   # the oracle is single-threaded C
+    t0 = time.perf_counter()
+    C = O.correlate(w.R)
+    t_corr = time.perf_counter() - t0
+    pop = O.init_pop(w.N, P, seed=seed)
+    t0 = time.perf_counter()
+    f = O.fitness(C, pop)
+    t_fit = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.breed(pop, f, E=2, seed=seed, gen=0)
+    t_breed = time.perf_counter() - t0
+    evals_per_s = P / (t_fit + t_breed)
+    return {
+        "value": evals_per_s, "unit": "fitness evals/s", "cores": threads, "kind": "oracle",
+        "sample": (f"one generation of the N={w.N}, P={P} workload on the CPU oracle: fitness of the "
+                   f"{P} initial labelings ({t_fit:.2f} s) + one breed step ({t_breed:.2f} s); "
+                   f"correlation of the window took {t_corr:.2f} s and is not in the rate"),
+        "gens_per_s": 1.0 / (t_fit + t_breed),
+        "correlate_s": t_corr,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
+              f"design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1403_4099_amd import pga, synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = synth.config3()
+    N, T, P, G = w.N, w.T, w.P, args.generations
+    R = torch.from_numpy(w.R).to(dev)
+    ld = pga.split_ld(N)
+    C = torch.empty((N, N), dtype=torch.float64, device=dev)
+    hi = torch.empty((ld, ld), dtype=torch.int16, device=dev)
+    lo = torch.empty((ld, ld), dtype=torch.int16, device=dev)
+    status = pga.new_status(dev)
+    cws = torch.empty(pga.load().pga_correlate_ws_bytes(N), dtype=torch.uint8, device=dev)
+    ctx = pga.Context()
+    insts = {}
+
+    def step(form):
+        L = pga.load()
+        stream = pga._stream()
+        split = form == "bf16x2"
+        rc = L.pga_correlate(pga._ptr(R), N, T, R.stride(0), pga._ptr(C), pga._ptr(hi) if split else None,
+                             pga._ptr(lo) if split else None, pga._ptr(status), pga._ptr(cws), cws.numel(),
+                             stream)
+        pga._check(rc, "pga_correlate")
+        I = insts.get(form)
+        if I is None:
+            I = pga.make_instance(C, P, hi=hi, lo=lo, stats_rows=G + 1, elites=w.elites, seed=w.seed)
+            insts[form] = I
+        ctx.evolve([I], G, form=form, init=True, status=status)
+        return pga.best(I.fitness, I.pop)
+
+    def timed(form, steps, warmup):
+        for _ in range(warmup):
+            step(form)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        res = None
+        for _ in range(steps):
+            res = step(form)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, e0.elapsed_time(e1) / 1e3, res
+
+    forms = [args.form] + ([] if args.no_compare else [f for f in ("bf16x2", "fp64") if f != args.form])
+    results = {}
+    for form in forms:
+        wall, ev, (lab, fbest, idx) = timed(form, args.steps, args.warmup)
+        results[form] = {"wall_s": wall, "event_s": ev, "best": fbest, "labels": lab,
+                         "clusters": int(len(set(lab.tolist())))}
+        print(f"[bench] {form}: {args.steps} steps in {wall:.3f} s (events {ev:.3f} s), best L_c {fbest:.6f}",
+              file=sys.stderr, flush=True)
+
+    # ---- kernel timing (HIP events around each launch, eager launches), same workload
+    pga.timing_enable(True)
+    kern = {}
+    for form in forms:
+        pga.timing_reset()
+        step(form)
+        torch.cuda.synchronize()
+        for k in ("pairsum_fp64", "pairsum_mfma", "finish", "rank", "breed", "correlate", "split", "init"):
+            ms, n = pga.timing_read(k)
+            if n:
+                kern.setdefault(form, {})[k] = {"avg_us": 1e3 * ms / n, "launches": n}
+    pga.timing_enable(False)
+
+    # ---- precision: BF16x2 vs FP64 fitness on the same populations
+    prec = {}
+    if "bf16x2" in results and "fp64" in results:
+        I = insts["bf16x2"]
+        f64 = pga.fitness(C, I.pop, "fp64")
+        fbf = pga.fitness(C, I.pop, "bf16x2", hi=hi, lo=lo)
+        rel_final = float(((fbf - f64).abs() / f64.abs().clamp_min(1e-300)).max())
+        pop0 = torch.from_numpy(synth.random_labelings(P, N, seed=123)).to(dev)
+        g64 = pga.fitness(C, pop0, "fp64")
+        gbf = pga.fitness(C, pop0, "bf16x2", hi=hi, lo=lo)
+        rel_init = float(((gbf - g64).abs() / g64.abs().clamp_min(1e-300)).max())
+        same_best = bool(np.array_equal(results["bf16x2"]["labels"], results["fp64"]["labels"]))
+        prec = {"max_rel_err_converged_pop": rel_final, "max_rel_err_random_pop": rel_init,
+                "identical_best_labeling": same_best,
+                "best_Lc": {f: results[f]["best"] for f in results}}
+
+    # ---- calibration copy for the HBM counters (plain device-to-device copy of known size)
+    nb = args.calib_copy_mib << 20
+    a = torch.empty(nb, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+    form = args.form
+    res = results[form]
+    evals = (G + 1) * P * args.steps
+    value = evals / res["wall_s"]
+    k = kern[form]["pairsum_mfma" if form == "bf16x2" else "pairsum_fp64"]
+    t_launch = k["avg_us"] * 1e-6
+    src = os.path.join(ROOT, "paper_1403_4099_amd", "csrc", "k_mfma.hip" if form == "bf16x2" else "k_fitness.hip")
+    if form == "bf16x2":
+        achieved = mfma_issued_flops(N, P) / t_launch / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_MFMA_BF16, "traffic": recorded_traffic(src, N, P),
+                "kernel": "k_pairsum_mfma", "avg_launch_us": k["avg_us"],
+                "work_per_launch": "issued v_mfma_f32_16x16x32_bf16 flops (hi and lo, 16x16 tile per 16 stocks)"}
+    else:
+        achieved = 2 * pair_visits(N, P) / t_launch / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU, "unit": "Tops/s",
+                "frac": achieved / PEAK_ALU, "traffic": recorded_traffic(src, N, P),
+                "kernel": "k_pairsum_fp64", "avg_launch_us": k["avg_us"],
+                "work_per_launch": "2 ops (label compare, FP64 add) per unordered pair per individual"}
+    other = {}
+    for f in results:
+        if f == form:
+            continue
+        kk = kern[f]["pairsum_mfma" if f == "bf16x2" else "pairsum_fp64"]
+        other[f] = {"fitness_evals_per_s": (G + 1) * P * args.steps / results[f]["wall_s"],
+                    "gens_per_s": G * args.steps / results[f]["wall_s"],
+                    "ms_per_step": 1e3 * results[f]["wall_s"] / args.steps,
+                    "pairsum_avg_us": kk["avg_us"],
+                    "pairsum_alu_frac": (2 * pair_visits(N, P) / (kk["avg_us"] * 1e-6) / 1e12) / PEAK_ALU
+                    if f == "fp64" else None}
+    line = {
+        "metric": "fitness evals/s + GA generations/s, BF16-split vs FP64 form at N=1024",
+        "value": value,
+        "unit": "fitness evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * res["wall_s"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x2+f64" if form == "bf16x2" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"precision-form N={N} T={T} P={P} G={G}, 32 planted geometric clusters",
+                   "form": form, "N": N, "T": T, "P": P, "generations": G, "parallelism": "single GPU"},
+        "gens_per_s": G * args.steps / res["wall_s"],
+        "pair_visits_per_s": pair_visits(N, P) * (G + 1) * args.steps / res["wall_s"],
+        "speedup_vs_fp64": (results["fp64"]["wall_s"] / res["wall_s"]) if (form == "bf16x2" and "fp64" in results) else None,
+        "other_forms": other,
+        "kernels_us": kern,
+        "precision": prec,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(w, P, w.seed)
+        line["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}
+    else:
+        line["cpu_baseline"] = None
+    ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -2,11 +2,12 @@
 // from n_s (Eq. 5) and c_s (Eq. 6).
 //
 // Split into two launches:
-//   pair-sum  w_pj = sum_{i<j} [s_pi = s_pj] C_ij  for every individual p and
-//             stock j (the O(N^2) part; FP64 VALU or BF16x2 MFMA form);
-//   finish    per individual: n_s by an LDS histogram, c_s = sum_{j in s}
-//             (C_jj + 2 w_pj) grouped exactly in 64-bit fixed point, then the
-//             FP64 log terms and a fixed-order block reduction.
+//   pair-sum  v_pj = C_jj + 2 sum_{i<j} [s_pi = s_pj] C_ij for every
+//             individual p and stock j (the O(N^2) part; FP64 VALU form here,
+//             BF16x2 MFMA form in k_mfma.hip);
+//   finish    per individual: n_s by an LDS histogram, c_s = sum_{j in s} v_pj
+//             grouped exactly in 64-bit fixed point, then the FP64 log terms
+//             and a fixed-order wave reduction.
 // Nothing here uses floating-point atomics, so every result is a pure
 // function of (C, labels): reruns and batching cannot change a bit.
 #include "pga_internal.hpp"
@@ -43,16 +44,24 @@ hipError_t launch_write_desc(const InstDesc &d, InstDesc *dst, int32_t *prefix, 
 
 // ---------------------------------------------------------------------------
 // FP64 pair-sum. One workgroup = 64 consecutive stocks j (one per lane) x 64
-// individuals (16 per wave). Each lane keeps its 16 labels s_pj and 16 FP64
-// accumulators in registers and walks the rows i < j of its column: the
-// column entry C_ij is loaded once (coalesced across the wave, L2-resident)
-// and reused by 16 individuals; the row labels s_pi are staged per 64-row
-// chunk in LDS, transposed so one 16-byte broadcast read serves 4
-// individuals. Per (pair, individual): compare, select 1.0/0.0, FMA.
-// Symmetry: only i < j is visited; the finish kernel doubles it and adds C_jj.
+// individuals (16 per wave); the four waves are independent (no workgroup
+// barrier). Each lane keeps its 16 labels s_pj and 16 FP64 accumulators in
+// registers and walks the rows i < j of its column in chunks of 64 rows:
+//   - C_ij is loaded once per (wave, row), coalesced across the wave, and
+//     reused by 16 individuals; loads run one group of 4 rows ahead;
+//   - the row labels s_pi of the wave's 16 individuals are staged per chunk in
+//     a wave-private LDS buffer (transposed, so one 16-byte broadcast read
+//     serves 4 individuals), double-buffered: the next chunk's labels are
+//     fetched into registers while the current chunk is processed.
+// Per (pair, individual): compare, select 1.0/0.0, FMA. Rows i >= j and rows
+// past N contribute C = 0, so every chunk runs all 64 rows without branches.
+__device__ __forceinline__ double fp64_c(const double *__restrict__ C, int N, int i, int j) {
+    return (i < j && j < N) ? C[(size_t)i * N + j] : 0.0;
+}
+
 __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity) {
     constexpr int B = kFp64B;
-    __shared__ int4 lab_s[kFp64Waves][64][B / 4];
+    __shared__ int4 lab_s[kFp64Waves][2][64][B / 4];
 
     const int tile = blockIdx.x;
     const int k = find_inst(t.tiles_fp64, t.n_inst, tile);
@@ -78,42 +87,64 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity) {
         acc[b] = 0.0;
     }
 
-    const int iend = min(jb * kFp64Cols + kFp64Cols, N);
-    for (int i0 = 0; i0 < iend; i0 += 64) {
-        {
-            const int ir = i0 + lane;
-            int v[B];
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const int p = pbase + b;
-                v[b] = (ir < N && p < P) ? labels[(size_t)p * N + ir] : (int)0x80000001;
-            }
-#pragma unroll
-            for (int q = 0; q < B / 4; ++q)
-                lab_s[wave][lane][q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-        }
-        __syncthreads();
-        const int rows = min(64, iend - i0);
-#pragma unroll 4
-        for (int r = 0; r < rows; ++r) {
-            const int i = i0 + r;
-            const double c = (jok && i < j) ? C[(size_t)i * N + j] : 0.0;
-#pragma unroll
-            for (int q = 0; q < B / 4; ++q) {
-                const int4 rl = lab_s[wave][r][q];
-                acc[4 * q + 0] = fma(rl.x == lj[4 * q + 0] ? 1.0 : 0.0, c, acc[4 * q + 0]);
-                acc[4 * q + 1] = fma(rl.y == lj[4 * q + 1] ? 1.0 : 0.0, c, acc[4 * q + 1]);
-                acc[4 * q + 2] = fma(rl.z == lj[4 * q + 2] ? 1.0 : 0.0, c, acc[4 * q + 2]);
-                acc[4 * q + 3] = fma(rl.w == lj[4 * q + 3] ? 1.0 : 0.0, c, acc[4 * q + 3]);
-            }
-        }
-        __syncthreads();
-    }
-    if (jok) {
+    auto fetch_labels = [&](int i0, int *v) {
+        const int ir = i0 + lane;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int p = pbase + b;
-            if (p < P) d.wsum[(size_t)p * N + j] = acc[b];
+            v[b] = (ir < N && p < P) ? labels[(size_t)p * N + ir] : (int)0x80000001;
+        }
+    };
+    auto store_labels = [&](int buf, const int *v) {
+#pragma unroll
+        for (int q = 0; q < B / 4; ++q)
+            lab_s[wave][buf][lane][q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    };
+
+    const int nchunks = jb + 1;                          // rows 0 .. 64 (jb + 1) - 1
+    int nxt[B];
+    fetch_labels(0, nxt);
+    store_labels(0, nxt);
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int i0 = ch * 64;
+        const int buf = ch & 1;
+        if (ch + 1 < nchunks) fetch_labels(i0 + 64, nxt);   // in flight during this chunk
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        double cq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cq[q] = fp64_c(C, N, i0 + q, j);
+        for (int r = 0; r < 64; r += 4) {
+            double cur[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cur[q] = cq[q];
+            if (r + 4 < 64) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cq[q] = fp64_c(C, N, i0 + r + 4 + q, j);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double c = cur[q];
+#pragma unroll
+                for (int u = 0; u < B / 4; ++u) {
+                    const int4 rl = lab_s[wave][buf][r + q][u];
+                    acc[4 * u + 0] = fma(rl.x == lj[4 * u + 0] ? 1.0 : 0.0, c, acc[4 * u + 0]);
+                    acc[4 * u + 1] = fma(rl.y == lj[4 * u + 1] ? 1.0 : 0.0, c, acc[4 * u + 1]);
+                    acc[4 * u + 2] = fma(rl.z == lj[4 * u + 2] ? 1.0 : 0.0, c, acc[4 * u + 2]);
+                    acc[4 * u + 3] = fma(rl.w == lj[4 * u + 3] ? 1.0 : 0.0, c, acc[4 * u + 3]);
+                }
+            }
+        }
+        if (ch + 1 < nchunks) store_labels(buf ^ 1, nxt);
+    }
+    if (jok) {
+        const double cjj = C[(size_t)j * N + j];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int p = pbase + b;
+            if (p < P) d.wsum[(size_t)p * N + j] = fma(2.0, acc[b], cjj);
         }
     }
 }
@@ -125,81 +156,81 @@ hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, hipStream_
 }
 
 // ---------------------------------------------------------------------------
-// Finish: one workgroup per individual.
-//   1. validity of labels, v_j = C_jj + 2 w_j, max |v_j|;
+// Finish: one wave per individual, up to four individuals per workgroup.
+//   1. validity of labels and of v_j; max |v_j| (order-free);
 //   2. n_s and sum_{j in s} v_j by integer LDS atomics, v_j scaled by 2^sc and
 //      rounded to int64 (sc chosen per individual so N max|v| 2^sc < 2^62:
 //      the integer sums are exact and order-free, error <= n_s 2^-(sc+1));
 //   3. per label s with n_s > 1: c_s, domain check, the two FP64 log terms
-//      of Eq. 8 in literal form; per-thread sums in ascending s, then a
-//      fixed tree over the workgroup.
-__device__ __forceinline__ double block_sum_fixed(double v, double *red) {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
+//      of Eq. 8 in literal form; per-lane sums in ascending s, then a
+//      butterfly over the wave (a fixed order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
 }
 
-__global__ __launch_bounds__(256) void k_finish(Tables t, int parity, int32_t *status) {
-    extern __shared__ unsigned char smem[];
-    __shared__ double red[256];
-    __shared__ int flags;
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    return v;
+}
 
-    const int g = blockIdx.x;
+// Per-wave LDS region of the finish kernel: csum (int64) then cnt (int32), each
+// padded to 16 bytes so every region and both arrays stay 16-byte aligned
+// (64-bit LDS atomics need naturally aligned addresses).
+__host__ __device__ __forceinline__ size_t finish_csum_bytes(int max_n) {
+    return ((size_t)max_n * sizeof(long long) + 15) / 16 * 16;
+}
+__host__ __device__ __forceinline__ size_t finish_wave_bytes(int max_n) {
+    return finish_csum_bytes(max_n) + ((size_t)max_n * sizeof(int) + 15) / 16 * 16;
+}
+
+__global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int max_n, int parity,
+                                                int32_t *status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = blockIdx.x * (int)(blockDim.x >> 6) + wave;
+    if (g >= total_inds) return;                     // whole wave leaves; no workgroup barrier below
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
     const int N = d.N;
     const int p = g - t.inds[k];
     const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
-    const double *__restrict__ w = d.wsum + (size_t)p * N;
-    const double *__restrict__ C = d.C;
-    long long *csum = (long long *)smem;
-    int *cnt = (int *)(smem + sizeof(long long) * (size_t)N);
+    const double *__restrict__ v = d.wsum + (size_t)p * N;
+    unsigned char *base = smem + (size_t)wave * finish_wave_bytes(max_n);
+    long long *csum = (long long *)base;
+    int *cnt = (int *)(base + finish_csum_bytes(max_n));
 
-    if (threadIdx.x == 0) flags = 0;
-    __syncthreads();
     int bad = 0;
     double mx = 0.0;
-    for (int j = threadIdx.x; j < N; j += 256) {
+    for (int j = lane; j < N; j += 64) {
         const int l = lab[j];
         if (l < 0 || l >= N) bad |= 1;
-        const double v = C[(size_t)j * N + j] + 2.0 * w[j];
-        if (!isfinite(v)) bad |= 2;
-        else mx = fmax(mx, fabs(v));
+        const double x = v[j];
+        if (!isfinite(x)) bad |= 2;
+        else mx = fmax(mx, fabs(x));
     }
-    if (bad) atomicOr(&flags, bad);
-    // max over the workgroup (order-free)
-    red[threadIdx.x] = mx;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-        __syncthreads();
-    }
-    mx = red[0];
-    const int fl = flags;
-    __syncthreads();
+    const bool any_label = __any(bad & 1);
+    const bool any_nonfinite = __any(bad & 2);
+    mx = wave_max(mx);
 
-    if (fl) {
-        if (threadIdx.x == 0) {
+    if (any_label || any_nonfinite) {
+        if (lane == 0) {
             d.fitness[p] = -INFINITY;
             if (status) {
-                if (fl & 1) atomicAdd(&status[PGA_ST_LABEL], 1);
+                if (any_label) atomicAdd(&status[PGA_ST_LABEL], 1);
                 atomicAdd(&status[PGA_ST_NONFINITE], 1);
             }
         }
         if (d.n_s_out)
-            for (int s = threadIdx.x; s < N; s += 256) d.n_s_out[(size_t)p * N + s] = 0;
+            for (int s = lane; s < N; s += 64) d.n_s_out[(size_t)p * N + s] = 0;
         if (d.c_s_out)
-            for (int s = threadIdx.x; s < N; s += 256) d.c_s_out[(size_t)p * N + s] = 0.0;
+            for (int s = lane; s < N; s += 64) d.c_s_out[(size_t)p * N + s] = 0.0;
         return;
     }
 
-    for (int s = threadIdx.x; s < N; s += 256) {
+    for (int s = lane; s < N; s += 64) {
         csum[s] = 0;
         cnt[s] = 0;
     }
@@ -209,19 +240,22 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int parity, int32_t *s
         frexp(mx * (double)N, &e);   // N max|v| < 2^e
         sc = 61 - e;
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < N; j += 256) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = lane; j < N; j += 64) {
         const int l = lab[j];
-        const double v = C[(size_t)j * N + j] + 2.0 * w[j];
-        const long long q = llrint(ldexp(v, sc));
+        const long long q = llrint(ldexp(v[j], sc));
         atomicAdd(&cnt[l], 1);
         atomicAdd((unsigned long long *)&csum[l], (unsigned long long)q);
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     double L = 0.0;
     int nbad = 0;
-    for (int s = threadIdx.x; s < N; s += 256) {
+    for (int s = lane; s < N; s += 64) {
         const int n = cnt[s];
         const double c = ldexp((double)csum[s], -sc);
         if (d.n_s_out) d.n_s_out[(size_t)p * N + s] = n;
@@ -236,9 +270,9 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int parity, int32_t *s
             }
         }
     }
-    const double Ltot = block_sum_fixed(L, red);
-    const double badtot = block_sum_fixed((double)nbad, red);
-    if (threadIdx.x == 0) {
+    const double Ltot = wave_sum(L);
+    const double badtot = wave_sum((double)nbad);
+    if (lane == 0) {
         if (badtot > 0.0) {
             d.fitness[p] = -INFINITY;
             if (status) {
@@ -254,8 +288,12 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int parity, int32_t *s
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status,
                          hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
-    const size_t lds = (size_t)max_n * (sizeof(long long) + sizeof(int));
-    hipLaunchKernelGGL(k_finish, dim3(total_inds), dim3(256), lds, s, t, parity, status);
+    // one wave per individual; as many waves per workgroup as fit in 64 KB of LDS (at most 4)
+    const size_t per_wave = finish_wave_bytes(max_n);
+    int wpg = (int)((64u << 10) / per_wave);
+    wpg = wpg < 1 ? 1 : wpg > 4 ? 4 : wpg;
+    hipLaunchKernelGGL(k_finish, dim3((total_inds + wpg - 1) / wpg), dim3(64 * wpg), per_wave * wpg, s, t,
+                       total_inds, max_n, parity, status);
     return hipGetLastError();
 }
 

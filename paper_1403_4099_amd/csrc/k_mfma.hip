@@ -1,19 +1,22 @@
-// BF16x2 pair-sum on MFMA: w_pj = sum_{i<j} [s_pi = s_pj] (hi_ji + lo_ji)
-// as the diagonal of a one-hot contraction (c_s = diag(Y^T C Y), Eq. 6).
+// BF16x2 pair-sum on MFMA: v_pj = C_jj + 2 sum_{i<j} [s_pi = s_pj] (hi_ji + lo_ji),
+// the sum over i being the diagonal of a one-hot contraction (c_s is the
+// diagonal of Y^T C Y, Eq. 6).
 //
 // One wave owns 16 stocks j = jt0 .. jt0+15 and walks the rows i < j in
 // chunks of 32 with v_mfma_f32_16x16x32_bf16:
 //   A[m][k] = C[jt0 + m][i0 + k]           (hi, then lo: two MFMAs)
 //   B[k][n] = [s_{i0+k} = s_{jt0+n}] [i0 + k < jt0 + n]   (0 or bf16 1.0)
-//   D[m][n] += sum_k A[m][k] B[k][n];  D[n][n] = partial w_{jt0+n}
+//   D[m][n] += sum_k A[m][k] B[k][n];  D[n][n] = partial sum for stock jt0+n
 // Lane l supplies row m = l%16 of A and column n = l%16 of B over the same
 // eight k = 8(l/16)..+7, so its A row and B column are both stock jt0 + l%16:
 // the lane needs only its own stock's label and the 8 row labels of its k
 // block. The one-hot column costs 3 packed 16-bit ALU ops per 2 rows (xor,
-// saturating 1 - x, multiply by the bf16 pattern of 1.0); A is loaded once
-// per (wave, chunk) and reused by the 16 individuals of the workgroup.
-// FP32 accumulation is flushed into FP64 every 256 rows (the LDS label
-// chunk), bounding its rounding to 256 terms.
+// saturating 1 - x, multiply by the bf16 pattern of 1.0); the i < j mask is
+// applied only in the chunk that reaches the diagonal. A is loaded once per
+// (wave, chunk), one chunk ahead, and reused by the 16 individuals of the
+// workgroup, whose row labels are staged in LDS once per 1024 rows.
+// FP32 accumulation is flushed into FP64 at every 256-row boundary, so no
+// FP32 partial sum spans more than 256 rows.
 #include "pga_internal.hpp"
 
 namespace pga {
@@ -66,70 +69,94 @@ __global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
         acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
         acc64[b] = 0.0;
     }
+    const int dreg = n & 3;                                   // lane holds D[n][n] in register n & 3 ...
+    const bool diag_lane = (n >> 2) == g;                     // ... when its 4-row group contains row n
 
-    const int wg_iend = min(jb * kMfmaCols + kMfmaCols, N);   // rows any wave of the group needs
-    const int my_iend = min(jt0 + 16, N);                     // rows this wave needs (i < j <= jt0+15)
-    const bool diag_lane = (n >> 2) == g;                     // lane holds D[n][n] in register n & 3
-    const int dreg = n & 3;
-
-    for (int c0 = 0; c0 < wg_iend; c0 += RC) {
-        // stage labels of rows c0 .. c0+RC-1 for the B individuals (16-bit)
-        for (int e = threadIdx.x; e < B * RC; e += 256) {
-            const int b = e / RC, r = e % RC;
-            const int i = c0 + r, p = pbase + b;
-            lab_s[b][r] = (i < N && p < P) ? (uint16_t)labels[(size_t)p * N + i] : (uint16_t)0xFFFFu;
-        }
-        __syncthreads();
-        const int cend = min(c0 + RC, my_iend);
-        for (int i0 = c0; i0 < cend; i0 += 32) {
-            const int ik = i0 + 8 * g;                        // first of this lane's 8 rows
-            uint4 ah = make_uint4(0, 0, 0, 0), al = make_uint4(0, 0, 0, 0);
-            if (j < ld) {
-                ah = *(const uint4 *)(hi + (size_t)j * ld + ik);
-                al = *(const uint4 *)(lo + (size_t)j * ld + ik);
-            }
-            const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah);
-            const bf16x8 Al = __builtin_bit_cast(bf16x8, al);
-            // mask for rows i >= j (only the chunk that reaches the diagonal)
-            uint32_t m0 = 0xFFFFFFFFu, m1 = 0xFFFFFFFFu, m2 = 0xFFFFFFFFu, m3 = 0xFFFFFFFFu;
-            if (i0 + 32 > jt0) {
-                auto pm = [&](int r) -> uint32_t {
-                    const uint32_t lo16 = (ik + r < j) ? 0xFFFFu : 0u;
-                    const uint32_t hi16 = (ik + r + 1 < j) ? 0xFFFF0000u : 0u;
-                    return lo16 | hi16;
-                };
-                m0 = pm(0);
-                m1 = pm(2);
-                m2 = pm(4);
-                m3 = pm(6);
-            }
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const uint4 lv = *(const uint4 *)&lab_s[b][ik - c0];
-                uint4 bv;
-                bv.x = onehot2(lv.x, lj2[b]) & m0;
-                bv.y = onehot2(lv.y, lj2[b]) & m1;
-                bv.z = onehot2(lv.z, lj2[b]) & m2;
-                bv.w = onehot2(lv.w, lj2[b]) & m3;
-                const bf16x8 Bv = __builtin_bit_cast(bf16x8, bv);
-                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bv, acc[b], 0, 0, 0);
-                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bv, acc[b], 0, 0, 0);
-            }
-        }
-        // flush the FP32 diagonal into FP64
+    auto flush = [&]() {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const float v = dreg == 0 ? acc[b][0] : dreg == 1 ? acc[b][1] : dreg == 2 ? acc[b][2] : acc[b][3];
             acc64[b] += (double)v;
             acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
+    };
+    auto load_a = [&](int i0, uint4 &ah, uint4 &al) {
+        ah = make_uint4(0, 0, 0, 0);
+        al = make_uint4(0, 0, 0, 0);
+        if (j < ld) {
+            ah = *(const uint4 *)(hi + (size_t)j * ld + i0 + 8 * g);
+            al = *(const uint4 *)(lo + (size_t)j * ld + i0 + 8 * g);
+        }
+    };
+    auto chunk = [&](int i0, int c0, uint4 ah, uint4 al, bool masked) {
+        const int ik = i0 + 8 * g;                            // first of this lane's 8 rows
+        uint32_t m[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+        if (masked) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                m[q] = ((ik + 2 * q < j) ? 0xFFFFu : 0u) | ((ik + 2 * q + 1 < j) ? 0xFFFF0000u : 0u);
+        }
+        const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah);
+        const bf16x8 Al = __builtin_bit_cast(bf16x8, al);
+#pragma unroll
+        for (int b = 0; b < B; b += 2) {
+            const uint4 l0 = *(const uint4 *)&lab_s[b][ik - c0];
+            const uint4 l1 = *(const uint4 *)&lab_s[b + 1][ik - c0];
+            uint4 v0, v1;
+            v0.x = onehot2(l0.x, lj2[b]);
+            v0.y = onehot2(l0.y, lj2[b]);
+            v0.z = onehot2(l0.z, lj2[b]);
+            v0.w = onehot2(l0.w, lj2[b]);
+            v1.x = onehot2(l1.x, lj2[b + 1]);
+            v1.y = onehot2(l1.y, lj2[b + 1]);
+            v1.z = onehot2(l1.z, lj2[b + 1]);
+            v1.w = onehot2(l1.w, lj2[b + 1]);
+            if (masked) {
+                v0.x &= m[0]; v0.y &= m[1]; v0.z &= m[2]; v0.w &= m[3];
+                v1.x &= m[0]; v1.y &= m[1]; v1.z &= m[2]; v1.w &= m[3];
+            }
+            const bf16x8 B0 = __builtin_bit_cast(bf16x8, v0);
+            const bf16x8 B1 = __builtin_bit_cast(bf16x8, v1);
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B0, acc[b], 0, 0, 0);
+            acc[b + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B1, acc[b + 1], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B0, acc[b], 0, 0, 0);
+            acc[b + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B1, acc[b + 1], 0, 0, 0);
+        }
+        if (((i0 + 32) % kMfmaFlushRows) == 0) flush();
+    };
+
+    const int wg_iend = min(jb * kMfmaCols + kMfmaCols, N);   // rows any wave of the group needs
+    const int my_iend = jt0 < N ? min(jt0 + 16, N) : 0;       // rows this wave needs (i < j <= jt0+15)
+    const int i_diag = (jt0 / 32) * 32;                       // first chunk that may hold i >= j
+
+    for (int c0 = 0; c0 < wg_iend; c0 += RC) {
+        const int rows = min(RC, wg_iend - c0);
+        for (int e = threadIdx.x; e < B * RC; e += 256) {
+            const int b = e / RC, r = e % RC;
+            const int i = c0 + r, p = pbase + b;
+            lab_s[b][r] = (r < rows && p < P) ? (uint16_t)labels[(size_t)p * N + i] : (uint16_t)0xFFFFu;
+        }
+        __syncthreads();
+        const int cend = min(c0 + RC, my_iend);
+        if (c0 < cend) {
+            uint4 ah, al, nh, nl;
+            load_a(c0, ah, al);
+            for (int i0 = c0; i0 < cend; i0 += 32) {
+                if (i0 + 32 < cend) load_a(i0 + 32, nh, nl);
+                chunk(i0, c0, ah, al, i0 >= i_diag);
+                ah = nh;
+                al = nl;
+            }
+        }
         __syncthreads();
     }
+    flush();
     if (diag_lane && j < N) {
+        const double cjj = d.C[(size_t)j * N + j];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int p = pbase + b;
-            if (p < P) d.wsum[(size_t)p * N + j] = acc64[b];
+            if (p < P) d.wsum[(size_t)p * N + j] = fma(2.0, acc64[b], cjj);
         }
     }
 }

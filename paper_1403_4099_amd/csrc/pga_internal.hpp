@@ -19,7 +19,7 @@ struct InstDesc {
     int32_t *pop[2];            // ping-pong population buffers
     double *fitness;            // P
     double *stats;              // (G + 1) x 4 or null
-    double *wsum;               // P x N pair-sum scratch
+    double *wsum;               // P x N: v_pj = C_jj + 2 sum_{i<j} [s_pi = s_pj] C_ij
     int32_t *elite;             // PGA_E_MAX
     int32_t *n_s_out;           // P x N or null
     double *c_s_out;            // P x N or null
@@ -50,7 +50,8 @@ constexpr int kFp64Inds = kFp64Waves * kFp64B;     // individuals per workgroup
 constexpr int kMfmaWaves = 4;                      // waves per workgroup, 16 columns each
 constexpr int kMfmaCols = 16 * kMfmaWaves;         // columns per workgroup
 constexpr int kMfmaB = 16;                         // individuals per workgroup
-constexpr int kMfmaRowChunk = 256;                 // rows staged in LDS at a time (and FP32 flush period)
+constexpr int kMfmaRowChunk = 1024;                // rows of labels staged in LDS at a time
+constexpr int kMfmaFlushRows = 256;                // FP32 accumulators are flushed to FP64 every 256 rows
 
 inline int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 inline int32_t fp64_tiles(int32_t N, int32_t P) { return ceil_div(N, kFp64Cols) * ceil_div(P, kFp64Inds); }
