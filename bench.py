@@ -42,7 +42,33 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=256,
                     help="size of the plain device copy run once for counter calibration")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the Poisson request stream of the serving run (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     return ap.parse_args()
+
+
+def serving_run(seconds, rate, form):
+    """Continuous-batching run over a Poisson stream of correlation windows (N in {64, 256, 1024}
+    at 6:3:1, T = 390, P = 1024 resident and warm-started per universe, 100 generations per
+    request in chunks of 10, 8 GiB admission budget). Windows are staged in HBM beforehand."""
+    import torch
+
+    from paper_1403_4099_amd import synth
+    from paper_1403_4099_amd.serve import GpuEngine, Request, Scheduler
+
+    _, stream = synth.serving_stream(duration=seconds, rate=rate, seed=4)
+    reqs = [Request(i, u, t, torch.from_numpy(R).cuda(), R.shape[0], R.shape[1])
+            for i, (t, u, R) in enumerate(stream)]
+    torch.cuda.synchronize()
+    sch = Scheduler(GpuEngine(P=1024, form=form), P=1024, generations=100, chunk=10,
+                    hbm_budget=8 << 30, form=form)
+    sch.run(reqs)
+    out = sch.summary()
+    out.update({"offered_rate_per_s": rate, "stream_seconds": seconds, "form": form,
+                "workload": "Poisson windows, N in {64,256,1024} 6:3:1 over 16 universes, T=390, "
+                            "P=1024, 100 generations, 5% drift per window"})
+    return out
 
 
 # ---------------------------------------------------------------- launch geometry (issued work)
@@ -267,6 +293,9 @@ def main():
         "precision": prec,
         "roofline": roof,
     }
+    if args.serve_seconds > 0:
+        line["serving"] = serving_run(args.serve_seconds, args.serve_rate, form)
+        print(f"[bench] serving: {line['serving']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, P, w.seed)
         line["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}

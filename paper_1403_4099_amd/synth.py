@@ -175,3 +175,75 @@ def random_symmetric_unit_diag(N: int, seed: int, scale: float = 0.3) -> np.ndar
     C = C + C.T
     np.fill_diagonal(C, 1.0)
     return C
+
+
+# ---------------------------------------------------------------- serving stream
+@dataclass
+class Universe:
+    uid: int
+    N: int
+    planted: np.ndarray      # current planted cluster id per stock
+    g: np.ndarray            # loading per planted cluster
+
+
+def serving_universes(seed: int = 4, counts=((64, 8), (256, 5), (1024, 3))):
+    """Resident stock universes: 8 of 64 stocks, 5 of 256, 3 of 1024 (16 in all).
+
+    Each has N // 16 planted clusters (at least 2) over 90% of its stocks, sizes by
+    Dirichlet(1) (minimum 2), loadings g ~ U[0.2, 0.7]; the rest are noise stocks.
+    """
+    rng = np.random.default_rng(seed)
+    us = []
+    uid = 0
+    for N, cnt in counts:
+        for _ in range(cnt):
+            k = max(2, N // 16)
+            covered = int(0.9 * N)
+            sizes = _dirichlet_sizes(rng, k, covered)
+            planted = np.concatenate([np.repeat(np.arange(k), sizes), k + np.arange(N - covered)])
+            planted = rng.permutation(planted).astype(np.int32)
+            us.append(Universe(uid, N, planted, rng.uniform(0.2, 0.7, size=k)))
+            uid += 1
+    return us
+
+
+def serving_stream(duration: float, rate: float = 200.0, T: int = 390, seed: int = 4,
+                   ratio=(6, 3, 1), drift: float = 0.05):
+    """Poisson arrivals over `duration` seconds; N-class drawn 6:3:1 over {64, 256, 1024},
+    universe uniform within its class; before each window 5% of the universe's stocks move
+    to another existing planted cluster; each window holds T fresh one-factor returns.
+
+    Returns (universes, requests) with requests = [(arrival_s, uid, R (N x T float64))].
+    """
+    rng = np.random.default_rng(seed + 1)
+    us = serving_universes(seed)
+    by_n = {}
+    for u in us:
+        by_n.setdefault(u.N, []).append(u)
+    classes = sorted(by_n)
+    p = np.array(ratio, dtype=np.float64)
+    p /= p.sum()
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        N = classes[int(rng.choice(len(classes), p=p))]
+        u = by_n[N][int(rng.integers(len(by_n[N])))]
+        k = len(u.g)
+        moved = rng.random(N) < drift
+        clustered = u.planted < k
+        idx = np.nonzero(moved & clustered)[0]
+        if idx.size:
+            u.planted[idx] = rng.integers(0, k, size=idx.size)
+        R = np.empty((N, T))
+        f = rng.standard_normal((k, T))
+        e = rng.standard_normal((N, T))
+        lab = u.planted
+        inc = lab < k
+        gl = np.where(inc, u.g[np.minimum(lab, k - 1)], 0.0)
+        R[:] = np.sqrt(gl)[:, None] * np.where(inc[:, None], f[np.minimum(lab, k - 1)], 0.0) \
+            + np.sqrt(1.0 - gl)[:, None] * e
+        out.append((t, u.uid, R))
+    return us, out

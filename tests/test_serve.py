@@ -1,0 +1,84 @@
+"""CPU tests of the continuous-batching scheduler's host logic with a fake engine
+(admission by HBM budget, one request per universe in flight, FIFO, retirement)."""
+import numpy as np
+
+from paper_1403_4099_amd.serve import Request, Scheduler, footprint_bytes
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeEngine:
+    def __init__(self, clock, cost_per_gen=1e-4):
+        self.clock = clock
+        self.cost = cost_per_gen
+        self.pops = {}
+        self.log = []
+
+    def resident(self, u):
+        return self.pops.get(u)
+
+    def start(self, req, gen0, warm):
+        self.log.append(("start", req.rid, req.universe, gen0, warm is not None))
+        return {"req": req, "gen": gen0}, None, None, None
+
+    def advance(self, insts, g):
+        self.log.append(("advance", tuple(i["req"].rid for i in insts), g))
+        self.clock.t += self.cost * g * len(insts)
+        for i in insts:
+            i["gen"] += g
+
+    def finish(self, inst):
+        return np.zeros(inst["req"].N, dtype=np.int32), float(inst["gen"])
+
+    def keep(self, u, inst):
+        self.pops[u] = inst["gen"]
+
+
+def _reqs(spec):
+    return [Request(i, u, t, None, N, 390) for i, (t, u, N) in enumerate(spec)]
+
+
+def test_all_requests_complete_and_universes_do_not_overlap():
+    clk = FakeClock()
+    eng = FakeEngine(clk)
+    s = Scheduler(eng, P=64, generations=20, chunk=5, hbm_budget=1 << 30, clock=clk)
+    reqs = _reqs([(0.0, 0, 64), (0.0, 0, 64), (0.0, 1, 256), (0.001, 2, 64), (0.001, 0, 64)])
+    res = s.run(reqs)
+    assert sorted(r.rid for r in res) == [0, 1, 2, 3, 4]
+    # universe 0's three requests ran one after another, warm-starting from the previous one
+    starts = [e for e in eng.log if e[0] == "start" and e[2] == 0]
+    assert [e[3] for e in starts] == [0, 20, 40]
+    assert [e[4] for e in starts] == [False, True, True]
+    # never two requests of one universe in the same chunk
+    rid_u = {r.rid: r.universe for r in reqs}
+    for e in eng.log:
+        if e[0] == "advance":
+            us = [rid_u[r] for r in e[1]]
+            assert len(us) == len(set(us))
+    # continuous batching: some chunk carried more than one request
+    assert max(len(e[1]) for e in eng.log if e[0] == "advance") >= 2
+    for r in res:
+        assert r.latency >= 0 and r.done >= r.admitted >= r.arrival
+
+
+def test_admission_respects_the_hbm_budget_and_rejects_oversize():
+    clk = FakeClock()
+    eng = FakeEngine(clk)
+    one = footprint_bytes(256, 64, 256, "fp64")
+    s = Scheduler(eng, P=64, generations=10, chunk=5, hbm_budget=int(1.5 * one), clock=clk)
+    reqs = _reqs([(0.0, 0, 256), (0.0, 1, 256), (0.0, 2, 4096)])
+    res = s.run(reqs)
+    assert sorted(r.rid for r in res) == [0, 1]
+    assert [r.rid for r in s.rejected] == [2]
+    # the budget held only one 256-stock request at a time
+    for e in eng.log:
+        if e[0] == "advance":
+            assert len(e[1]) == 1
+    summ = s.summary()
+    assert summ["requests"] == 2 and summ["rejected"] == 1 and summ["max_in_flight"] == 1
