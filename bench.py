@@ -45,7 +45,43 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson request stream of the serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--batched-instances", type=int, default=256,
+                    help="instances of the ragged batched run (0 = skip)")
     return ap.parse_args()
+
+
+def batched_run(n_inst, form, generations=200, reps=2):
+    """Ragged batched form: n_inst independent GA instances (N ~ U{32..512}, T = 1024,
+    P = 512 each) advanced together by ONE pga_evolve call (one graph launch) per rep."""
+    import torch
+
+    from paper_1403_4099_amd import pga, synth
+
+    insts = []
+    for i in range(n_inst):
+        w = synth.config4_instance(i)
+        R = torch.from_numpy(w.R).cuda()
+        out = pga.correlate(R, split=(form == "bf16x2"))
+        C, hi, lo = out if form == "bf16x2" else (out, None, None)
+        insts.append(pga.make_instance(C, w.P, hi=hi, lo=lo, stats_rows=generations + 1, elites=w.elites,
+                                       seed=w.seed, instance_id=i))
+    ctx = pga.Context()
+    ctx.evolve(insts, generations, form=form, init=True)          # warm-up: captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.evolve(insts, generations, form=form, init=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    Ps = sum(I.P for I in insts)
+    pairs = sum(I.P * I.N * (I.N - 1) / 2 for I in insts)
+    ctx.close()
+    return {"instances": n_inst, "form": form, "generations": generations,
+            "seconds_per_run": dt, "gens_per_s": generations / dt,
+            "fitness_evals_per_s": Ps * (generations + 1) / dt,
+            "pair_visits_per_s": pairs * (generations + 1) / dt,
+            "sum_N": int(sum(I.N for I in insts)),
+            "workload": "256 instances, N ~ U{32..512}, T=1024, 2-12 planted clusters, P=512, G=200"}
 
 
 def serving_run(seconds, rate, form):
@@ -74,7 +110,7 @@ def serving_run(seconds, rate, form):
 # ---------------------------------------------------------------- launch geometry (issued work)
 def mfma_issued_flops(N: int, P: int) -> float:
     """MFMA flops the BF16x2 pair-sum kernel issues for one launch (all tiles, padding included)."""
-    cols, B = 64, 16
+    cols, B = 64, 8
     n_jb = -(-N // cols)
     n_pb = -(-P // B)
     mfmas = 0
@@ -293,6 +329,9 @@ def main():
         "precision": prec,
         "roofline": roof,
     }
+    if args.batched_instances > 0:
+        line["batched"] = batched_run(args.batched_instances, form)
+        print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
     if args.serve_seconds > 0:
         line["serving"] = serving_run(args.serve_seconds, args.serve_rate, form)
         print(f"[bench] serving: {line['serving']}", file=sys.stderr, flush=True)

@@ -56,7 +56,7 @@ hipError_t launch_write_desc(const InstDesc &d, InstDesc *dst, int32_t *prefix, 
 // Per (pair, individual): compare, select 1.0/0.0, FMA. Rows i >= j and rows
 // past N contribute C = 0, so every chunk runs all 64 rows without branches.
 __device__ __forceinline__ double fp64_c(const double *__restrict__ C, int N, int i, int j) {
-    return (i < j && j < N) ? C[(size_t)i * N + j] : 0.0;
+    return (i < j && j < N) ? gld(C + (size_t)i * N + j) : 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity) {
@@ -69,30 +69,21 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity) {
     const int N = d.N, P = d.P;
     const int local = tile - t.tiles_fp64[k];
     const int n_jb = (N + kFp64Cols - 1) / kFp64Cols;
-    const int jb = n_jb - 1 - (local % n_jb);          // heaviest column blocks first
-    const int pb = local / n_jb;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = jb * kFp64Cols + lane;
-    const bool jok = j < N;
+    const int n_pairs = (n_jb + 1) / 2;
+    const int jp = local % n_pairs;
+    const int pb = local / n_pairs;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, kept scalar
+    const int lane = threadIdx.x & 63;
     const int pbase = pb * kFp64Inds + wave * B;
     const int32_t *__restrict__ labels = d.pop[parity];
     const double *__restrict__ C = d.C;
-
-    int lj[B];
-    double acc[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const int p = pbase + b;
-        lj[b] = (jok && p < P) ? labels[(size_t)p * N + j] : (int)0x80000000;
-        acc[b] = 0.0;
-    }
 
     auto fetch_labels = [&](int i0, int *v) {
         const int ir = i0 + lane;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int p = pbase + b;
-            v[b] = (ir < N && p < P) ? labels[(size_t)p * N + ir] : (int)0x80000001;
+            v[b] = (ir < N && p < P) ? gld(labels + (size_t)p * N + ir) : (int)0x80000001;
         }
     };
     auto store_labels = [&](int buf, const int *v) {
@@ -101,50 +92,71 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity) {
             lab_s[wave][buf][lane][q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
     };
 
-    const int nchunks = jb + 1;                          // rows 0 .. 64 (jb + 1) - 1
-    int nxt[B];
-    fetch_labels(0, nxt);
-    store_labels(0, nxt);
-    for (int ch = 0; ch < nchunks; ++ch) {
-        const int i0 = ch * 64;
-        const int buf = ch & 1;
-        if (ch + 1 < nchunks) fetch_labels(i0 + 64, nxt);   // in flight during this chunk
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // The triangle is folded: column blocks n_jb-1-jp (jp + 1 ... n_jb chunks of rows) and
+    // jp are done by the same workgroup, so every workgroup has n_jb + 1 chunks of work.
+    for (int half = 0; half < 2; ++half) {
+        const int jb = half == 0 ? n_jb - 1 - jp : jp;
+        if (half == 1 && jb == n_jb - 1 - jp) break;       // middle block of an odd count: once
+        const int j = jb * kFp64Cols + lane;
+        const bool jok = j < N;
 
-        double cq[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) cq[q] = fp64_c(C, N, i0 + q, j);
-        for (int r = 0; r < 64; r += 4) {
-            double cur[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) cur[q] = cq[q];
-            if (r + 4 < 64) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) cq[q] = fp64_c(C, N, i0 + r + 4 + q, j);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double c = cur[q];
-#pragma unroll
-                for (int u = 0; u < B / 4; ++u) {
-                    const int4 rl = lab_s[wave][buf][r + q][u];
-                    acc[4 * u + 0] = fma(rl.x == lj[4 * u + 0] ? 1.0 : 0.0, c, acc[4 * u + 0]);
-                    acc[4 * u + 1] = fma(rl.y == lj[4 * u + 1] ? 1.0 : 0.0, c, acc[4 * u + 1]);
-                    acc[4 * u + 2] = fma(rl.z == lj[4 * u + 2] ? 1.0 : 0.0, c, acc[4 * u + 2]);
-                    acc[4 * u + 3] = fma(rl.w == lj[4 * u + 3] ? 1.0 : 0.0, c, acc[4 * u + 3]);
-                }
-            }
-        }
-        if (ch + 1 < nchunks) store_labels(buf ^ 1, nxt);
-    }
-    if (jok) {
-        const double cjj = C[(size_t)j * N + j];
+        int lj[B];
+        double acc[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int p = pbase + b;
-            if (p < P) d.wsum[(size_t)p * N + j] = fma(2.0, acc[b], cjj);
+            lj[b] = (jok && p < P) ? gld(labels + (size_t)p * N + j) : (int)0x80000000;
+            acc[b] = 0.0;
+        }
+
+        const int nchunks = jb + 1;                      // rows 0 .. 64 (jb + 1) - 1
+        int nxt[B];
+        fetch_labels(0, nxt);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();                 // previous block's reads of buffer 0 are done
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        store_labels(0, nxt);
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int i0 = ch * 64;
+            const int buf = ch & 1;
+            if (ch + 1 < nchunks) fetch_labels(i0 + 64, nxt);   // in flight during this chunk
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+            double cq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cq[q] = fp64_c(C, N, i0 + q, j);
+            for (int r = 0; r < 64; r += 4) {
+                double cur[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cur[q] = cq[q];
+                if (r + 4 < 64) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cq[q] = fp64_c(C, N, i0 + r + 4 + q, j);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double c = cur[q];
+#pragma unroll
+                    for (int u = 0; u < B / 4; ++u) {
+                        const int4 rl = lab_s[wave][buf][r + q][u];
+                        acc[4 * u + 0] = fma(rl.x == lj[4 * u + 0] ? 1.0 : 0.0, c, acc[4 * u + 0]);
+                        acc[4 * u + 1] = fma(rl.y == lj[4 * u + 1] ? 1.0 : 0.0, c, acc[4 * u + 1]);
+                        acc[4 * u + 2] = fma(rl.z == lj[4 * u + 2] ? 1.0 : 0.0, c, acc[4 * u + 2]);
+                        acc[4 * u + 3] = fma(rl.w == lj[4 * u + 3] ? 1.0 : 0.0, c, acc[4 * u + 3]);
+                    }
+                }
+            }
+            if (ch + 1 < nchunks) store_labels(buf ^ 1, nxt);
+        }
+        if (jok) {
+            const double cjj = gld(C + (size_t)j * N + j);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int p = pbase + b;
+                if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc[b], cjj));
+            }
         }
     }
 }
@@ -205,9 +217,9 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
     int bad = 0;
     double mx = 0.0;
     for (int j = lane; j < N; j += 64) {
-        const int l = lab[j];
+        const int l = gld(lab + j);
         if (l < 0 || l >= N) bad |= 1;
-        const double x = v[j];
+        const double x = gld(v + j);
         if (!isfinite(x)) bad |= 2;
         else mx = fmax(mx, fabs(x));
     }
@@ -244,8 +256,8 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int j = lane; j < N; j += 64) {
-        const int l = lab[j];
-        const long long q = llrint(ldexp(v[j], sc));
+        const int l = gld(lab + j);
+        const long long q = llrint(ldexp(gld(v + j), sc));
         atomicAdd(&cnt[l], 1);
         atomicAdd((unsigned long long *)&csum[l], (unsigned long long)q);
     }
@@ -258,8 +270,8 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
     for (int s = lane; s < N; s += 64) {
         const int n = cnt[s];
         const double c = ldexp((double)csum[s], -sc);
-        if (d.n_s_out) d.n_s_out[(size_t)p * N + s] = n;
-        if (d.c_s_out) d.c_s_out[(size_t)p * N + s] = c;
+        if (d.n_s_out) gst(d.n_s_out + (size_t)p * N + s, n);
+        if (d.c_s_out) gst(d.c_s_out + (size_t)p * N + s, c);
         if (n > 1) {
             const double nd = (double)n;
             const double n2 = nd * nd;

@@ -19,6 +19,8 @@
 // FP32 partial sum spans more than 256 rows.
 #include "pga_internal.hpp"
 
+#include <type_traits>
+
 namespace pga {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -33,20 +35,14 @@ __device__ __forceinline__ uint32_t onehot2(uint32_t labs, uint32_t lj2) {
     return __builtin_bit_cast(uint32_t, t * bf1);
 }
 
-__global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
+// One column block jb (64 stocks, 16 per wave) for the B individuals of batch pb.
+__device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, int parity,
+                                           uint16_t (*lab_s)[kMfmaRowChunk]) {
     constexpr int B = kMfmaB;
     constexpr int RC = kMfmaRowChunk;
-    __shared__ __align__(16) uint16_t lab_s[B][RC];
-
-    const int tile = blockIdx.x;
-    const int k = find_inst(t.tiles_mfma, t.n_inst, tile);
-    const InstDesc &d = t.desc[k];
     const int N = d.N, P = d.P, ld = d.ld_h;
-    const int local = tile - t.tiles_mfma[k];
-    const int n_jb = (N + kMfmaCols - 1) / kMfmaCols;
-    const int jb = n_jb - 1 - (local % n_jb);            // heaviest column blocks first
-    const int pb = local / n_jb;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, kept scalar
+    const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int jt0 = jb * kMfmaCols + 16 * wave;
     const int j = jt0 + n;
@@ -59,7 +55,7 @@ __global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int p = pbase + b;
-        const uint32_t l = (j < N && p < P) ? (uint32_t)labels[(size_t)p * N + j] & 0xFFFFu : 0xFFFEu;
+        const uint32_t l = (j < N && p < P) ? (uint32_t)gld(labels + (size_t)p * N + j) & 0xFFFFu : 0xFFFEu;
         lj2[b] = l | (l << 16);
     }
     floatx4 acc[B];
@@ -84,14 +80,15 @@ __global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
         ah = make_uint4(0, 0, 0, 0);
         al = make_uint4(0, 0, 0, 0);
         if (j < ld) {
-            ah = *(const uint4 *)(hi + (size_t)j * ld + i0 + 8 * g);
-            al = *(const uint4 *)(lo + (size_t)j * ld + i0 + 8 * g);
+            ah = gld_u4(hi + (size_t)j * ld + i0 + 8 * g);
+            al = gld_u4(lo + (size_t)j * ld + i0 + 8 * g);
         }
     };
-    auto chunk = [&](int i0, int c0, uint4 ah, uint4 al, bool masked) {
+    auto chunk = [&](auto masked_tag, int i0, int c0, uint4 ah, uint4 al) {
+        constexpr bool masked = decltype(masked_tag)::value;
         const int ik = i0 + 8 * g;                            // first of this lane's 8 rows
         uint32_t m[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-        if (masked) {
+        if constexpr (masked) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 m[q] = ((ik + 2 * q < j) ? 0xFFFFu : 0u) | ((ik + 2 * q + 1 < j) ? 0xFFFF0000u : 0u);
@@ -111,7 +108,7 @@ __global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
             v1.y = onehot2(l1.y, lj2[b + 1]);
             v1.z = onehot2(l1.z, lj2[b + 1]);
             v1.w = onehot2(l1.w, lj2[b + 1]);
-            if (masked) {
+            if constexpr (masked) {
                 v0.x &= m[0]; v0.y &= m[1]; v0.z &= m[2]; v0.w &= m[3];
                 v1.x &= m[0]; v1.y &= m[1]; v1.z &= m[2]; v1.w &= m[3];
             }
@@ -134,16 +131,24 @@ __global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
         for (int e = threadIdx.x; e < B * RC; e += 256) {
             const int b = e / RC, r = e % RC;
             const int i = c0 + r, p = pbase + b;
-            lab_s[b][r] = (r < rows && p < P) ? (uint16_t)labels[(size_t)p * N + i] : (uint16_t)0xFFFFu;
+            lab_s[b][r] = (r < rows && p < P) ? (uint16_t)gld(labels + (size_t)p * N + i) : (uint16_t)0xFFFFu;
         }
         __syncthreads();
         const int cend = min(c0 + RC, my_iend);
         if (c0 < cend) {
             uint4 ah, al, nh, nl;
             load_a(c0, ah, al);
-            for (int i0 = c0; i0 < cend; i0 += 32) {
+            int i0 = c0;
+            const int uend = min(cend, max(c0, i_diag));        // chunks entirely below the diagonal
+            for (; i0 < uend; i0 += 32) {
                 if (i0 + 32 < cend) load_a(i0 + 32, nh, nl);
-                chunk(i0, c0, ah, al, i0 >= i_diag);
+                chunk(std::false_type{}, i0, c0, ah, al);
+                ah = nh;
+                al = nl;
+            }
+            for (; i0 < cend; i0 += 32) {
+                if (i0 + 32 < cend) load_a(i0 + 32, nh, nl);
+                chunk(std::true_type{}, i0, c0, ah, al);
                 ah = nh;
                 al = nl;
             }
@@ -152,12 +157,31 @@ __global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
     }
     flush();
     if (diag_lane && j < N) {
-        const double cjj = d.C[(size_t)j * N + j];
+        const double cjj = gld(d.C + (size_t)j * N + j);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int p = pbase + b;
-            if (p < P) d.wsum[(size_t)p * N + j] = fma(2.0, acc64[b], cjj);
+            if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[b], cjj));
         }
+    }
+}
+
+// The triangle is folded: column blocks n_jb-1-jp and jp share a workgroup, so every
+// workgroup processes the same number of row chunks.
+__global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
+    __shared__ __align__(16) uint16_t lab_s[kMfmaB][kMfmaRowChunk];
+    const int tile = blockIdx.x;
+    const int k = find_inst(t.tiles_mfma, t.n_inst, tile);
+    const InstDesc &d = t.desc[k];
+    const int local = tile - t.tiles_mfma[k];
+    const int n_jb = (d.N + kMfmaCols - 1) / kMfmaCols;
+    const int n_pairs = (n_jb + 1) / 2;
+    const int jp = local % n_pairs;
+    const int pb = local / n_pairs;
+    mfma_block(d, n_jb - 1 - jp, pb, parity, lab_s);
+    if (jp != n_jb - 1 - jp) {
+        __syncthreads();
+        mfma_block(d, jp, pb, parity, lab_s);
     }
 }
 

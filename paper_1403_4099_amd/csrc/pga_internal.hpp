@@ -49,13 +49,15 @@ constexpr int kFp64Inds = kFp64Waves * kFp64B;     // individuals per workgroup
 
 constexpr int kMfmaWaves = 4;                      // waves per workgroup, 16 columns each
 constexpr int kMfmaCols = 16 * kMfmaWaves;         // columns per workgroup
-constexpr int kMfmaB = 16;                         // individuals per workgroup
+constexpr int kMfmaB = 8;                          // individuals per workgroup
 constexpr int kMfmaRowChunk = 1024;                // rows of labels staged in LDS at a time
 constexpr int kMfmaFlushRows = 256;                // FP32 accumulators are flushed to FP64 every 256 rows
 
 inline int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
-inline int32_t fp64_tiles(int32_t N, int32_t P) { return ceil_div(N, kFp64Cols) * ceil_div(P, kFp64Inds); }
-inline int32_t mfma_tiles(int32_t N, int32_t P) { return ceil_div(N, kMfmaCols) * ceil_div(P, kMfmaB); }
+// Pair-sum tiles fold the triangle: column blocks jb and n_jb - 1 - jb share a workgroup.
+inline int32_t fold_pairs(int32_t N, int32_t cols) { return (ceil_div(N, cols) + 1) / 2; }
+inline int32_t fp64_tiles(int32_t N, int32_t P) { return fold_pairs(N, kFp64Cols) * ceil_div(P, kFp64Inds); }
+inline int32_t mfma_tiles(int32_t N, int32_t P) { return fold_pairs(N, kMfmaCols) * ceil_div(P, kMfmaB); }
 inline int32_t split_ld(int32_t N) { return (int32_t)(((int64_t)N + 31) / 32 * 32); }
 
 // ---- Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) ---------------------
@@ -88,6 +90,23 @@ __device__ __forceinline__ U4 draw(uint32_t blk, uint32_t who, uint32_t gen, uin
 
 // floor(w * m / 2^32)
 __device__ __forceinline__ uint32_t scale_u32(uint32_t w, uint32_t m) { return __umulhi(w, m); }
+
+// ---- explicit global-memory access ------------------------------------------
+// Pointers read from a descriptor are generic; the compiler then emits flat
+// loads, which count on the same wait counter as LDS operations, so a wait for
+// an LDS result would also wait for every in-flight prefetch. These helpers
+// access global memory through address-space-1 pointers (global loads/stores).
+#define PGA_GLOBAL __attribute__((address_space(1)))
+typedef uint32_t pga_u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ T gld(const T *p) { return *(const PGA_GLOBAL T *)p; }
+template <class T>
+__device__ __forceinline__ void gst(T *p, T v) { *(PGA_GLOBAL T *)p = v; }
+__device__ __forceinline__ uint4 gld_u4(const void *p) {
+    const pga_u32x4 v = *(const PGA_GLOBAL pga_u32x4 *)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
 
 // Instance lookup: largest k with prefix[k] <= t (prefix is exclusive, n + 1 entries).
 __device__ __forceinline__ int find_inst(const int32_t *prefix, int n, int t) {

@@ -129,6 +129,26 @@ def test_batched_instances_equal_each_alone():
         assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness) and torch.equal(a.stats, b.stats)
 
 
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+def test_ragged_batch_of_batched_workload_instances_equals_alone(form):
+    """24 instances of the batched workload (N ~ U{32..512}) in one evolve call == each alone."""
+    say(f"ragged batch of 24 ({form})")
+    G, P = 4, 64
+    ws = [synth.config4_instance(i, T=128) for i in range(24)]
+    Cs = [O.correlate(w.R) for w in ws]
+    alone = [_run(C, P, G, form, eager=False, seed=3, inst=i) for i, C in enumerate(Cs)]
+    ctx = pga.Context()
+    insts = [_inst(C, P, G, form=form, seed=3, instance_id=i) for i, C in enumerate(Cs)]
+    ctx.evolve(insts, G, form=form, init=True)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, insts):
+        assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness) and torch.equal(a.stats, b.stats)
+    if form == "fp64":
+        for C, b in zip(Cs, insts):
+            f_o, mag = O.fitness(C, b.pop.cpu().numpy(), want_mag=True)
+            assert np.all(np.abs(b.fitness.cpu().numpy() - f_o) <= fitness_tol(mag))
+
+
 def test_free_running_config1_recovers_planted_and_matches_oracle():
     say("free-running config 1")
     w = synth.config1()
