@@ -129,8 +129,12 @@ def pair_visits(N: int, P: int) -> float:
 
 
 def source_sha(path):
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of a kernel source together with the shared header that fixes its tile geometry."""
+    h = hashlib.sha256()
+    for p in (path, os.path.join(os.path.dirname(path), "pga_internal.hpp")):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic(kernel_src: str, N: int, P: int):
