@@ -359,29 +359,79 @@ void oracle_stats(const double *f, int P, double out[4])
     out[3] = (double)arg;
 }
 
-/* G generations of Algorithm 1 from generation gen0, then a final fitness.
- * If init != 0 the population is first filled by oracle_init_pop at gen0.
- * pop (P x N) is updated in place; fit (P) holds the final fitness; stats
- * (nullable) receives G + 1 rows of oracle_stats (each evaluated
- * generation, then the final one). */
+/* Termination test (Algorithm 1, "determine if termination criteria are
+ * met"; Table 3 gives an error tolerance and a number of stall generations).
+ * state = {ref, stall, stopped, gens}. The best fitness b of the generation
+ * just evaluated improves on the reference ref when ref is not finite and b
+ * is, or when b > ref + tol * max(1, |ref|); an improvement sets ref = b and
+ * stall = 0, anything else adds one stall generation. With stall_gens > 0 the
+ * run stops once stall reaches stall_gens. */
+static void term_update(double state[4], double b, int stall_gens, double tol)
+{
+    double ref = state[0];
+    int improved = isfinite(ref) ? (b > ref + tol * fmax(1.0, fabs(ref))) : isfinite(b);
+    if (improved) {
+        state[0] = b;
+        state[1] = 0.0;
+    } else {
+        state[1] += 1.0;
+    }
+    if (stall_gens > 0 && state[1] >= (double)stall_gens) state[2] = 1.0;
+}
+
+/* Up to G generations of Algorithm 1 from generation gen0, then a final
+ * fitness. If init != 0 the population is first filled by oracle_init_pop at
+ * gen0 and state is reset to {-inf, 0, 0, 0}. Each generation: evaluate,
+ * record statistics row g, apply the termination test, and, unless the run
+ * has stopped, breed generation g + 1 (state[3] counts the generations bred).
+ * A stopped run keeps its last population: nothing further is evaluated,
+ * recorded or bred, in this call or a later one with the same state. pop
+ * (P x N) is updated in place; fit (P) holds the fitness of the final
+ * population; stats (nullable) receives up to G + 1 rows of oracle_stats,
+ * rows after a stop are left untouched. stall_gens = 0 disables the test. */
+int oracle_evolve_term(const double *C, int N, int P, int E, uint32_t p_cross_thr, uint32_t p_mut_thr,
+                       uint64_t seed, uint32_t inst, uint32_t gen0, int G, int init,
+                       int stall_gens, double tol, int32_t *pop, double *fit, double *stats,
+                       int32_t *status, double state[4])
+{
+    if (N < 1 || P < 1 || E < 0 || E >= P || G < 0 || stall_gens < 0) return -1;
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)P * (size_t)N);
+    if (!next) return -2;
+    if (init) {
+        oracle_init_pop(N, P, seed, inst, gen0, pop);
+        state[0] = -INFINITY;
+        state[1] = state[2] = state[3] = 0.0;
+    }
+    if (state[2] != 0.0) {
+        /* already stopped: fit is the fitness of the kept population */
+        oracle_fitness(C, N, pop, P, fit, NULL, NULL, NULL, NULL);
+        free(next);
+        return 0;
+    }
+    double row[4];
+    for (int g = 0; g <= G; ++g) {
+        oracle_fitness(C, N, pop, P, fit, NULL, NULL, NULL, status);
+        oracle_stats(fit, P, row);
+        if (stats) memcpy(stats + 4 * (size_t)g, row, sizeof(row));
+        term_update(state, row[0], stall_gens, tol);
+        if (g == G || state[2] != 0.0) break;
+        oracle_breed(pop, fit, N, P, E, p_cross_thr, p_mut_thr, seed, inst, gen0 + (uint32_t)g, next);
+        memcpy(pop, next, sizeof(int32_t) * (size_t)P * (size_t)N);
+        state[3] += 1.0;
+    }
+    free(next);
+    return 0;
+}
+
+/* G generations of Algorithm 1 with no termination test, then a final
+ * fitness: G + 1 statistics rows. */
 int oracle_evolve(const double *C, int N, int P, int E, uint32_t p_cross_thr, uint32_t p_mut_thr,
                   uint64_t seed, uint32_t inst, uint32_t gen0, int G, int init,
                   int32_t *pop, double *fit, double *stats, int32_t *status)
 {
-    if (N < 1 || P < 1 || E < 0 || E >= P || G < 0) return -1;
-    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)P * (size_t)N);
-    if (!next) return -2;
-    if (init) oracle_init_pop(N, P, seed, inst, gen0, pop);
-    for (int g = 0; g < G; ++g) {
-        oracle_fitness(C, N, pop, P, fit, NULL, NULL, NULL, status);
-        if (stats) oracle_stats(fit, P, stats + 4 * (size_t)g);
-        oracle_breed(pop, fit, N, P, E, p_cross_thr, p_mut_thr, seed, inst, gen0 + (uint32_t)g, next);
-        memcpy(pop, next, sizeof(int32_t) * (size_t)P * (size_t)N);
-    }
-    oracle_fitness(C, N, pop, P, fit, NULL, NULL, NULL, status);
-    if (stats) oracle_stats(fit, P, stats + 4 * (size_t)G);
-    free(next);
-    return 0;
+    double state[4] = {-INFINITY, 0.0, 0.0, 0.0};
+    return oracle_evolve_term(C, N, P, E, p_cross_thr, p_mut_thr, seed, inst, gen0, G, init, 0, 0.0,
+                              pop, fit, stats, status, state);
 }
 
 /* ------------------------------------------------------------------ */

@@ -60,6 +60,9 @@ def lib():
         L.oracle_evolve.argtypes = [vp, ct.c_int, ct.c_int, ct.c_int, u32, u32, u64, u32, u32,
                                     ct.c_int, ct.c_int, vp, vp, vp, vp]
         L.oracle_evolve.restype = ct.c_int
+        L.oracle_evolve_term.argtypes = [vp, ct.c_int, ct.c_int, ct.c_int, u32, u32, u64, u32, u32,
+                                         ct.c_int, ct.c_int, ct.c_int, d, vp, vp, vp, vp, vp]
+        L.oracle_evolve_term.restype = ct.c_int
         L.oracle_canonical.argtypes = [vp, ct.c_int, vp]
         L.oracle_canonical.restype = None
         L.oracle_best.argtypes = [vp, vp, ct.c_int, ct.c_int, vp, vp, vp]
@@ -199,6 +202,30 @@ def evolve(C, P, G, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mut_thr=None, seed=0, in
     if rc != 0:
         raise ValueError(f"oracle_evolve rc={rc}")
     return pop, fit, st
+
+
+def evolve_term(C, P, G, stall_gens, tol, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mut_thr=None, seed=0,
+                inst=0, gen0=0, pop=None, state=None, status=None):
+    """Algorithm 1 with its termination test (Table 3: tolerance, stall generations).
+
+    Returns (pop, fit, stats[(G+1) x 4], state) with state = [ref, stall, stopped, gens];
+    statistics rows after a stop stay NaN. pop=None initialises the population (and
+    the state); otherwise pass the state of the previous call to continue it."""
+    C = _c64(C)
+    N = C.shape[0]
+    if p_mut_thr is None:
+        p_mut_thr = mut_thr(N)
+    init = pop is None
+    pop = np.empty((P, N), dtype=np.int32) if init else _ci32(pop).copy()
+    st8 = np.array([-np.inf, 0, 0, 0], dtype=np.float64) if state is None else _c64(state).copy()
+    fit = np.empty(P, dtype=np.float64)
+    st = np.full((G + 1, 4), np.nan, dtype=np.float64)
+    status = status if status is not None else status_zero()
+    rc = lib().oracle_evolve_term(_p(C), N, P, E, p_cross_thr, p_mut_thr, seed, inst, gen0, G, int(init),
+                                  stall_gens, float(tol), _p(pop), _p(fit), _p(st), _p(status), _p(st8))
+    if rc != 0:
+        raise ValueError(f"oracle_evolve_term rc={rc}")
+    return pop, fit, st, st8
 
 
 def canonical(lab):
