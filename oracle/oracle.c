@@ -232,6 +232,8 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
 #define TAG_SEL 1u
 #define TAG_XOV 2u
 #define TAG_MUT 3u
+#define TAG_SUS 4u
+#define TAG_SHUF 5u
 
 static void draw(uint32_t w0, uint32_t w1, uint32_t gen, uint32_t tag, uint32_t inst,
                  uint64_t seed, uint32_t out[4])
@@ -295,33 +297,123 @@ static int tournament2(const double *f, int a, int b)
     return a < b ? a : b;
 }
 
+/* ---- Stochastic universal sampling after rank scaling --------------- */
+/* Algorithm 1 scales the fitness and then selects; Section 3.1 names the
+ * selection: stochastic universal sampling (Baker, 1987), where individuals
+ * occupy consecutive segments of a line in proportion to their (scaled)
+ * fitness and the line is read at equally spaced points from one random
+ * offset. The paper does not say which scaling; this build ranks
+ * (fitness desc, index asc) and gives rank r (1 = best) the weight
+ * floor(2^24 / sqrt(r)), and an individual with fitness -inf weight 0 (if
+ * every individual has -inf, all weights are 1). Integer weights keep the
+ * segment boundaries exact. */
+static uint64_t sus_weight(int r)
+{
+    return (uint64_t)floor(16777216.0 / sqrt((double)r));
+}
+
+/* Pseudo-random permutation of [0, n) (a four-round Feistel network on
+ * 2h-bit words, 4^h >= n, with round function word 0 of Philox draw
+ * (right half, round) [SHUF], applied again while the value is >= n). */
+uint32_t oracle_shuffle_index(uint32_t x, uint32_t n, uint64_t seed, uint32_t inst, uint32_t gen)
+{
+    int h = 1;
+    while (((uint64_t)1 << (2 * h)) < (uint64_t)n) ++h;
+    const uint32_t mask = (1u << h) - 1u;
+    do {
+        uint32_t L = x >> h, R = x & mask;
+        for (uint32_t round = 0; round < 4; ++round) {
+            uint32_t w[4];
+            draw(R, round, gen, TAG_SHUF, inst, seed, w);
+            uint32_t t = R;
+            R = L ^ (w[0] & mask);
+            L = t;
+        }
+        x = (L << h) | R;
+    } while (x >= n);
+    return x;
+}
+
+/* Parents of the P - E children: parents[2j], parents[2j+1] for child E + j.
+ * n = 2(P - E) pointers; with W = total weight and u = floor(w0 W / 2^32)
+ * (w0: word 0 of draw (0, 0xFFFFFFFF) [SUS]), pointer k sits at
+ * floor((u + k W) / n) and selects the individual whose segment [cum_{p-1},
+ * cum_p) holds it (cum: inclusive prefix sums of the weights in index
+ * order). The selected list is then shuffled: parents[k] = sel[pi(k)]. */
+void oracle_sus_parents(const double *f, int P, int E, uint64_t seed, uint32_t inst, uint32_t gen,
+                        int32_t *parents)
+{
+    const int n = 2 * (P - E);
+    if (n <= 0) return;
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)P);
+    uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)P);
+    uint64_t *cum = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)P);
+    int32_t *sel = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    oracle_rank(f, P, order);
+    int any = 0;
+    for (int r = 0; r < P; ++r) {
+        int p = order[r];
+        w[p] = isfinite(f[p]) ? sus_weight(r + 1) : 0;
+        any |= w[p] != 0;
+    }
+    if (!any)
+        for (int p = 0; p < P; ++p) w[p] = 1;
+    uint64_t acc = 0;
+    for (int p = 0; p < P; ++p) { acc += w[p]; cum[p] = acc; }
+    const uint64_t W = acc;
+    uint32_t wd[4];
+    draw(0u, 0xFFFFFFFFu, gen, TAG_SUS, inst, seed, wd);
+    const uint64_t u = (uint64_t)(((unsigned __int128)wd[0] * W) >> 32);
+    int p = 0;
+    for (int k = 0; k < n; ++k) {
+        const uint64_t pos = (u + (uint64_t)k * W) / (uint64_t)n;
+        while (cum[p] <= pos) ++p;
+        sel[k] = p;
+    }
+    for (int k = 0; k < n; ++k)
+        parents[k] = sel[oracle_shuffle_index((uint32_t)k, (uint32_t)n, seed, inst, gen)];
+    free(order); free(w); free(cum); free(sel);
+}
+
 /* One replacement step from population pop with fitness f (generation gen)
  * into out (Algorithm 1: elitism, selection, crossover, mutation,
  * replacement; Section 3.1).
  *   - out[0..E) are the E fittest individuals, copied unchanged;
- *   - each child c in [E, P): parent A is the winner of a tournament between
- *     draws w0, w1 of (0, c) [SEL]; parent B between w2, w3; indices are
- *     scale_u32(w, P);
+ *   - each child c in [E, P), selection 0: parent A is the winner of a
+ *     tournament between draws w0, w1 of (0, c) [SEL]; parent B between w2,
+ *     w3; indices are scale_u32(w, P). Selection 1: parents 2(c - E) and
+ *     2(c - E) + 1 of oracle_sus_parents;
  *   - crossover happens when word 0 of draw (0, c) [XOV] is below
  *     p_cross_thr; then gene j comes from B when bit j%32 of word (j%128)/32
  *     of draw (1 + j/128, c) [XOV] is set, otherwise from A;
  *   - mutation: draw (j/2, c) [MUT] gives words (2(j%2), 2(j%2)+1) = (d, v);
  *     when d < p_mut_thr gene j becomes scale_u32(v, N). */
-void oracle_breed(const int32_t *pop, const double *f, int N, int P, int E,
-                  uint32_t p_cross_thr, uint32_t p_mut_thr, uint64_t seed, uint32_t inst,
-                  uint32_t gen, int32_t *out)
+void oracle_breed_sel(const int32_t *pop, const double *f, int N, int P, int E, int selection,
+                      uint32_t p_cross_thr, uint32_t p_mut_thr, uint64_t seed, uint32_t inst,
+                      uint32_t gen, int32_t *out)
 {
     int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)P);
     oracle_rank(f, P, order);
     for (int e = 0; e < E; ++e)
         memcpy(out + (size_t)e * N, pop + (size_t)order[e] * N, sizeof(int32_t) * (size_t)N);
     free(order);
+    int32_t *par = NULL;
+    if (selection == 1) {
+        par = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * (P - E) + 1));
+        oracle_sus_parents(f, P, E, seed, inst, gen, par);
+    }
 
     for (int c = E; c < P; ++c) {
         uint32_t ws[4], wx[4];
-        draw(0u, (uint32_t)c, gen, TAG_SEL, inst, seed, ws);
-        int A = tournament2(f, (int)scale_u32(ws[0], (uint32_t)P), (int)scale_u32(ws[1], (uint32_t)P));
-        int B = tournament2(f, (int)scale_u32(ws[2], (uint32_t)P), (int)scale_u32(ws[3], (uint32_t)P));
+        int A, B;
+        if (selection == 1) {
+            A = par[2 * (c - E)];
+            B = par[2 * (c - E) + 1];
+        } else {
+            draw(0u, (uint32_t)c, gen, TAG_SEL, inst, seed, ws);
+            A = tournament2(f, (int)scale_u32(ws[0], (uint32_t)P), (int)scale_u32(ws[1], (uint32_t)P));
+            B = tournament2(f, (int)scale_u32(ws[2], (uint32_t)P), (int)scale_u32(ws[3], (uint32_t)P));
+        }
         draw(0u, (uint32_t)c, gen, TAG_XOV, inst, seed, wx);
         int cross = wx[0] < p_cross_thr;
         for (int j = 0; j < N; ++j) {
@@ -339,6 +431,14 @@ void oracle_breed(const int32_t *pop, const double *f, int N, int P, int E,
             out[(size_t)c * N + j] = gene;
         }
     }
+    free(par);
+}
+
+void oracle_breed(const int32_t *pop, const double *f, int N, int P, int E,
+                  uint32_t p_cross_thr, uint32_t p_mut_thr, uint64_t seed, uint32_t inst,
+                  uint32_t gen, int32_t *out)
+{
+    oracle_breed_sel(pop, f, N, P, E, 0, p_cross_thr, p_mut_thr, seed, inst, gen, out);
 }
 
 /* Per-generation statistics (Algorithm 1, "evaluate state and statistics"):
@@ -388,13 +488,15 @@ static void term_update(double state[4], double b, int stall_gens, double tol)
  * recorded or bred, in this call or a later one with the same state. pop
  * (P x N) is updated in place; fit (P) holds the fitness of the final
  * population; stats (nullable) receives up to G + 1 rows of oracle_stats,
- * rows after a stop are left untouched. stall_gens = 0 disables the test. */
-int oracle_evolve_term(const double *C, int N, int P, int E, uint32_t p_cross_thr, uint32_t p_mut_thr,
-                       uint64_t seed, uint32_t inst, uint32_t gen0, int G, int init,
+ * rows after a stop are left untouched. stall_gens = 0 disables the test.
+ * selection: 0 tournaments of two, 1 stochastic universal sampling. */
+int oracle_evolve_term(const double *C, int N, int P, int E, int selection, uint32_t p_cross_thr,
+                       uint32_t p_mut_thr, uint64_t seed, uint32_t inst, uint32_t gen0, int G, int init,
                        int stall_gens, double tol, int32_t *pop, double *fit, double *stats,
                        int32_t *status, double state[4])
 {
     if (N < 1 || P < 1 || E < 0 || E >= P || G < 0 || stall_gens < 0) return -1;
+    if (selection != 0 && selection != 1) return -1;
     int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)P * (size_t)N);
     if (!next) return -2;
     if (init) {
@@ -415,7 +517,8 @@ int oracle_evolve_term(const double *C, int N, int P, int E, uint32_t p_cross_th
         if (stats) memcpy(stats + 4 * (size_t)g, row, sizeof(row));
         term_update(state, row[0], stall_gens, tol);
         if (g == G || state[2] != 0.0) break;
-        oracle_breed(pop, fit, N, P, E, p_cross_thr, p_mut_thr, seed, inst, gen0 + (uint32_t)g, next);
+        oracle_breed_sel(pop, fit, N, P, E, selection, p_cross_thr, p_mut_thr, seed, inst,
+                         gen0 + (uint32_t)g, next);
         memcpy(pop, next, sizeof(int32_t) * (size_t)P * (size_t)N);
         state[3] += 1.0;
     }
@@ -430,7 +533,7 @@ int oracle_evolve(const double *C, int N, int P, int E, uint32_t p_cross_thr, ui
                   int32_t *pop, double *fit, double *stats, int32_t *status)
 {
     double state[4] = {-INFINITY, 0.0, 0.0, 0.0};
-    return oracle_evolve_term(C, N, P, E, p_cross_thr, p_mut_thr, seed, inst, gen0, G, init, 0, 0.0,
+    return oracle_evolve_term(C, N, P, E, 0, p_cross_thr, p_mut_thr, seed, inst, gen0, G, init, 0, 0.0,
                               pop, fit, stats, status, state);
 }
 

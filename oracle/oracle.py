@@ -60,8 +60,15 @@ def lib():
         L.oracle_evolve.argtypes = [vp, ct.c_int, ct.c_int, ct.c_int, u32, u32, u64, u32, u32,
                                     ct.c_int, ct.c_int, vp, vp, vp, vp]
         L.oracle_evolve.restype = ct.c_int
-        L.oracle_evolve_term.argtypes = [vp, ct.c_int, ct.c_int, ct.c_int, u32, u32, u64, u32, u32,
+        L.oracle_evolve_term.argtypes = [vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u32, u32, u64, u32, u32,
                                          ct.c_int, ct.c_int, ct.c_int, d, vp, vp, vp, vp, vp]
+        L.oracle_breed_sel.argtypes = [vp, vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u32, u32, u64, u32,
+                                       u32, vp]
+        L.oracle_breed_sel.restype = None
+        L.oracle_sus_parents.argtypes = [vp, ct.c_int, ct.c_int, u64, u32, u32, vp]
+        L.oracle_sus_parents.restype = None
+        L.oracle_shuffle_index.argtypes = [u32, u32, u64, u32, u32]
+        L.oracle_shuffle_index.restype = u32
         L.oracle_evolve_term.restype = ct.c_int
         L.oracle_canonical.argtypes = [vp, ct.c_int, vp]
         L.oracle_canonical.restype = None
@@ -167,15 +174,31 @@ def mut_thr(N):
     return (2**32) // N if N > 1 else 2**32 - 1
 
 
-def breed(pop, f, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mut_thr=None, seed=0, inst=0, gen=0):
+def breed(pop, f, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mut_thr=None, seed=0, inst=0, gen=0, selection=0):
+    """One replacement step; selection 0 = tournaments of two, 1 = stochastic universal sampling."""
     pop = _ci32(pop)
     f = _c64(f)
     P, N = pop.shape
     if p_mut_thr is None:
         p_mut_thr = mut_thr(N)
     out = np.empty_like(pop)
-    lib().oracle_breed(_p(pop), _p(f), N, P, E, p_cross_thr, p_mut_thr, seed, inst, gen, _p(out))
+    lib().oracle_breed_sel(_p(pop), _p(f), N, P, E, selection, p_cross_thr, p_mut_thr, seed, inst, gen,
+                           _p(out))
     return out
+
+
+def sus_parents(f, E=2, seed=0, inst=0, gen=0):
+    """Parents (2(P-E),) chosen by stochastic universal sampling after rank scaling."""
+    f = _c64(f)
+    P = f.shape[0]
+    out = np.empty(max(0, 2 * (P - E)), dtype=np.int32)
+    lib().oracle_sus_parents(_p(f), P, E, seed, inst, gen, _p(out))
+    return out
+
+
+def shuffle_index(x, n, seed=0, inst=0, gen=0):
+    """Image of x under the Philox-keyed permutation of [0, n) used to pair SUS parents."""
+    return int(lib().oracle_shuffle_index(x, n, seed, inst, gen))
 
 
 def stats(f):
@@ -205,7 +228,7 @@ def evolve(C, P, G, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mut_thr=None, seed=0, in
 
 
 def evolve_term(C, P, G, stall_gens, tol, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mut_thr=None, seed=0,
-                inst=0, gen0=0, pop=None, state=None, status=None):
+                inst=0, gen0=0, pop=None, state=None, status=None, selection=0):
     """Algorithm 1 with its termination test (Table 3: tolerance, stall generations).
 
     Returns (pop, fit, stats[(G+1) x 4], state) with state = [ref, stall, stopped, gens];
@@ -221,8 +244,9 @@ def evolve_term(C, P, G, stall_gens, tol, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mu
     fit = np.empty(P, dtype=np.float64)
     st = np.full((G + 1, 4), np.nan, dtype=np.float64)
     status = status if status is not None else status_zero()
-    rc = lib().oracle_evolve_term(_p(C), N, P, E, p_cross_thr, p_mut_thr, seed, inst, gen0, G, int(init),
-                                  stall_gens, float(tol), _p(pop), _p(fit), _p(st), _p(status), _p(st8))
+    rc = lib().oracle_evolve_term(_p(C), N, P, E, selection, p_cross_thr, p_mut_thr, seed, inst, gen0, G,
+                                  int(init), stall_gens, float(tol), _p(pop), _p(fit), _p(st), _p(status),
+                                  _p(st8))
     if rc != 0:
         raise ValueError(f"oracle_evolve_term rc={rc}")
     return pop, fit, st, st8
