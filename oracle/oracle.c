@@ -165,6 +165,55 @@ void oracle_fitness(const double *C, int N, const int32_t *pop, int P, double *f
 }
 
 /* ------------------------------------------------------------------ */
+/* Online EWMA correlation (Section 4.2.4, data pre-processing): market */
+/* mode removed, then an exponentially weighted covariance with         */
+/* forgetting factor lambda, then the correlation of that covariance.   */
+/* ------------------------------------------------------------------ */
+/* R is N x T (row stride ld), the T newest returns in time order. S (N x N)
+ * is the covariance state: when reset != 0 it starts at 0, otherwise the
+ * call continues from it. For each t in order: m_t = (1/N) sum_i R_it when
+ * market != 0 (the equal-weight market return, removed from every stock),
+ * else 0; x_i = R_it - m_t; S_ij <- lambda S_ij + (1 - lambda) x_i x_j.
+ * Then C_ij = S_ij / sqrt(S_ii S_jj) clamped to [-1, 1], C_ii = 1, and a
+ * stock with S_ii = 0 gets 0 off the diagonal (counted in status[2]). The
+ * paper does not give its market-mode estimator or the EWMA's exact form;
+ * these are this build's readings. */
+void oracle_ewma(const double *R, int N, int T, long ld, double lambda, int reset, int market,
+                 double *S, double *C, int32_t *status)
+{
+    if (reset)
+        for (long e = 0; e < (long)N * N; ++e) S[e] = 0.0;
+    double *x = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    for (int t = 0; t < T; ++t) {
+        double m = 0.0;
+        if (market) {
+            for (int i = 0; i < N; ++i) m += R[(size_t)i * ld + t];
+            m /= (double)N;
+        }
+        for (int i = 0; i < N; ++i) x[i] = R[(size_t)i * ld + t] - m;
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j)
+                S[(size_t)i * N + j] = lambda * S[(size_t)i * N + j] + (1.0 - lambda) * x[i] * x[j];
+    }
+    free(x);
+    for (int i = 0; i < N; ++i)
+        if (S[(size_t)i * N + i] == 0.0 && status) status[ST_ZEROVAR] += 1;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double v;
+            const double a = S[(size_t)i * N + i], b = S[(size_t)j * N + j];
+            if (i == j) v = 1.0;
+            else if (a == 0.0 || b == 0.0) v = 0.0;
+            else {
+                v = S[(size_t)i * N + j] / sqrt(a * b);
+                if (v > 1.0) v = 1.0;
+                if (v < -1.0) v = -1.0;
+            }
+            C[(size_t)i * N + j] = v;
+        }
+}
+
+/* ------------------------------------------------------------------ */
 /* BF16 hi + lo split of C (mixed-precision form).                      */
 /* ------------------------------------------------------------------ */
 /* Round x to the nearest bfloat16 value, ties to even, in one rounding from
@@ -304,12 +353,24 @@ static int tournament2(const double *f, int a, int b)
  * fitness and the line is read at equally spaced points from one random
  * offset. The paper does not say which scaling; this build ranks
  * (fitness desc, index asc) and gives rank r (1 = best) the weight
- * floor(2^24 / sqrt(r)), and an individual with fitness -inf weight 0 (if
- * every individual has -inf, all weights are 1). Integer weights keep the
- * segment boundaries exact. */
+ * floor(2^24 / sqrt(r)) = floor(sqrt(floor(2^48 / r))), computed in exact
+ * integer arithmetic, and an individual with fitness -inf weight 0 (if every
+ * individual has -inf, all weights are 1). Integer weights keep the segment
+ * boundaries exact. */
+static uint64_t isqrt_u64(uint64_t x)
+{
+    /* largest y with y * y <= x, one bit at a time from the top */
+    uint64_t y = 0;
+    for (int b = 31; b >= 0; --b) {
+        uint64_t t = y | ((uint64_t)1 << b);
+        if (t * t <= x) y = t;
+    }
+    return y;
+}
+
 static uint64_t sus_weight(int r)
 {
-    return (uint64_t)floor(16777216.0 / sqrt((double)r));
+    return isqrt_u64(((uint64_t)1 << 48) / (uint64_t)r);
 }
 
 /* Pseudo-random permutation of [0, n) (a four-round Feistel network on

@@ -69,6 +69,8 @@ def lib():
         L.oracle_sus_parents.restype = None
         L.oracle_shuffle_index.argtypes = [u32, u32, u64, u32, u32]
         L.oracle_shuffle_index.restype = u32
+        L.oracle_ewma.argtypes = [vp, ct.c_int, ct.c_int, ct.c_long, d, ct.c_int, ct.c_int, vp, vp, vp]
+        L.oracle_ewma.restype = None
         L.oracle_evolve_term.restype = ct.c_int
         L.oracle_canonical.argtypes = [vp, ct.c_int, vp]
         L.oracle_canonical.restype = None
@@ -250,6 +252,19 @@ def evolve_term(C, P, G, stall_gens, tol, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mu
     if rc != 0:
         raise ValueError(f"oracle_evolve_term rc={rc}")
     return pop, fit, st, st8
+
+
+def ewma(R, lam=0.98, S=None, market=True, status=None):
+    """Online EWMA correlation (Section 4.2.4): returns (C, S). S=None starts from a zero state;
+    otherwise the recursion continues from the given state (not modified)."""
+    R = _c64(R)
+    N, T = R.shape
+    reset = S is None
+    S = np.zeros((N, N), dtype=np.float64) if reset else _c64(S).copy()
+    C = np.empty((N, N), dtype=np.float64)
+    status = status if status is not None else status_zero()
+    lib().oracle_ewma(_p(R), N, T, T, float(lam), int(reset), int(market), _p(S), _p(C), _p(status))
+    return C, S
 
 
 def canonical(lab):

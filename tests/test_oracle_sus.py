@@ -19,7 +19,7 @@ def _rank_weights(f):
     order = sorted(range(P), key=lambda p: (-f[p], p))
     w = np.zeros(P, dtype=np.float64)
     for r, p in enumerate(order, start=1):
-        w[p] = math.floor(2**24 / math.sqrt(r)) if np.isfinite(f[p]) else 0.0
+        w[p] = math.isqrt(2**48 // r) if np.isfinite(f[p]) else 0.0
     return w if w.sum() > 0 else np.ones(P)
 
 
