@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--batched-instances", type=int, default=256,
                     help="instances of the ragged batched run (0 = skip)")
+    ap.add_argument("--tune-reps", type=int, default=5,
+                    help="timed evaluations per pair-sum kernel variant in the autotuning pass")
     return ap.parse_args()
 
 
@@ -108,9 +110,10 @@ def serving_run(seconds, rate, form):
 
 
 # ---------------------------------------------------------------- launch geometry (issued work)
-def mfma_issued_flops(N: int, P: int) -> float:
-    """MFMA flops the BF16x2 pair-sum kernel issues for one launch (all tiles, padding included)."""
-    cols, B = 64, 8
+def mfma_issued_flops(N: int, P: int, B: int = 8) -> float:
+    """MFMA flops the BF16x2 pair-sum kernel issues for one launch (all tiles, padding included;
+    B individuals per workgroup)."""
+    cols = 64
     n_jb = -(-N // cols)
     n_pb = -(-P // B)
     mfmas = 0
@@ -152,27 +155,38 @@ def recorded_traffic(kernel_src: str, N: int, P: int):
 
 # ---------------------------------------------------------------- CPU baseline (oracle)
 def cpu_baseline(w, P, seed):
+    """The oracle, unchanged, on the host cores: the population's fitness is split into row blocks
+    evaluated by concurrent calls into the oracle (each call is single-threaded C and releases
+    the GIL), then one breed step. A single-thread run of a slice gives the per-core rate."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
     import oracle as O
-    from paper_1403_4099_amd import synth
 
-    threads = 1   # the oracle is single-threaded C
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
     t0 = time.perf_counter()
     C = O.correlate(w.R)
     t_corr = time.perf_counter() - t0
     pop = O.init_pop(w.N, P, seed=seed)
     t0 = time.perf_counter()
-    f = O.fitness(C, pop)
+    O.fitness(C, pop[: max(1, P // threads)])
+    t_one = time.perf_counter() - t0
+    blocks = np.array_split(np.arange(P), threads)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda ix: O.fitness(C, pop[ix]), blocks))
     t_fit = time.perf_counter() - t0
+    f = np.concatenate(parts)
     t0 = time.perf_counter()
     O.breed(pop, f, E=2, seed=seed, gen=0)
     t_breed = time.perf_counter() - t0
     evals_per_s = P / (t_fit + t_breed)
     return {
         "value": evals_per_s, "unit": "fitness evals/s", "cores": threads, "kind": "oracle",
-        "sample": (f"one generation of the N={w.N}, P={P} workload on the CPU oracle: fitness of the "
-                   f"{P} initial labelings ({t_fit:.2f} s) + one breed step ({t_breed:.2f} s); "
+        "sample": (f"one generation of the N={w.N}, P={P} workload on the CPU oracle with {threads} "
+                   f"threads: fitness of the {P} initial labelings ({t_fit:.2f} s) + one breed step "
+                   f"({t_breed:.2f} s); one thread alone: {max(1, P // threads) / t_one:.0f} evals/s; "
                    f"correlation of the window took {t_corr:.2f} s and is not in the rate"),
         "gens_per_s": 1.0 / (t_fit + t_breed),
         "correlate_s": t_corr,
@@ -236,6 +250,22 @@ def main():
         return wall, e0.elapsed_time(e1) / 1e3, res
 
     forms = [args.form] + ([] if args.no_compare else [f for f in ("bf16x2", "fp64") if f != args.form])
+
+    # ---- autotune the pair-sum kernel of each form on this shape (random labelings of the workload)
+    L = pga.load()
+    rc = L.pga_correlate(pga._ptr(R), N, T, R.stride(0), pga._ptr(C), pga._ptr(hi), pga._ptr(lo),
+                         pga._ptr(status), pga._ptr(cws), cws.numel(), pga._stream())
+    pga._check(rc, "pga_correlate")
+    pop_tune = torch.from_numpy(synth.random_labelings(P, N, seed=7)).to(dev)
+    tuned = {}
+    for form in forms:
+        v, ms = pga.tune(C, pop_tune, form, hi=hi, lo=lo, reps=args.tune_reps)
+        tuned[form] = {"variant": v, "individuals_per_group": pga.variants(form)[v][0],
+                       "xcd_order": pga.variants(form)[v][1],
+                       "ms_per_variant": {f"{a}x{b}": round(m, 4) for (a, b), m in zip(pga.variants(form), ms)}}
+        print(f"[bench] autotune {form}: {tuned[form]}", file=sys.stderr, flush=True)
+    del pop_tune
+
     results = {}
     for form in forms:
         wall, ev, (lab, fbest, idx) = timed(form, args.steps, args.warmup)
@@ -288,7 +318,7 @@ def main():
     t_launch = k["avg_us"] * 1e-6
     src = os.path.join(ROOT, "paper_1403_4099_amd", "csrc", "k_mfma.hip" if form == "bf16x2" else "k_fitness.hip")
     if form == "bf16x2":
-        achieved = mfma_issued_flops(N, P) / t_launch / 1e12
+        achieved = mfma_issued_flops(N, P, tuned[form]["individuals_per_group"]) / t_launch / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_MFMA_BF16, "traffic": recorded_traffic(src, N, P),
                 "kernel": "k_pairsum_mfma", "avg_launch_us": k["avg_us"],
@@ -331,6 +361,7 @@ def main():
         "other_forms": other,
         "kernels_us": kern,
         "precision": prec,
+        "autotune": tuned,
         "roofline": roof,
     }
     if args.batched_instances > 0:

@@ -60,6 +60,12 @@ extern "C" {
 #define PGA_N_MAX 4096            /* largest number of stocks per instance */
 #define PGA_E_MAX 64              /* largest elite count */
 
+#define PGA_SELECT_TOURNAMENT 0   /* parents: winners of tournaments of two */
+#define PGA_SELECT_SUS 1          /* parents: stochastic universal sampling after rank scaling */
+
+#define PGA_EWMA_RESET 1          /* pga_ewma: start from a zero covariance state */
+#define PGA_EWMA_MARKET 2         /* pga_ewma: remove the equal-weight market return first */
+
 #define PGA_EVOLVE_INIT 1         /* fill pop with the initial population at gen0 first */
 #define PGA_EVOLVE_EAGER 2        /* launch kernels one by one instead of replaying a HIP graph */
 
@@ -72,13 +78,35 @@ typedef struct pga_ctx pga_ctx;
  * per-gene random-replacement mutation). */
 typedef struct {
     int32_t elites;        /* E, 0 <= E < P, E <= PGA_E_MAX (elitism, Section 3.1) */
-    int32_t tournament;    /* tournament size; must be 2 */
+    int32_t tournament;    /* tournament size; must be 2 with PGA_SELECT_TOURNAMENT */
     uint32_t p_cross_thr;  /* crossover when a uniform u32 is below this (0.9 -> 3865470566) */
     uint32_t p_mut_thr;    /* per-gene mutation when a uniform u32 is below this (1/N -> floor(2^32/N)) */
     uint64_t seed;         /* Philox4x32-10 key: (seed & 0xffffffff, seed >> 32) */
     uint32_t instance_id;  /* goes into every Philox counter; < 2^28 */
     uint32_t gen0;         /* absolute generation index of the population in `pop` on entry */
+    int32_t stall_gens;    /* termination test: stop after this many generations without an
+                              improvement (Table 3: 50); 0 disables the test */
+    int32_t selection;     /* PGA_SELECT_TOURNAMENT or PGA_SELECT_SUS */
+    double tol;            /* termination test: an improvement must exceed tol * max(1, |ref|)
+                              (Table 3 "error tolerance": 1e-5) */
 } pga_params;
+
+/* Termination state of one instance (Algorithm 1, "determine if termination
+ * criteria are met"). Device memory owned by the caller; PGA_EVOLVE_INIT
+ * resets it, otherwise a call continues from it. After each evaluated
+ * generation with best fitness b: b improves on ref when ref is not finite
+ * and b is, or when b > ref + tol * max(1, |ref|); an improvement sets
+ * ref = b and stall = 0, anything else adds 1 to stall; the instance stops
+ * when stall reaches stall_gens. A stopped instance keeps its population:
+ * no later generation of this or any later call evaluates, records
+ * statistics rows or breeds it. */
+typedef struct {
+    double ref;            /* reference best fitness (-inf before the first evaluation) */
+    int32_t stall;         /* evaluated generations since the last improvement */
+    int32_t stopped;       /* 1 once the test has fired */
+    int32_t gens;          /* generations bred, summed over calls (the next call's gen0) */
+    int32_t call_gens;     /* generations bred by the latest pga_evolve call */
+} pga_term_state;
 
 /* One GA instance. Host struct holding device pointers. */
 typedef struct {
@@ -90,7 +118,9 @@ typedef struct {
     int32_t *pop;          /* P x N labels: generation gen0 on entry, gen0 + G on return */
     int32_t *pop_tmp;      /* P x N scratch, ping-pong partner of pop */
     double *fitness;       /* P: on return, the fitness of the final population */
-    double *stats;         /* nullable; (G + 1) x 4 rows {best, mean of finite, #-inf, argbest} */
+    double *stats;         /* nullable; (G + 1) x 4 rows {best, mean of finite, #-inf, argbest};
+                              rows after a stop are left untouched */
+    pga_term_state *term;  /* device; required when prm.stall_gens > 0, else nullable */
     pga_params prm;
 } pga_instance;
 
@@ -122,6 +152,28 @@ int32_t pga_split_ld(int32_t N);
  * pga_split_ld(N) x pga_split_ld(N) uint16 bit patterns. */
 int pga_split(const double *C, int32_t N, uint16_t *C_hi, uint16_t *C_lo, void *stream);
 
+/* ---- online EWMA correlation (Section 4.2.4, data pre-processing) ------ */
+/* The step before the path for streaming windows: the paper removes the
+ * market mode, keeps an exponentially weighted moving-average covariance
+ * with forgetting factor lambda (0.98 there), and takes the correlation of
+ * that covariance. R: N x T FP64 (row stride ld_r >= T), the T newest
+ * returns in time order. S: N x N FP64 covariance state, caller-owned,
+ * updated in place (PGA_EWMA_RESET: start from 0; otherwise continue). For
+ * each t: m_t = (1/N) sum_i R_it with PGA_EWMA_MARKET, else 0;
+ * x_t = R_t - m_t; S <- lambda S + (1 - lambda) x_t x_t^T. Then
+ * C_ij = S_ij / sqrt(S_ii S_jj) clamped to [-1, 1], C_ii = 1, and a stock
+ * with S_ii = 0 gets 0 off the diagonal and is counted in
+ * status[PGA_ST_ZEROVAR]. C_hi / C_lo (nullable, both or neither): also the
+ * BF16 split of C as pga_split. Computed as S <- lambda^T S + X X^T with
+ * x_it scaled by sqrt((1 - lambda) lambda^(T-1-t)) (FP64 throughout).
+ * Errors: PGA_ERR_ARG (null pointer, N < 1, T < 1, ld_r < T, lambda outside
+ * [0, 1), unknown flag, one of hi/lo), PGA_ERR_UNSUPPORTED (split with
+ * N > PGA_N_MAX), PGA_ERR_WORKSPACE (pga_ewma_ws_bytes(N, T)). Async. */
+size_t pga_ewma_ws_bytes(int32_t N, int32_t T);
+int pga_ewma(const double *R, int32_t N, int32_t T, int32_t ld_r, double lambda, int32_t flags,
+             double *S, double *C, uint16_t *C_hi, uint16_t *C_lo, int32_t *status, void *ws,
+             size_t ws_bytes, void *stream);
+
 /* ---- fitness (Eqs. 5, 6, 8) -------------------------------------------- */
 /* For each of the P labelings (labels: P x N int32):
  *   n_s = #{i : s_i = s}, c_s = sum_{i,j} C_ij [s_i = s][s_j = s] (diagonal
@@ -140,6 +192,37 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
                 int32_t *n_s, double *c_s, int32_t *status, void *ws, size_t ws_bytes,
                 void *stream);
 
+/* ---- kernel variants and autotuning ------------------------------------- */
+/* The pair-sum kernel of each form comes in variants that differ only in how
+ * work is grouped: individuals per group (per wave for PGA_FORM_FP64, per
+ * workgroup for PGA_FORM_BF16X2) and whether tiles are renumbered so that
+ * each of the 8 XCDs receives a contiguous range. All variants of a form
+ * give bitwise identical results. pga_fitness and pga_evolve use the variant
+ * the process-wide tuning table holds for (form, ceil(N / 64), ceil(log2 P))
+ * (N: largest N of the call, P: its total number of individuals), variant 0
+ * when there is none or when it does not fit N. The table is shared by all
+ * threads and devices of the process and guarded by a lock.
+ *
+ * pga_variant_count: number of variants of `form` (PGA_ERR_ARG for a bad form).
+ * pga_variant_info: individuals per group and XCD ordering of one variant.
+ * pga_tune (SYNC): times every variant that fits N on `labels` (P x N, device)
+ *   with `reps` evaluations after one warm-up, each timed by HIP events on
+ *   `stream`; stores the fastest in the table and returns it in out_variant;
+ *   out_ms (nullable, pga_variant_count(form) floats, host) receives the
+ *   mean milliseconds per evaluation, -1 for variants that do not fit.
+ *   Workspace: pga_tune_ws_bytes(N, P, form). Errors as pga_fitness.
+ * pga_tune_set: sets (variant >= 0) or clears (-1) the table entry.
+ * pga_tune_get: the variant a call with this (form, N, P) would use. */
+int pga_variant_count(int32_t form);
+int pga_variant_info(int32_t form, int32_t variant, int32_t *individuals_per_group,
+                     int32_t *xcd_order);
+size_t pga_tune_ws_bytes(int32_t N, int32_t P, int32_t form);
+int pga_tune(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
+             const int32_t *labels, int32_t P, int32_t form, int32_t reps, void *ws,
+             size_t ws_bytes, int32_t *out_variant, float *out_ms, void *stream);
+int pga_tune_set(int32_t form, int32_t N, int32_t P, int32_t variant);
+int pga_tune_get(int32_t form, int32_t N, int32_t P);
+
 /* ---- evolution (Algorithm 1) ------------------------------------------- */
 /* Runs `generations` (G >= 0) generations on each of the n_inst instances
  * (inst is a HOST array; the descriptors are copied before return, the
@@ -147,16 +230,29 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
  * index gen0 + k): fitness of pop_g; statistics row k; the E fittest copied
  * unchanged to slots 0..E-1 (ties: lower index first); each child slot
  * c >= E gets parents A and B from two tournaments of two (higher fitness
- * wins, ties to the lower index), uniform crossover with probability
- * p_cross, then per-gene mutation to a uniform label. After G generations
+ * wins, ties to the lower index) or, with PGA_SELECT_SUS, by stochastic
+ * universal sampling (Section 3.1) after rank scaling: rank r (fitness desc,
+ * index asc) weighs floor(sqrt(floor(2^48 / r))), -inf weighs 0 (all 1 if
+ * every fitness is -inf); n = 2(P - E) pointers floor((u + k W) / n), W the
+ * total weight and u = floor(w W / 2^32) for word 0 w of draw
+ * (0, 0xFFFFFFFF, g, SUS), select from the index-ordered segments, and
+ * child E + j takes the pointers pi(2j), pi(2j + 1) of a four-round Feistel
+ * permutation pi of [0, n) (h-bit halves, 4^h >= n, round function word 0
+ * of draw (right half, round, g, SHUFFLE), repeated while >= n); then
+ * uniform crossover with probability p_cross and per-gene mutation to a
+ * uniform label. After G generations
  * the final population is evaluated into `fitness` and stats row G.
  * Random draws come from Philox4x32-10 with counter
  *   (block, individual or child, generation, tag | instance_id << 4),
- * tags INIT=0, SELECT=1, CROSSOVER=2, MUTATION=3, so a run is a pure
+ * tags INIT=0, SELECT=1, CROSSOVER=2, MUTATION=3, SUS=4, SHUFFLE=5, so a run is a pure
  * function of (pop at gen0, seed, instance_id, gen0, G): evolving 0->g then
  * g->G equals 0->G bit for bit, alone or batched with other instances.
- * flags: PGA_EVOLVE_INIT fills pop at gen0 first; PGA_EVOLVE_EAGER skips the
- * HIP graph. All instances use the same `form`. */
+ * With prm.stall_gens > 0 the termination test (pga_term_state) runs after
+ * every evaluation; an instance that stops ends with its last evaluated
+ * population in `pop` and its fitness in `fitness`, while the others of the
+ * batch go on. flags: PGA_EVOLVE_INIT fills pop at gen0 first (and resets
+ * the termination state); PGA_EVOLVE_EAGER skips the HIP graph. All
+ * instances use the same `form`. */
 size_t pga_evolve_ws_bytes(const pga_instance *inst, int32_t n_inst, int32_t form);
 int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t generations,
                int32_t form, int32_t flags, void *ws, size_t ws_bytes, int32_t *status,
@@ -178,7 +274,8 @@ int pga_best(const double *fitness, const int32_t *labels, int32_t P, int32_t N,
  * pga_timing_read synchronises the recorded events and returns the summed
  * elapsed milliseconds and launch count for kernel id
  *   0 pair-sum FP64, 1 pair-sum BF16x2 MFMA, 2 finish (n_s, c_s, L_c),
- *   3 rank/stats, 4 breed, 5 correlate, 6 split, 7 init. */
+ *   3 rank/stats, 4 breed, 5 correlate, 6 split, 7 init, 8 SUS ranks and
+ *   weights, 9 EWMA correlation. */
 int pga_timing_enable(int on);
 int pga_timing_reset(void);
 int pga_timing_read(int kernel_id, double *total_ms, int64_t *count);

@@ -7,6 +7,8 @@
 //               [-1, 1], zero-variance stocks get 0 off the diagonal
 //   split     : hi = bf16(C), lo = bf16(C - hi), round to nearest even from
 //               FP64, zero padding up to the 32-aligned leading dimension
+//   ewma      : online exponentially weighted correlation with the market
+//               mode removed (pre-processing step before the path)
 #include "pga_internal.hpp"
 
 #include <math.h>
@@ -53,19 +55,15 @@ hipError_t launch_row_stats(const double *R, int N, int T, int64_t ld, double *m
 }
 
 // 64 x 64 output tile per workgroup; thread (tx, ty) owns rows i0 + 4ty..+3
-// and columns j0 + 4tx..+3. K loop over t in chunks of 16 through LDS.
+// and columns j0 + 4tx..+3. K loop over t in chunks of 16 through LDS;
+// x(g, t) gives the (already centred or weighted) value of row g at time t.
 constexpr int kCT = 64, kCK = 16;
 
-__global__ __launch_bounds__(256) void k_corr(const double *R, int N, int T, int64_t ld,
-                                              const double *mu, const double *ss, double *C) {
+template <class X>
+__device__ __forceinline__ void gram_tile(X x, int N, int T, int i0, int j0, double (&acc)[4][4]) {
     __shared__ double As[kCK][kCT + 1];
     __shared__ double Bs[kCK][kCT + 1];
-    const int ti = blockIdx.y, tj = blockIdx.x;
-    if (ti > tj) return;
-    const int i0 = ti * kCT, j0 = tj * kCT;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-
-    double acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -78,8 +76,8 @@ __global__ __launch_bounds__(256) void k_corr(const double *R, int N, int T, int
             const int r = idx >> 4, kk = idx & 15;
             const int t = t0 + kk;
             const int gi = i0 + r, gj = j0 + r;
-            As[kk][r] = (gi < N && t < T) ? R[(size_t)gi * ld + t] - mu[gi] : 0.0;
-            Bs[kk][r] = (gj < N && t < T) ? R[(size_t)gj * ld + t] - mu[gj] : 0.0;
+            As[kk][r] = (gi < N && t < T) ? x(gi, t) : 0.0;
+            Bs[kk][r] = (gj < N && t < T) ? x(gj, t) : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -91,12 +89,22 @@ __global__ __launch_bounds__(256) void k_corr(const double *R, int N, int T, int
                 b[q] = Bs[kk][4 * tx + q];
             }
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void k_corr(const double *R, int N, int T, int64_t ld,
+                                              const double *mu, const double *ss, double *C) {
+    const int ti = blockIdx.y, tj = blockIdx.x;
+    if (ti > tj) return;
+    const int i0 = ti * kCT, j0 = tj * kCT;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4];
+    gram_tile([&](int g, int t) { return R[(size_t)g * ld + t] - mu[g]; }, N, T, i0, j0, acc);
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
         const int i = i0 + 4 * ty + x;
@@ -168,6 +176,80 @@ hipError_t launch_split(const double *C, int N, uint16_t *hi, uint16_t *lo, hipS
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_split, dim3(blocks), dim3(256), 0, s, C, N, ld, hi, lo);
+    return hipGetLastError();
+}
+
+// ---- online EWMA correlation (Section 4.2.4 pre-processing) ------------------
+// The recursion S <- lambda S + (1 - lambda) x_t x_t^T over t = 0 .. T-1 is
+// S <- lambda^T S + sum_t w_t x_t x_t^T with w_t = (1 - lambda) lambda^(T-1-t):
+//   prep : x_it = sqrt(w_t) (R_it - m_t), m_t the equal-weight market return
+//          (sum over i in ascending order, / N) or 0; one thread per t;
+//   gram : S_ij <- lambda^T S_ij + sum_t x_it x_jt on the 64 x 64 tiles of
+//          the upper triangle (same FP64 tile as the correlation), mirrored;
+//   norm : C_ij = S_ij / sqrt(S_ii S_jj), clamp, C_ii = 1, zero variance -> 0.
+__global__ __launch_bounds__(256) void k_ewma_prep(const double *R, int N, int T, int64_t ld, double lam,
+                                                   int market, double *X) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= T) return;
+    double m = 0.0;
+    if (market) {
+        for (int i = 0; i < N; ++i) m += R[(size_t)i * ld + t];
+        m /= (double)N;
+    }
+    const double sw = sqrt((1.0 - lam) * pow(lam, (double)(T - 1 - t)));
+    for (int i = 0; i < N; ++i) X[(size_t)i * T + t] = sw * (R[(size_t)i * ld + t] - m);
+}
+
+__global__ __launch_bounds__(256) void k_ewma_gram(const double *X, int N, int T, double decay, int reset,
+                                                   double *S) {
+    const int ti = blockIdx.y, tj = blockIdx.x;
+    if (ti > tj) return;
+    const int i0 = ti * kCT, j0 = tj * kCT;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4];
+    gram_tile([&](int g, int t) { return X[(size_t)g * T + t]; }, N, T, i0, j0, acc);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        const int i = i0 + 4 * ty + x;
+        if (i >= N) continue;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int j = j0 + 4 * tx + y;
+            if (j >= N || j < i) continue;
+            const double v = reset ? acc[x][y] : fma(decay, S[(size_t)i * N + j], acc[x][y]);
+            S[(size_t)i * N + j] = v;
+            S[(size_t)j * N + i] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ewma_norm(const double *S, int N, double *C, int32_t *status) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    const int i = (int)(e / N), j = (int)(e - (int64_t)i * N);
+    const double a = S[(size_t)i * N + i], b = S[(size_t)j * N + j];
+    double v;
+    if (i == j) {
+        v = 1.0;
+        if (a == 0.0 && status) atomicAdd(&status[PGA_ST_ZEROVAR], 1);
+    } else if (a == 0.0 || b == 0.0) {
+        v = 0.0;
+    } else {
+        v = fmin(1.0, fmax(-1.0, S[(size_t)i * N + j] / sqrt(a * b)));
+    }
+    C[e] = v;
+}
+
+hipError_t launch_ewma(const double *R, int N, int T, int64_t ld, double lam, int reset, int market, double *S,
+                       double *C, double *X, int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_ewma_prep, dim3((T + 255) / 256), dim3(256), 0, s, R, N, T, ld, lam, market, X);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nt = (N + kCT - 1) / kCT;
+    hipLaunchKernelGGL(k_ewma_gram, dim3(nt, nt), dim3(256), 0, s, X, N, T, pow(lam, (double)T), reset, S);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t nn = (int64_t)N * N;
+    hipLaunchKernelGGL(k_ewma_norm, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, S, N, C, status);
     return hipGetLastError();
 }
 

@@ -21,60 +21,158 @@ namespace pga {
 // tables travel as kernel arguments, so no host buffer has to outlive the call.
 struct DescBlob {
     InstDesc d;
-    int32_t prefix[6];   // {0, fp64 tiles}, {0, mfma tiles}, {0, P}
+    int32_t prefix[4];   // {0, tiles}, {0, P}
 };
 
 __global__ void k_write_desc(DescBlob b, InstDesc *dst, int32_t *prefix) {
     if (threadIdx.x == 0) *dst = b.d;
-    if (threadIdx.x < 6) prefix[threadIdx.x] = b.prefix[threadIdx.x];
+    if (threadIdx.x < 4) prefix[threadIdx.x] = b.prefix[threadIdx.x];
 }
 
-hipError_t launch_write_desc(const InstDesc &d, InstDesc *dst, int32_t *prefix, hipStream_t s) {
+hipError_t launch_write_desc(const InstDesc &d, int32_t tiles, InstDesc *dst, int32_t *prefix, hipStream_t s) {
     DescBlob b;
     b.d = d;
     b.prefix[0] = 0;
-    b.prefix[1] = fp64_tiles(d.N, d.P);
+    b.prefix[1] = tiles;
     b.prefix[2] = 0;
-    b.prefix[3] = mfma_tiles(d.N, d.P);
-    b.prefix[4] = 0;
-    b.prefix[5] = d.P;
+    b.prefix[3] = d.P;
     hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, s, b, dst, prefix);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// FP64 pair-sum. One workgroup = 64 consecutive stocks j (one per lane) x 64
-// individuals (16 per wave); the four waves are independent (no workgroup
-// barrier). Each lane keeps its 16 labels s_pj and 16 FP64 accumulators in
+// FP64 pair-sum. One workgroup = 64 consecutive stocks j (one per lane) x 4B
+// individuals (B = 8 or 16 per wave); the four waves are independent (no
+// workgroup barrier). Each lane keeps its B labels s_pj and B FP64 accumulators in
 // registers and walks the rows i < j of its column in chunks of 64 rows:
 //   - C_ij is loaded once per (wave, row), coalesced across the wave, and
-//     reused by 16 individuals; loads run one group of 4 rows ahead;
-//   - the row labels s_pi of the wave's 16 individuals are staged per chunk in
+//     reused by B individuals; loads run one group of 4 rows ahead;
+//   - the row labels s_pi of the wave's B individuals are staged per chunk in
 //     a wave-private LDS buffer (transposed, so one 16-byte broadcast read
 //     serves 4 individuals), double-buffered: the next chunk's labels are
 //     fetched into registers while the current chunk is processed.
-// Per (pair, individual): compare, select 1.0/0.0, FMA. Rows i >= j and rows
+// Per (pair, individual): compare, masked FP64 add. Rows i >= j and rows
 // past N contribute C = 0, so every chunk runs all 64 rows without branches.
+// acc[b] += c on the lanes where row label r[b] equals lj[b], for the 8 or 16
+// individuals of a wave: each compare writes a lane mask to an SGPR pair, the
+// scalar unit narrows EXEC to it, and the FP64 add runs under that mask. Two
+// vector instructions per (pair, individual); the scalar ones issue alongside
+// other waves' vector work. Masks are made in two groups of 8, each group's
+// compares under the full EXEC, which is restored before the block ends.
+__device__ __forceinline__ void add_if_equal8(double *acc, const int *r, const int *lj, double c) {
+    uint64_t m[8], sv;
+    asm volatile(
+        "s_mov_b64 %[sv], exec\n\t"
+        "v_cmp_eq_u32_e64 %[m0], %[r0], %[l0]\n\t"
+        "v_cmp_eq_u32_e64 %[m1], %[r1], %[l1]\n\t"
+        "v_cmp_eq_u32_e64 %[m2], %[r2], %[l2]\n\t"
+        "v_cmp_eq_u32_e64 %[m3], %[r3], %[l3]\n\t"
+        "v_cmp_eq_u32_e64 %[m4], %[r4], %[l4]\n\t"
+        "v_cmp_eq_u32_e64 %[m5], %[r5], %[l5]\n\t"
+        "v_cmp_eq_u32_e64 %[m6], %[r6], %[l6]\n\t"
+        "v_cmp_eq_u32_e64 %[m7], %[r7], %[l7]\n\t"
+        "s_and_b64 exec, %[sv], %[m0]\n\t"
+        "v_add_f64 %[a0], %[a0], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m1]\n\t"
+        "v_add_f64 %[a1], %[a1], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m2]\n\t"
+        "v_add_f64 %[a2], %[a2], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m3]\n\t"
+        "v_add_f64 %[a3], %[a3], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m4]\n\t"
+        "v_add_f64 %[a4], %[a4], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m5]\n\t"
+        "v_add_f64 %[a5], %[a5], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m6]\n\t"
+        "v_add_f64 %[a6], %[a6], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m7]\n\t"
+        "v_add_f64 %[a7], %[a7], %[c]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [a0] "+v"(acc[0]), [a1] "+v"(acc[1]), [a2] "+v"(acc[2]), [a3] "+v"(acc[3]), [a4] "+v"(acc[4]), [a5] "+v"(acc[5]), [a6] "+v"(acc[6]), [a7] "+v"(acc[7]), [m0] "=&s"(m[0]), [m1] "=&s"(m[1]), [m2] "=&s"(m[2]), [m3] "=&s"(m[3]), [m4] "=&s"(m[4]), [m5] "=&s"(m[5]), [m6] "=&s"(m[6]), [m7] "=&s"(m[7]), [sv] "=&s"(sv)
+        : [r0] "v"(r[0]), [r1] "v"(r[1]), [r2] "v"(r[2]), [r3] "v"(r[3]), [r4] "v"(r[4]), [r5] "v"(r[5]), [r6] "v"(r[6]), [r7] "v"(r[7]), [l0] "v"(lj[0]), [l1] "v"(lj[1]), [l2] "v"(lj[2]), [l3] "v"(lj[3]), [l4] "v"(lj[4]), [l5] "v"(lj[5]), [l6] "v"(lj[6]), [l7] "v"(lj[7]), [c] "v"(c)
+        : "scc");
+}
+
+__device__ __forceinline__ void add_if_equal16(double *acc, const int *r, const int *lj, double c) {
+    uint64_t m[8], sv;
+    asm volatile(
+        "s_mov_b64 %[sv], exec\n\t"
+        "v_cmp_eq_u32_e64 %[m0], %[r0], %[l0]\n\t"
+        "v_cmp_eq_u32_e64 %[m1], %[r1], %[l1]\n\t"
+        "v_cmp_eq_u32_e64 %[m2], %[r2], %[l2]\n\t"
+        "v_cmp_eq_u32_e64 %[m3], %[r3], %[l3]\n\t"
+        "v_cmp_eq_u32_e64 %[m4], %[r4], %[l4]\n\t"
+        "v_cmp_eq_u32_e64 %[m5], %[r5], %[l5]\n\t"
+        "v_cmp_eq_u32_e64 %[m6], %[r6], %[l6]\n\t"
+        "v_cmp_eq_u32_e64 %[m7], %[r7], %[l7]\n\t"
+        "s_and_b64 exec, %[sv], %[m0]\n\t"
+        "v_add_f64 %[a0], %[a0], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m1]\n\t"
+        "v_add_f64 %[a1], %[a1], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m2]\n\t"
+        "v_add_f64 %[a2], %[a2], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m3]\n\t"
+        "v_add_f64 %[a3], %[a3], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m4]\n\t"
+        "v_add_f64 %[a4], %[a4], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m5]\n\t"
+        "v_add_f64 %[a5], %[a5], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m6]\n\t"
+        "v_add_f64 %[a6], %[a6], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m7]\n\t"
+        "v_add_f64 %[a7], %[a7], %[c]\n\t"
+        "s_mov_b64 exec, %[sv]\n\t"
+        "v_cmp_eq_u32_e64 %[m0], %[r8], %[l8]\n\t"
+        "v_cmp_eq_u32_e64 %[m1], %[r9], %[l9]\n\t"
+        "v_cmp_eq_u32_e64 %[m2], %[r10], %[l10]\n\t"
+        "v_cmp_eq_u32_e64 %[m3], %[r11], %[l11]\n\t"
+        "v_cmp_eq_u32_e64 %[m4], %[r12], %[l12]\n\t"
+        "v_cmp_eq_u32_e64 %[m5], %[r13], %[l13]\n\t"
+        "v_cmp_eq_u32_e64 %[m6], %[r14], %[l14]\n\t"
+        "v_cmp_eq_u32_e64 %[m7], %[r15], %[l15]\n\t"
+        "s_and_b64 exec, %[sv], %[m0]\n\t"
+        "v_add_f64 %[a8], %[a8], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m1]\n\t"
+        "v_add_f64 %[a9], %[a9], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m2]\n\t"
+        "v_add_f64 %[a10], %[a10], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m3]\n\t"
+        "v_add_f64 %[a11], %[a11], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m4]\n\t"
+        "v_add_f64 %[a12], %[a12], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m5]\n\t"
+        "v_add_f64 %[a13], %[a13], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m6]\n\t"
+        "v_add_f64 %[a14], %[a14], %[c]\n\t"
+        "s_and_b64 exec, %[sv], %[m7]\n\t"
+        "v_add_f64 %[a15], %[a15], %[c]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [a0] "+v"(acc[0]), [a1] "+v"(acc[1]), [a2] "+v"(acc[2]), [a3] "+v"(acc[3]), [a4] "+v"(acc[4]), [a5] "+v"(acc[5]), [a6] "+v"(acc[6]), [a7] "+v"(acc[7]), [a8] "+v"(acc[8]), [a9] "+v"(acc[9]), [a10] "+v"(acc[10]), [a11] "+v"(acc[11]), [a12] "+v"(acc[12]), [a13] "+v"(acc[13]), [a14] "+v"(acc[14]), [a15] "+v"(acc[15]), [m0] "=&s"(m[0]), [m1] "=&s"(m[1]), [m2] "=&s"(m[2]), [m3] "=&s"(m[3]), [m4] "=&s"(m[4]), [m5] "=&s"(m[5]), [m6] "=&s"(m[6]), [m7] "=&s"(m[7]), [sv] "=&s"(sv)
+        : [r0] "v"(r[0]), [r1] "v"(r[1]), [r2] "v"(r[2]), [r3] "v"(r[3]), [r4] "v"(r[4]), [r5] "v"(r[5]), [r6] "v"(r[6]), [r7] "v"(r[7]), [r8] "v"(r[8]), [r9] "v"(r[9]), [r10] "v"(r[10]), [r11] "v"(r[11]), [r12] "v"(r[12]), [r13] "v"(r[13]), [r14] "v"(r[14]), [r15] "v"(r[15]), [l0] "v"(lj[0]), [l1] "v"(lj[1]), [l2] "v"(lj[2]), [l3] "v"(lj[3]), [l4] "v"(lj[4]), [l5] "v"(lj[5]), [l6] "v"(lj[6]), [l7] "v"(lj[7]), [l8] "v"(lj[8]), [l9] "v"(lj[9]), [l10] "v"(lj[10]), [l11] "v"(lj[11]), [l12] "v"(lj[12]), [l13] "v"(lj[13]), [l14] "v"(lj[14]), [l15] "v"(lj[15]), [c] "v"(c)
+        : "scc");
+}
+
 __device__ __forceinline__ double fp64_c(const double *__restrict__ C, int N, int i, int j) {
     return (i < j && j < N) ? gld(C + (size_t)i * N + j) : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity) {
-    constexpr int B = kFp64B;
+template <int B>
+__global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int xcd) {
     __shared__ int4 lab_s[kFp64Waves][2][64][B / 4];
 
-    const int tile = blockIdx.x;
-    const int k = find_inst(t.tiles_fp64, t.n_inst, tile);
+    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int k = find_inst(t.tiles, t.n_inst, tile);
     const InstDesc &d = t.desc[k];
+    if (inst_stopped(d)) return;
     const int N = d.N, P = d.P;
-    const int local = tile - t.tiles_fp64[k];
+    const int local = tile - t.tiles[k];
     const int n_jb = (N + kFp64Cols - 1) / kFp64Cols;
     const int n_pairs = (n_jb + 1) / 2;
     const int jp = local % n_pairs;
     const int pb = local / n_pairs;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, kept scalar
     const int lane = threadIdx.x & 63;
-    const int pbase = pb * kFp64Inds + wave * B;
+    const int pbase = pb * (kFp64Waves * B) + wave * B;
     const int32_t *__restrict__ labels = d.pop[parity];
     const double *__restrict__ C = d.C;
 
@@ -138,14 +236,17 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const double c = cur[q];
+                    int rl[B];
 #pragma unroll
                     for (int u = 0; u < B / 4; ++u) {
-                        const int4 rl = lab_s[wave][buf][r + q][u];
-                        acc[4 * u + 0] = fma(rl.x == lj[4 * u + 0] ? 1.0 : 0.0, c, acc[4 * u + 0]);
-                        acc[4 * u + 1] = fma(rl.y == lj[4 * u + 1] ? 1.0 : 0.0, c, acc[4 * u + 1]);
-                        acc[4 * u + 2] = fma(rl.z == lj[4 * u + 2] ? 1.0 : 0.0, c, acc[4 * u + 2]);
-                        acc[4 * u + 3] = fma(rl.w == lj[4 * u + 3] ? 1.0 : 0.0, c, acc[4 * u + 3]);
+                        const int4 v = lab_s[wave][buf][r + q][u];
+                        rl[4 * u + 0] = v.x;
+                        rl[4 * u + 1] = v.y;
+                        rl[4 * u + 2] = v.z;
+                        rl[4 * u + 3] = v.w;
                     }
+                    if constexpr (B == 16) add_if_equal16(acc, rl, lj, c);
+                    else add_if_equal8(acc, rl, lj, c);
                 }
             }
             if (ch + 1 < nchunks) store_labels(buf ^ 1, nxt);
@@ -161,9 +262,14 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity) {
     }
 }
 
-hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, hipStream_t s) {
+hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, const Variant &v, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pairsum_fp64, dim3(total_tiles), dim3(256), 0, s, t, parity);
+    if (v.ipg == 16)
+        hipLaunchKernelGGL(k_pairsum_fp64<16>, dim3(total_tiles), dim3(256), 0, s, t, parity, v.xcd);
+    else if (v.ipg == 8)
+        hipLaunchKernelGGL(k_pairsum_fp64<8>, dim3(total_tiles), dim3(256), 0, s, t, parity, v.xcd);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -188,15 +294,22 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Per-wave LDS region of the finish kernel: csum (int64) then cnt (int32), each
-// padded to 16 bytes so every region and both arrays stay 16-byte aligned
-// (64-bit LDS atomics need naturally aligned addresses).
+// Per-wave LDS region of the finish kernel: csum (int64), cnt (int32) and the
+// list of non-singleton labels (int32). Each array is padded to 16 bytes, so
+// every region and every array in it starts 16-byte aligned (64-bit LDS
+// atomics need naturally aligned addresses).
 __host__ __device__ __forceinline__ size_t finish_csum_bytes(int max_n) {
     return ((size_t)max_n * sizeof(long long) + 15) / 16 * 16;
 }
-__host__ __device__ __forceinline__ size_t finish_wave_bytes(int max_n) {
-    return finish_csum_bytes(max_n) + ((size_t)max_n * sizeof(int) + 15) / 16 * 16;
+__host__ __device__ __forceinline__ size_t finish_cnt_bytes(int max_n) {
+    return ((size_t)max_n * sizeof(int) + 15) / 16 * 16;
 }
+__host__ __device__ __forceinline__ size_t finish_wave_bytes(int max_n) {
+    // csum, cnt, and the list of labels with n_s > 1 (at most max_n / 2 of them)
+    return finish_csum_bytes(max_n) + finish_cnt_bytes(max_n) + ((size_t)(max_n / 2 + 1) * sizeof(int) + 15) / 16 * 16;
+}
+
+constexpr int kFinCache = 16;
 
 __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int max_n, int parity,
                                                 int32_t *status) {
@@ -206,6 +319,7 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
     if (g >= total_inds) return;                     // whole wave leaves; no workgroup barrier below
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
+    if (inst_stopped(d)) return;
     const int N = d.N;
     const int p = g - t.inds[k];
     const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
@@ -213,10 +327,27 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
     unsigned char *base = smem + (size_t)wave * finish_wave_bytes(max_n);
     long long *csum = (long long *)base;
     int *cnt = (int *)(base + finish_csum_bytes(max_n));
+    int *lst = (int *)(base + finish_csum_bytes(max_n) + finish_cnt_bytes(max_n));
 
+    // The first kFinCache * 64 labels and values stay in registers (all loads issued
+    // together); stocks beyond that are read again in the accumulation pass.
+    int lr[kFinCache];
+    double vr[kFinCache];
+#pragma unroll
+    for (int u = 0; u < kFinCache; ++u) {
+        const int j = lane + 64 * u;
+        lr[u] = j < N ? gld(lab + j) : 0;
+        vr[u] = j < N ? gld(v + j) : 0.0;
+    }
     int bad = 0;
     double mx = 0.0;
-    for (int j = lane; j < N; j += 64) {
+#pragma unroll
+    for (int u = 0; u < kFinCache; ++u) {
+        if (lr[u] < 0 || lr[u] >= N) bad |= 1;
+        if (!isfinite(vr[u])) bad |= 2;
+        else mx = fmax(mx, fabs(vr[u]));
+    }
+    for (int j = lane + 64 * kFinCache; j < N; j += 64) {
         const int l = gld(lab + j);
         if (l < 0 || l >= N) bad |= 1;
         const double x = gld(v + j);
@@ -255,7 +386,14 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int j = lane; j < N; j += 64) {
+#pragma unroll
+    for (int u = 0; u < kFinCache; ++u) {
+        if (lane + 64 * u < N) {
+            atomicAdd(&cnt[lr[u]], 1);
+            atomicAdd((unsigned long long *)&csum[lr[u]], (unsigned long long)llrint(ldexp(vr[u], sc)));
+        }
+    }
+    for (int j = lane + 64 * kFinCache; j < N; j += 64) {
         const int l = gld(lab + j);
         const long long q = llrint(ldexp(gld(v + j), sc));
         atomicAdd(&cnt[l], 1);
@@ -265,21 +403,37 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+    // Pass A: per-label outputs, and the labels with n_s > 1 compacted in ascending order
+    // (wave ballot + prefix), so the log terms below run with every lane busy.
+    int nlist = 0;
+    for (int s0 = 0; s0 < N; s0 += 64) {
+        const int s = s0 + lane;
+        const int n = s < N ? cnt[s] : 0;
+        if (s < N) {
+            if (d.n_s_out) gst(d.n_s_out + (size_t)p * N + s, n);
+            if (d.c_s_out) gst(d.c_s_out + (size_t)p * N + s, ldexp((double)csum[s], -sc));
+        }
+        const uint64_t m = __ballot(n > 1);
+        if (n > 1) lst[nlist + __popcll(m & ((1ull << lane) - 1ull))] = s;
+        nlist += __popcll(m);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // Pass B: the two FP64 log terms of Eq. 8 for each listed cluster; per-lane sums in list
+    // order, then a butterfly over the wave (a fixed order).
     double L = 0.0;
     int nbad = 0;
-    for (int s = lane; s < N; s += 64) {
-        const int n = cnt[s];
+    for (int m = lane; m < nlist; m += 64) {
+        const int s = lst[m];
+        const double nd = (double)cnt[s];
         const double c = ldexp((double)csum[s], -sc);
-        if (d.n_s_out) gst(d.n_s_out + (size_t)p * N + s, n);
-        if (d.c_s_out) gst(d.c_s_out + (size_t)p * N + s, c);
-        if (n > 1) {
-            const double nd = (double)n;
-            const double n2 = nd * nd;
-            if (!(c > 0.0 && c < n2)) {
-                nbad += 1;
-            } else {
-                L += log(nd / c) + (nd - 1.0) * log((n2 - nd) / (n2 - c));
-            }
+        const double n2 = nd * nd;
+        if (!(c > 0.0 && c < n2)) {
+            nbad += 1;
+        } else {
+            L += log(nd / c) + (nd - 1.0) * log((n2 - nd) / (n2 - c));
         }
     }
     const double Ltot = wave_sum(L);

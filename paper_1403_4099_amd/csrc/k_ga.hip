@@ -23,6 +23,12 @@ __global__ __launch_bounds__(256) void k_init(Tables t) {
     const InstDesc &d = t.desc[k];
     const int N = d.N;
     const int p = g - t.inds[k];
+    if (p == 0 && threadIdx.x == 0 && d.term) {
+        pga_term_state z;
+        z.ref = -INFINITY;
+        z.stall = z.stopped = z.gens = z.call_gens = 0;
+        *d.term = z;
+    }
     int32_t *__restrict__ row = d.pop[0] + (size_t)p * N;
     const int nq = (N + 3) >> 2;
     for (int q = threadIdx.x; q < nq; q += 256) {
@@ -74,54 +80,141 @@ __device__ Cand block_best(Cand c, double *rf, int *ri) {
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_rank(Tables t, int gen_off) {
-    __shared__ double rf[256];
-    __shared__ int ri[256];
+// Wave butterflies: the comparison is a total order and the sums run in a fixed
+// pattern, so every lane ends with the same, reproducible value.
+__device__ __forceinline__ Cand wave_best(Cand c) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        const double fo = __shfl_xor(c.f, m, 64);
+        const int io = __shfl_xor(c.i, m, 64);
+        if (io >= 0 && (c.i < 0 || ranks_before(fo, io, c.f, c.i))) c = Cand{fo, io};
+    }
+    return c;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// 16 waves; each thread keeps up to kRankCache of its fitness values in registers
+// (all loads issued at once), so the E selection rounds and the statistics pass
+// cost one memory latency; values past 16 * 64 * kRankCache are re-read.
+constexpr int kRankThreads = 1024;
+constexpr int kRankWaves = kRankThreads / 64;
+constexpr int kRankCache = 8;
+
+__global__ __launch_bounds__(kRankThreads) void k_rank(Tables t, int gen_off, int final) {
+    __shared__ double wf[kRankWaves];
+    __shared__ int wi[kRankWaves];
     const InstDesc &d = t.desc[blockIdx.x];
+    if (d.term) {
+        const bool stopped = inst_stopped(d);
+        __syncthreads();                                   // every thread has read the flag
+        if (gen_off == 0 && threadIdx.x == 0) gst(&d.term->call_gens, 0);
+        if (stopped) return;
+    }
     const int P = d.P, E = d.E;
     const double *__restrict__ f = d.fitness;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (d.selection == PGA_SELECT_SUS)                     // the SUS rank kernel adds into these
+        for (int p = threadIdx.x; p < P; p += kRankThreads) gst(d.sus_rank + p, 1);
+
+    double fr[kRankCache];
+#pragma unroll
+    for (int v = 0; v < kRankCache; ++v) {
+        const int p = threadIdx.x + v * kRankThreads;
+        fr[v] = p < P ? gld(f + p) : -INFINITY;
+    }
+
+    auto block_best = [&](Cand c) -> Cand {
+        c = wave_best(c);
+        if (lane == 0) {
+            wf[wave] = c.f;
+            wi[wave] = c.i;
+        }
+        __syncthreads();
+        Cand b{0.0, -1};
+        for (int w = 0; w < kRankWaves; ++w)
+            if (wi[w] >= 0 && (b.i < 0 || ranks_before(wf[w], wi[w], b.f, b.i))) b = Cand{wf[w], wi[w]};
+        __syncthreads();
+        return b;
+    };
+    auto block_sum = [&](double v) -> double {
+        v = wave_sum_d(v);
+        if (lane == 0) wf[wave] = v;
+        __syncthreads();
+        double r = 0.0;
+        for (int w = 0; w < kRankWaves; ++w) r += wf[w];
+        __syncthreads();
+        return r;
+    };
+    // Best candidate of this thread ranked after prev (prev.i < 0: no bound).
+    auto thread_best = [&](Cand prev) -> Cand {
+        Cand c{0.0, -1};
+#pragma unroll
+        for (int v = 0; v < kRankCache; ++v) {
+            const int p = threadIdx.x + v * kRankThreads;
+            if (p >= P) break;
+            if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fr[v], p)) continue;
+            if (c.i < 0 || ranks_before(fr[v], p, c.f, c.i)) c = Cand{fr[v], p};
+        }
+        for (int p = threadIdx.x + kRankCache * kRankThreads; p < P; p += kRankThreads) {
+            const double fp = gld(f + p);
+            if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fp, p)) continue;
+            if (c.i < 0 || ranks_before(fp, p, c.f, c.i)) c = Cand{fp, p};
+        }
+        return c;
+    };
 
     Cand prev{0.0, -1};
     int argbest = 0;
     const int rounds = E > 1 ? E : 1;
     for (int r = 0; r < rounds; ++r) {
-        Cand c{0.0, -1};
-        for (int p = threadIdx.x; p < P; p += 256) {
-            const double fp = f[p];
-            if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fp, p)) continue;
-            if (c.i < 0 || ranks_before(fp, p, c.f, c.i)) c = Cand{fp, p};
-        }
-        const Cand b = block_best(c, rf, ri);
+        const Cand b = block_best(thread_best(prev));
         if (r == 0) argbest = b.i;
         if (r < E && threadIdx.x == 0) d.elite[r] = b.i;
         prev = b;
     }
+    if (d.term && threadIdx.x == 0) {
+        // termination test on this generation's best; count the generation about to be bred
+        pga_term_state st = *d.term;
+        const double b = gld(f + argbest);
+        const bool improved = isfinite(st.ref) ? (b > st.ref + d.tol * fmax(1.0, fabs(st.ref))) : isfinite(b);
+        if (improved) {
+            st.ref = b;
+            st.stall = 0;
+        } else {
+            st.stall += 1;
+        }
+        if (d.stall_gens > 0 && st.stall >= d.stall_gens) st.stopped = 1;
+        if (!final && !st.stopped) {
+            st.gens += 1;
+            st.call_gens += 1;
+        }
+        *d.term = st;
+    }
     if (d.stats) {
         double sum = 0.0, ninv = 0.0;
-        for (int p = threadIdx.x; p < P; p += 256) {
-            const double fp = f[p];
+#pragma unroll
+        for (int v = 0; v < kRankCache; ++v) {
+            const int p = threadIdx.x + v * kRankThreads;
+            if (p >= P) break;
+            if (isfinite(fr[v])) sum += fr[v];
+            else ninv += 1.0;
+        }
+        for (int p = threadIdx.x + kRankCache * kRankThreads; p < P; p += kRankThreads) {
+            const double fp = gld(f + p);
             if (isfinite(fp)) sum += fp;
             else ninv += 1.0;
         }
-        rf[threadIdx.x] = sum;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) rf[threadIdx.x] += rf[threadIdx.x + w];
-            __syncthreads();
-        }
-        const double total = rf[0];
-        __syncthreads();
-        rf[threadIdx.x] = ninv;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) rf[threadIdx.x] += rf[threadIdx.x + w];
-            __syncthreads();
-        }
-        const double inv = rf[0];
+        const double total = block_sum(sum);
+        const double inv = block_sum(ninv);
         if (threadIdx.x == 0) {
             double *row = d.stats + 4 * (size_t)gen_off;
             const double nfin = (double)P - inv;
-            row[0] = f[argbest];
+            row[0] = gld(f + argbest);
             row[1] = nfin > 0.0 ? total / nfin : -INFINITY;
             row[2] = inv;
             row[3] = (double)argbest;
@@ -129,8 +222,8 @@ __global__ __launch_bounds__(256) void k_rank(Tables t, int gen_off) {
     }
 }
 
-hipError_t launch_rank(Tables t, int gen_off, hipStream_t s) {
-    hipLaunchKernelGGL(k_rank, dim3(t.n_inst), dim3(256), 0, s, t, gen_off);
+hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s) {
+    hipLaunchKernelGGL(k_rank, dim3(t.n_inst), dim3(kRankThreads), 0, s, t, gen_off, final);
     return hipGetLastError();
 }
 
@@ -151,10 +244,121 @@ __device__ __forceinline__ int tournament2(const double *f, int a, int b) {
     return ranks_before(fa, a, fb, b) ? a : b;
 }
 
+// ---------------------------------------------------------------------------
+// Stochastic universal sampling after rank scaling (PGA_SELECT_SUS).
+//   k_sus_rank:   rank_p = 1 + #{q : q ranks before p}; workgroup (x, y, inst)
+//                 compares individuals [256x, 256x + 256) with [256y, 256y + 256)
+//                 and adds its integer counts atomically (exact, order-free);
+//   k_sus_prefix: weight floor(sqrt(floor(2^48 / rank))) (0 for -inf, 1 for all
+//                 when every fitness is -inf) and the inclusive prefix over the
+//                 individuals in index order, in 64-bit integers;
+//   k_breed:      pointer k at floor((u + k W) / n) picks the individual whose
+//                 segment holds it; child E + j uses pointers pi(2j), pi(2j+1).
+__global__ __launch_bounds__(256) void k_sus_rank(Tables t) {
+    __shared__ double fq[256];
+    const InstDesc &d = t.desc[blockIdx.z];
+    if (d.selection != PGA_SELECT_SUS || inst_stopped(d)) return;
+    const int P = d.P;
+    const int p0 = blockIdx.x * 256, q0 = blockIdx.y * 256;
+    if (p0 >= P || q0 >= P) return;                          // uniform over the workgroup
+    const int p = p0 + threadIdx.x, q = q0 + threadIdx.x;
+    fq[threadIdx.x] = q < P ? gld(d.fitness + q) : 0.0;
+    __syncthreads();
+    if (p >= P) return;
+    const double fp = gld(d.fitness + p);
+    const int nq = min(256, P - q0);
+    int cnt = 0;
+    for (int r = 0; r < nq; ++r) cnt += ranks_before(fq[r], q0 + r, fp, p) ? 1 : 0;
+    if (cnt) atomicAdd(d.sus_rank + p, cnt);
+}
+
+__device__ __forceinline__ uint64_t isqrt_u48(uint64_t x) {
+    uint64_t y = (uint64_t)sqrt((double)x);                 // within one of the exact root
+    while (y * y > x) --y;
+    while ((y + 1) * (y + 1) <= x) ++y;
+    return y;
+}
+
+__global__ __launch_bounds__(1024) void k_sus_prefix(Tables t) {
+    __shared__ uint64_t wsum[16];
+    __shared__ uint64_t carry_s;
+    const InstDesc &d = t.desc[blockIdx.x];
+    if (d.selection != PGA_SELECT_SUS || inst_stopped(d)) return;
+    const int P = d.P;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int pass = 0; pass < 2; ++pass) {                   // pass 1 only if every weight was 0
+        uint64_t carry = 0;
+        for (int base = 0; base < P; base += 1024) {
+            const int p = base + threadIdx.x;
+            uint64_t w = 0;
+            if (p < P) {
+                if (pass == 1) w = 1;
+                else if (isfinite(gld(d.fitness + p)))
+                    w = isqrt_u48(((uint64_t)1 << 48) / (uint64_t)gld(d.sus_rank + p));
+            }
+            uint64_t x = w;                                  // inclusive scan over the wave
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint64_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) wsum[wave] = x;
+            __syncthreads();
+            uint64_t before = carry;
+            for (int v = 0; v < wave; ++v) before += wsum[v];
+            if (p < P) gst(d.sus_cum + p, before + x);
+            if (threadIdx.x == 1023) carry_s = before + x;
+            __syncthreads();
+            carry = carry_s;
+            __syncthreads();
+        }
+        if (carry != 0) break;
+    }
+}
+
+hipError_t launch_sus(Tables t, int max_p, hipStream_t s) {
+    if (t.n_inst <= 0 || max_p <= 0) return hipSuccess;
+    const int nb = (max_p + 255) / 256;
+    hipLaunchKernelGGL(k_sus_rank, dim3(nb, nb, t.n_inst), dim3(256), 0, s, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sus_prefix, dim3(t.n_inst), dim3(1024), 0, s, t);
+    return hipGetLastError();
+}
+
+// Image of x under the Feistel permutation of [0, n) that pairs SUS parents.
+__device__ uint32_t shuffle_index(uint32_t x, uint32_t n, const InstDesc &d, uint32_t gen) {
+    int h = 1;
+    while (((uint64_t)1 << (2 * h)) < (uint64_t)n) ++h;
+    const uint32_t mask = (1u << h) - 1u;
+    do {
+        uint32_t L = x >> h, R = x & mask;
+        for (uint32_t round = 0; round < 4; ++round) {
+            const uint32_t t = R;
+            R = L ^ (draw(R, round, gen, kTagShuf, d.inst_id, d.seed).x & mask);
+            L = t;
+        }
+        x = (L << h) | R;
+    } while (x >= n);
+    return x;
+}
+
+// Individual whose SUS segment holds pointer k (smallest p with cum[p] > pos).
+__device__ int sus_pick(const InstDesc &d, uint32_t k, uint32_t n, uint64_t u, uint64_t W) {
+    const uint64_t pos = (u + (uint64_t)k * W) / (uint64_t)n;
+    int lo = 0, hi = d.P - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (gld(d.sus_cum + mid) > pos) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off) {
     const int g = blockIdx.x;
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
+    if (inst_stopped(d)) return;                           // set by this generation's rank
     const int N = d.N, P = d.P, E = d.E;
     const int c = g - t.inds[k];
     const int32_t *__restrict__ src = d.pop[parity];
@@ -167,9 +371,25 @@ __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off
     }
     const uint32_t gen = d.gen0 + (uint32_t)gen_off;
     const double *__restrict__ f = d.fitness;
-    const U4 sel = draw(0u, (uint32_t)c, gen, kTagSel, d.inst_id, d.seed);
-    const int A = tournament2(f, (int)scale_u32(sel.x, (uint32_t)P), (int)scale_u32(sel.y, (uint32_t)P));
-    const int B = tournament2(f, (int)scale_u32(sel.z, (uint32_t)P), (int)scale_u32(sel.w, (uint32_t)P));
+    int A, B;
+    if (d.selection == PGA_SELECT_SUS) {
+        __shared__ int par_s[2];
+        if (threadIdx.x < 2) {
+            const uint32_t n = 2u * (uint32_t)(P - E);
+            const uint64_t W = gld(d.sus_cum + (P - 1));
+            const uint32_t w0 = draw(0u, 0xFFFFFFFFu, gen, kTagSus, d.inst_id, d.seed).x;
+            const uint64_t u = __umul64hi((uint64_t)w0 << 32, W);          // floor(w0 W / 2^32)
+            const uint32_t k = shuffle_index(2u * (uint32_t)(c - E) + threadIdx.x, n, d, gen);
+            par_s[threadIdx.x] = sus_pick(d, k, n, u, W);
+        }
+        __syncthreads();
+        A = par_s[0];
+        B = par_s[1];
+    } else {
+        const U4 sel = draw(0u, (uint32_t)c, gen, kTagSel, d.inst_id, d.seed);
+        A = tournament2(f, (int)scale_u32(sel.x, (uint32_t)P), (int)scale_u32(sel.y, (uint32_t)P));
+        B = tournament2(f, (int)scale_u32(sel.z, (uint32_t)P), (int)scale_u32(sel.w, (uint32_t)P));
+    }
     const bool cross = draw(0u, (uint32_t)c, gen, kTagXov, d.inst_id, d.seed).x < d.p_cross;
     const int32_t *__restrict__ ra = src + (size_t)A * N;
     const int32_t *__restrict__ rb = src + (size_t)B * N;
@@ -205,12 +425,15 @@ hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, hipSt
     return hipGetLastError();
 }
 
-// After an odd number of generations the population sits in pop[1]; copy it
-// back so the caller always finds the result in the buffer it passed as pop.
-__global__ __launch_bounds__(256) void k_copy_back(Tables t) {
+// After an odd number of bred generations the population sits in pop[1]; copy
+// it back so the caller always finds the result in the buffer it passed as
+// pop. Without a termination test every call breeds G generations.
+__global__ __launch_bounds__(256) void k_copy_back(Tables t, int G) {
     const int g = blockIdx.x;
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
+    const int bred = d.term ? gld(&d.term->call_gens) : G;
+    if ((bred & 1) == 0) return;
     const int N = d.N;
     const int p = g - t.inds[k];
     const int32_t *__restrict__ a = d.pop[1] + (size_t)p * N;
@@ -218,9 +441,9 @@ __global__ __launch_bounds__(256) void k_copy_back(Tables t) {
     for (int j = threadIdx.x; j < N; j += 256) b[j] = a[j];
 }
 
-hipError_t launch_copy_back(Tables t, int total_inds, hipStream_t s) {
+hipError_t launch_copy_back(Tables t, int total_inds, int G, hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_back, dim3(total_inds), dim3(256), 0, s, t);
+    hipLaunchKernelGGL(k_copy_back, dim3(total_inds), dim3(256), 0, s, t, G);
     return hipGetLastError();
 }
 

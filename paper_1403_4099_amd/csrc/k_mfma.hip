@@ -4,19 +4,28 @@
 //
 // One wave owns 16 stocks j = jt0 .. jt0+15 and walks the rows i < j in
 // chunks of 32 with v_mfma_f32_16x16x32_bf16:
-//   A[m][k] = C[jt0 + m][i0 + k]           (hi, then lo: two MFMAs)
-//   B[k][n] = [s_{i0+k} = s_{jt0+n}] [i0 + k < jt0 + n]   (0 or bf16 1.0)
+//   A[m][k] = 2^125 C[jt0 + m][i0 + k]       (hi, then lo: two MFMAs)
+//   B[k][n] = 2^-125 [s_{i0+k} = s_{jt0+n}] [i0 + k < jt0 + n]
 //   D[m][n] += sum_k A[m][k] B[k][n];  D[n][n] = partial sum for stock jt0+n
 // Lane l supplies row m = l%16 of A and column n = l%16 of B over the same
-// eight k = 8(l/16)..+7, so its A row and B column are both stock jt0 + l%16:
-// the lane needs only its own stock's label and the 8 row labels of its k
-// block. The one-hot column costs 3 packed 16-bit ALU ops per 2 rows (xor,
-// saturating 1 - x, multiply by the bf16 pattern of 1.0); the i < j mask is
-// applied only in the chunk that reaches the diagonal. A is loaded once per
-// (wave, chunk), one chunk ahead, and reused by the 16 individuals of the
-// workgroup, whose row labels are staged in LDS once per 1024 rows.
-// FP32 accumulation is flushed into FP64 at every 256-row boundary, so no
-// FP32 partial sum spans more than 256 rows.
+// eight k = 8(l/16)..+7, so its A row and B column are both stock jt0 + l%16.
+//
+// Label codes. A workgroup serves one block of 64 stocks, which carry at most
+// 64 distinct labels. Each such label gets a code (the block position of one
+// stock that has it, 0..63); a row whose label is not among them gets the
+// code kCodeNone. Codes are stored shifted into bits 8..15 of a 16-bit word,
+// so for a row word r and a column word c the saturating difference
+// 0x0100 - (r ^ c) is 0x0100 (the bf16 number 2^-125) when the labels are
+// equal and 0 otherwise: two packed 16-bit ALU ops build two B elements. The
+// 2^-125 is undone by keeping A as the split parts times 2^125 (a workspace
+// copy made once per call); every product is then exactly the split part, as
+// with a one-hot of 1.0.
+//
+// The i < j mask is applied only in the chunk that reaches the diagonal. A is
+// loaded once per (wave, chunk), one chunk ahead, and reused by the B (4, 8
+// or 16) individuals of the workgroup, whose row codes are staged in LDS
+// 8192 / B rows at a time. FP32 accumulation is flushed into FP64 at every 256-row
+// boundary, so no FP32 partial sum spans more than 256 rows.
 #include "pga_internal.hpp"
 
 #include <type_traits>
@@ -27,37 +36,64 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ uint32_t onehot2(uint32_t labs, uint32_t lj2) {
-    const u16x2 x = __builtin_bit_cast(u16x2, labs ^ lj2);
-    const u16x2 one = {1, 1};
-    const u16x2 t = __builtin_elementwise_sub_sat(one, x);   // 1 where equal, else 0
-    const u16x2 bf1 = {0x3F80, 0x3F80};                        // bf16 1.0
-    return __builtin_bit_cast(uint32_t, t * bf1);
+constexpr int kCodeShift = 8;
+constexpr uint16_t kOneHot = 0x0100;        // bf16 2^-125
+constexpr uint8_t kCodeNone = 0xFF;         // row label not present in the column block
+constexpr uint8_t kCodeBadCol = 0xFE;       // column beyond N, beyond P, or label out of range
+
+__device__ __forceinline__ uint32_t onehot2(uint32_t rows2, uint32_t col2) {
+    const u16x2 x = __builtin_bit_cast(u16x2, rows2 ^ col2);
+    const u16x2 one = {kOneHot, kOneHot};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(one, x));
 }
 
+// LDS of one workgroup (dynamic): row codes [B][kMfmaRowCodes / B] (16-bit,
+// shifted), then the label -> code tables [B][cstride] (bytes, cstride >= N).
+struct MfmaLds {
+    uint16_t *rows;
+    uint8_t *code;
+    int cstride;
+};
+
 // One column block jb (64 stocks, 16 per wave) for the B individuals of batch pb.
-__device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, int parity,
-                                           uint16_t (*lab_s)[kMfmaRowChunk]) {
-    constexpr int B = kMfmaB;
-    constexpr int RC = kMfmaRowChunk;
+// On entry every code table entry below N holds kCodeNone; it is restored on exit.
+template <int B>
+__device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, int parity, const MfmaLds &s) {
+    constexpr int RC = kMfmaRowCodes / B;                     // rows staged per pass
     const int N = d.N, P = d.P, ld = d.ld_h;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, kept scalar
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
+    const int q = 16 * wave + n;                              // position of this lane's stock in the block
     const int jt0 = jb * kMfmaCols + 16 * wave;
     const int j = jt0 + n;
     const int pbase = pb * B;
     const int32_t *__restrict__ labels = d.pop[parity];
-    const uint16_t *__restrict__ hi = d.hi;
-    const uint16_t *__restrict__ lo = d.lo;
+    const uint16_t *__restrict__ hs = d.hs;
+    const uint16_t *__restrict__ ls = d.ls;
+    auto code = [&](int b, int l) -> uint8_t & { return s.code[(size_t)b * s.cstride + l]; };
+    auto rowc = [&](int b, int r) -> uint16_t * { return s.rows + (size_t)b * RC + r; };
 
-    uint32_t lj2[B];
+    // Column labels; lanes with g == 0 register them in the code table.
+    int32_t lj[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int p = pbase + b;
-        const uint32_t l = (j < N && p < P) ? (uint32_t)gld(labels + (size_t)p * N + j) & 0xFFFFu : 0xFFFEu;
-        lj2[b] = l | (l << 16);
+        lj[b] = (j < N && p < P) ? gld(labels + (size_t)p * N + j) : -1;
     }
+    if (g == 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if ((uint32_t)lj[b] < (uint32_t)N) code(b, lj[b]) = (uint8_t)q;
+    }
+    __syncthreads();
+    uint32_t col2[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint32_t c = (uint32_t)lj[b] < (uint32_t)N ? (uint32_t)code(b, lj[b]) : kCodeBadCol;
+        col2[b] = (c << kCodeShift) | (c << (16 + kCodeShift));
+    }
+
     floatx4 acc[B];
     double acc64[B];
 #pragma unroll
@@ -76,13 +112,11 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
             acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
     };
+    // Only waves with jt0 < N load A, and then j < ld for every lane (ld is a
+    // multiple of 32 and jt0 a multiple of 16), so the loads need no guard.
     auto load_a = [&](int i0, uint4 &ah, uint4 &al) {
-        ah = make_uint4(0, 0, 0, 0);
-        al = make_uint4(0, 0, 0, 0);
-        if (j < ld) {
-            ah = gld_u4(hi + (size_t)j * ld + i0 + 8 * g);
-            al = gld_u4(lo + (size_t)j * ld + i0 + 8 * g);
-        }
+        ah = gld_u4(hs + (size_t)j * ld + i0 + 8 * g);
+        al = gld_u4(ls + (size_t)j * ld + i0 + 8 * g);
     };
     auto chunk = [&](auto masked_tag, int i0, int c0, uint4 ah, uint4 al) {
         constexpr bool masked = decltype(masked_tag)::value;
@@ -90,24 +124,24 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         uint32_t m[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
         if constexpr (masked) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                m[q] = ((ik + 2 * q < j) ? 0xFFFFu : 0u) | ((ik + 2 * q + 1 < j) ? 0xFFFF0000u : 0u);
+            for (int r = 0; r < 4; ++r)
+                m[r] = ((ik + 2 * r < j) ? 0xFFFFu : 0u) | ((ik + 2 * r + 1 < j) ? 0xFFFF0000u : 0u);
         }
         const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah);
         const bf16x8 Al = __builtin_bit_cast(bf16x8, al);
 #pragma unroll
         for (int b = 0; b < B; b += 2) {
-            const uint4 l0 = *(const uint4 *)&lab_s[b][ik - c0];
-            const uint4 l1 = *(const uint4 *)&lab_s[b + 1][ik - c0];
+            const uint4 l0 = *(const uint4 *)rowc(b, ik - c0);
+            const uint4 l1 = *(const uint4 *)rowc(b + 1, ik - c0);
             uint4 v0, v1;
-            v0.x = onehot2(l0.x, lj2[b]);
-            v0.y = onehot2(l0.y, lj2[b]);
-            v0.z = onehot2(l0.z, lj2[b]);
-            v0.w = onehot2(l0.w, lj2[b]);
-            v1.x = onehot2(l1.x, lj2[b + 1]);
-            v1.y = onehot2(l1.y, lj2[b + 1]);
-            v1.z = onehot2(l1.z, lj2[b + 1]);
-            v1.w = onehot2(l1.w, lj2[b + 1]);
+            v0.x = onehot2(l0.x, col2[b]);
+            v0.y = onehot2(l0.y, col2[b]);
+            v0.z = onehot2(l0.z, col2[b]);
+            v0.w = onehot2(l0.w, col2[b]);
+            v1.x = onehot2(l1.x, col2[b + 1]);
+            v1.y = onehot2(l1.y, col2[b + 1]);
+            v1.z = onehot2(l1.z, col2[b + 1]);
+            v1.w = onehot2(l1.w, col2[b + 1]);
             if constexpr (masked) {
                 v0.x &= m[0]; v0.y &= m[1]; v0.z &= m[2]; v0.w &= m[3];
                 v1.x &= m[0]; v1.y &= m[1]; v1.z &= m[2]; v1.w &= m[3];
@@ -121,6 +155,25 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         }
         if (((i0 + 32) % kMfmaFlushRows) == 0) flush();
     };
+    // Chunks [i0, end) of one kind, two per iteration so the prefetch ping-pongs
+    // between (ah, al) and (nh, nl) without register copies; on return the next
+    // chunk's A (if any, below cend) is in (ah, al).
+    auto run = [&](auto masked_tag, int &i0, int end, int cend, int c0, uint4 &ah, uint4 &al) {
+        uint4 nh, nl;
+        while (i0 < end) {
+            if (i0 + 32 < cend) load_a(i0 + 32, nh, nl);
+            chunk(masked_tag, i0, c0, ah, al);
+            i0 += 32;
+            if (i0 >= end) {
+                ah = nh;
+                al = nl;
+                return;
+            }
+            if (i0 + 32 < cend) load_a(i0 + 32, ah, al);
+            chunk(masked_tag, i0, c0, nh, nl);
+            i0 += 32;
+        }
+    };
 
     const int wg_iend = min(jb * kMfmaCols + kMfmaCols, N);   // rows any wave of the group needs
     const int my_iend = jt0 < N ? min(jt0 + 16, N) : 0;       // rows this wave needs (i < j <= jt0+15)
@@ -128,30 +181,45 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
 
     for (int c0 = 0; c0 < wg_iend; c0 += RC) {
         const int rows = min(RC, wg_iend - c0);
-        for (int e = threadIdx.x; e < B * RC; e += 256) {
-            const int b = e / RC, r = e % RC;
-            const int i = c0 + r, p = pbase + b;
-            lab_s[b][r] = (r < rows && p < P) ? (uint16_t)gld(labels + (size_t)p * N + i) : (uint16_t)0xFFFFu;
+        const int rows32 = (rows + 31) & ~31;                 // chunks read whole 32-row groups
+        // Thread t stages rows t + 256k of every individual: all RK * B labels are
+        // loaded before the first table lookup, so the pass costs one memory latency.
+        constexpr int RK = RC / 256;
+        int32_t lab[RK][B];
+#pragma unroll
+        for (int k = 0; k < RK; ++k) {
+            const int r = threadIdx.x + 256 * k;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int p = pbase + b;
+                lab[k][b] = (r < rows && p < P) ? gld(labels + (size_t)p * N + c0 + r) : -1;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RK; ++k)                          // all table reads (index clamped, in range), then all writes
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const bool ok = (uint32_t)lab[k][b] < (uint32_t)N;
+                const int32_t c = code(b, ok ? lab[k][b] : 0);
+                lab[k][b] = ok ? c : (int32_t)kCodeNone;
+            }
+#pragma unroll
+        for (int k = 0; k < RK; ++k) {
+            const int r = threadIdx.x + 256 * k;
+            if (r < rows32) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) *rowc(b, r) = (uint16_t)(lab[k][b] << kCodeShift);
+            }
         }
         __syncthreads();
         const int cend = min(c0 + RC, my_iend);
         if (c0 < cend) {
-            uint4 ah, al, nh, nl;
+            uint4 ah, al;
             load_a(c0, ah, al);
             int i0 = c0;
             const int uend = min(cend, max(c0, i_diag));        // chunks entirely below the diagonal
-            for (; i0 < uend; i0 += 32) {
-                if (i0 + 32 < cend) load_a(i0 + 32, nh, nl);
-                chunk(std::false_type{}, i0, c0, ah, al);
-                ah = nh;
-                al = nl;
-            }
-            for (; i0 < cend; i0 += 32) {
-                if (i0 + 32 < cend) load_a(i0 + 32, nh, nl);
-                chunk(std::true_type{}, i0, c0, ah, al);
-                ah = nh;
-                al = nl;
-            }
+            run(std::false_type{}, i0, uend, cend, c0, ah, al);
+            run(std::true_type{}, i0, cend, cend, c0, ah, al);
         }
         __syncthreads();
     }
@@ -164,30 +232,90 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
             if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[b], cjj));
         }
     }
+    // Restore the table (every reader passed the barrier that closes the row loop).
+    if (g == 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if ((uint32_t)lj[b] < (uint32_t)N) code(b, lj[b]) = kCodeNone;
+    }
 }
 
 // The triangle is folded: column blocks n_jb-1-jp and jp share a workgroup, so every
 // workgroup processes the same number of row chunks.
-__global__ __launch_bounds__(256) void k_pairsum_mfma(Tables t, int parity) {
-    __shared__ __align__(16) uint16_t lab_s[kMfmaB][kMfmaRowChunk];
-    const int tile = blockIdx.x;
-    const int k = find_inst(t.tiles_mfma, t.n_inst, tile);
+template <int B>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_pairsum_mfma(Tables t, int parity, int xcd,
+                                                                                     int cstride) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int k = find_inst(t.tiles, t.n_inst, tile);
     const InstDesc &d = t.desc[k];
-    const int local = tile - t.tiles_mfma[k];
+    if (inst_stopped(d)) return;                              // uniform over the workgroup
+    const int local = tile - t.tiles[k];
     const int n_jb = (d.N + kMfmaCols - 1) / kMfmaCols;
     const int n_pairs = (n_jb + 1) / 2;
     const int jp = local % n_pairs;
     const int pb = local / n_pairs;
-    mfma_block(d, n_jb - 1 - jp, pb, parity, lab_s);
+    const MfmaLds s{(uint16_t *)lds, lds + sizeof(uint16_t) * kMfmaRowCodes, cstride};
+    {
+        const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
+        for (int e = threadIdx.x; e < B * words; e += 256) {
+            const int b = e / words, w = e - b * words;
+            *(uint32_t *)(s.code + (size_t)b * cstride + 4 * w) = 0xFFFFFFFFu;
+        }
+    }
+    __syncthreads();
+    mfma_block<B>(d, n_jb - 1 - jp, pb, parity, s);
     if (jp != n_jb - 1 - jp) {
         __syncthreads();
-        mfma_block(d, jp, pb, parity, lab_s);
+        mfma_block<B>(d, jp, pb, parity, s);
     }
 }
 
-hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, hipStream_t s) {
+hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Variant &v, int max_n,
+                               hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pairsum_mfma, dim3(total_tiles), dim3(256), 0, s, t, parity);
+    if (!variant_ok(v, max_n)) return hipErrorInvalidValue;
+    const int cstride = (int)mfma_code_stride(max_n);
+    const size_t lds = mfma_lds_bytes(v.ipg, max_n);
+    if (v.ipg == 8)
+        hipLaunchKernelGGL(k_pairsum_mfma<8>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.xcd, cstride);
+    else if (v.ipg == 4)
+        hipLaunchKernelGGL(k_pairsum_mfma<4>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.xcd, cstride);
+    else if (v.ipg == 16)
+        hipLaunchKernelGGL(k_pairsum_mfma<16>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.xcd, cstride);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---- scaled split parts ----------------------------------------------------------
+// hs = hi * 2^125, ls = lo * 2^125, elementwise over the ld x ld split of every
+// instance (blockIdx.y). The scaling is exact: |hi|, |lo| <= 1, so the result
+// is a normal bf16 with the same significand (NaN and infinities stay so).
+__device__ __forceinline__ uint32_t scale2(uint32_t w) {
+    const float a = __uint_as_float(w << 16) * 0x1p125f;
+    const float b = __uint_as_float(w & 0xFFFF0000u) * 0x1p125f;
+    return (__float_as_uint(a) >> 16) | (__float_as_uint(b) & 0xFFFF0000u);
+}
+
+__global__ __launch_bounds__(256) void k_scale_split(Tables t) {
+    const InstDesc &d = t.desc[blockIdx.y];
+    const size_t n8 = (size_t)d.ld_h * d.ld_h / 8;            // ld is a multiple of 32
+    for (size_t v = (size_t)blockIdx.x * 256 + threadIdx.x; v < n8; v += (size_t)gridDim.x * 256) {
+        const uint4 h = gld_u4(d.hi + 8 * v);
+        const uint4 l = gld_u4(d.lo + 8 * v);
+        const pga_u32x4 hs = {scale2(h.x), scale2(h.y), scale2(h.z), scale2(h.w)};
+        const pga_u32x4 ls = {scale2(l.x), scale2(l.y), scale2(l.z), scale2(l.w)};
+        *(PGA_GLOBAL pga_u32x4 *)(d.hs + 8 * v) = hs;
+        *(PGA_GLOBAL pga_u32x4 *)(d.ls + 8 * v) = ls;
+    }
+}
+
+hipError_t launch_scale_split(Tables t, int max_ld, hipStream_t s) {
+    if (t.n_inst <= 0 || max_ld <= 0) return hipSuccess;
+    const size_t n8 = (size_t)max_ld * max_ld / 8;
+    const int gx = (int)std::min<size_t>((n8 + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_scale_split, dim3(gx, t.n_inst), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

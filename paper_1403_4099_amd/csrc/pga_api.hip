@@ -4,15 +4,38 @@
 // enqueued), workspace carving, descriptor upload, the generation schedule
 // of Algorithm 1 (fitness -> rank/statistics -> breed, repeated, then a
 // final fitness), its capture into a HIP graph that is replayed on later
-// calls with the same shapes, and optional per-kernel event timing.
+// calls with the same shapes, the pair-sum kernel variants and their tuning
+// table, and optional per-kernel event timing.
 #include "pga_internal.hpp"
 
+#include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <tuple>
 #include <vector>
 
 using namespace pga;
+
+// ---- pair-sum kernel variants ----------------------------------------------------
+namespace pga {
+namespace {
+const Variant kFp64Variants[] = {{PGA_FORM_FP64, 16, 0}, {PGA_FORM_FP64, 8, 0},
+                                 {PGA_FORM_FP64, 16, 1}, {PGA_FORM_FP64, 8, 1}};
+const Variant kMfmaVariants[] = {{PGA_FORM_BF16X2, 8, 0}, {PGA_FORM_BF16X2, 4, 0}, {PGA_FORM_BF16X2, 16, 0},
+                                 {PGA_FORM_BF16X2, 8, 1}, {PGA_FORM_BF16X2, 4, 1}, {PGA_FORM_BF16X2, 16, 1}};
+}  // namespace
+
+int n_variants(int form) {
+    if (form == PGA_FORM_FP64) return (int)(sizeof(kFp64Variants) / sizeof(Variant));
+    if (form == PGA_FORM_BF16X2) return (int)(sizeof(kMfmaVariants) / sizeof(Variant));
+    return 0;
+}
+
+Variant variant_at(int form, int idx) {
+    return form == PGA_FORM_FP64 ? kFp64Variants[idx] : kMfmaVariants[idx];
+}
+}  // namespace pga
 
 namespace {
 
@@ -37,8 +60,9 @@ struct TimedLaunch {
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_tl;
-double g_tsum[8] = {0};
-int64_t g_tcnt[8] = {0};
+constexpr int kTimers = 10;
+double g_tsum[kTimers] = {0};
+int64_t g_tcnt[kTimers] = {0};
 
 template <class F>
 hipError_t timed(int id, hipStream_t s, F &&launch) {
@@ -69,26 +93,63 @@ bool timing_on() {
     return g_timing;
 }
 
+// ---- tuning table ----------------------------------------------------------------
+// Variant index per (form, ceil(N / 64), ceil(log2 P)); N is the largest N of
+// a launch and P its total number of individuals. Filled by pga_tune or
+// pga_tune_set; absent keys use variant 0.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune;
+
+std::tuple<int, int, int> tune_key(int form, int N, int P) {
+    int pb = 0;
+    while (pb < 31 && (1 << pb) < P) ++pb;
+    return std::make_tuple(form, (N + 63) / 64, pb);
+}
+
+int pick_variant(int form, int max_n, int total_p) {
+    int v = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(tune_key(form, max_n, total_p));
+        if (it != g_tune.end()) v = it->second;
+    }
+    if (v < 0 || v >= n_variants(form) || !variant_ok(variant_at(form, v), max_n)) v = 0;
+    return v;
+}
+
 // ---- workspace layout ----------------------------------------------------------
-// [InstDesc x n][prefix fp64 n+1][prefix mfma n+1][prefix inds n+1]
+// [InstDesc x n][prefix tiles n+1][prefix inds n+1]
 // then per instance: [wsum P x N doubles][elite PGA_E_MAX int32]
+// and, for the BF16x2 form, [hi * 2^125 ld x ld][lo * 2^125 ld x ld] (bf16),
+// and, for SUS selection, [rank P int32][weight prefix P uint64].
 struct Layout {
     size_t desc_off, pre_off, inst_off;
-    std::vector<size_t> wsum_off, elite_off;
+    std::vector<size_t> wsum_off, elite_off, hs_off, ls_off, rank_off, cum_off;
     size_t total;
 };
 
-Layout make_layout(const int32_t *Ns, const int32_t *Ps, int n) {
+Layout make_layout(const int32_t *Ns, const int32_t *Ps, int n, int form, const int32_t *sel = nullptr) {
     Layout L;
     L.desc_off = 0;
     L.pre_off = align_up(sizeof(InstDesc) * (size_t)n, 256);
-    L.inst_off = align_up(L.pre_off + sizeof(int32_t) * 3 * ((size_t)n + 1), 256);
+    L.inst_off = align_up(L.pre_off + sizeof(int32_t) * 2 * ((size_t)n + 1), 256);
     size_t off = L.inst_off;
     for (int k = 0; k < n; ++k) {
         L.wsum_off.push_back(off);
         off = align_up(off + sizeof(double) * (size_t)Ns[k] * (size_t)Ps[k], 256);
         L.elite_off.push_back(off);
         off = align_up(off + sizeof(int32_t) * PGA_E_MAX, 256);
+        const size_t ld = (size_t)split_ld(Ns[k]);
+        const size_t split_bytes = form == PGA_FORM_BF16X2 ? sizeof(uint16_t) * ld * ld : 0;
+        L.hs_off.push_back(off);
+        off = align_up(off + split_bytes, 256);
+        L.ls_off.push_back(off);
+        off = align_up(off + split_bytes, 256);
+        const bool sus = sel && sel[k] == PGA_SELECT_SUS;
+        L.rank_off.push_back(off);
+        off = align_up(off + (sus ? sizeof(int32_t) * (size_t)Ps[k] : 0), 256);
+        L.cum_off.push_back(off);
+        off = align_up(off + (sus ? sizeof(uint64_t) * (size_t)Ps[k] : 0), 256);
     }
     L.total = off;
     return L;
@@ -98,25 +159,26 @@ Tables tables_at(void *ws, const Layout &L, int n) {
     char *b = (char *)ws;
     Tables t;
     t.desc = (const InstDesc *)(b + L.desc_off);
-    t.tiles_fp64 = (const int32_t *)(b + L.pre_off);
-    t.tiles_mfma = t.tiles_fp64 + (n + 1);
-    t.inds = t.tiles_mfma + (n + 1);
+    t.tiles = (const int32_t *)(b + L.pre_off);
+    t.inds = t.tiles + (n + 1);
     t.n_inst = n;
     return t;
 }
 
 // ---- the schedule ----------------------------------------------------------------
 struct Shape {
-    int n_inst, tiles_fp64, tiles_mfma, inds, max_n;
+    int n_inst, tiles, inds, max_n;
+    Variant v;
+    int max_p, sus;      // largest P; 1 if an instance selects by SUS
 };
 
 hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, int32_t *status,
                        hipStream_t s) {
     hipError_t e;
     if (form == PGA_FORM_FP64)
-        e = timed(0, s, [&] { return launch_pairsum_fp64(t, sh.tiles_fp64, parity, s); });
+        e = timed(0, s, [&] { return launch_pairsum_fp64(t, sh.tiles, parity, sh.v, s); });
     else
-        e = timed(1, s, [&] { return launch_pairsum_mfma(t, sh.tiles_mfma, parity, s); });
+        e = timed(1, s, [&] { return launch_pairsum_mfma(t, sh.tiles, parity, sh.v, sh.max_n, s); });
     if (e != hipSuccess) return e;
     return timed(2, s, [&] { return launch_finish(t, sh.inds, sh.max_n, parity, status, s); });
 }
@@ -127,16 +189,14 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
     for (int k = 0; k < G; ++k) {
         const int parity = k & 1;
         if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
-        if ((e = timed(3, s, [&] { return launch_rank(t, k, s); })) != hipSuccess) return e;
+        if ((e = timed(3, s, [&] { return launch_rank(t, k, 0, s); })) != hipSuccess) return e;
+        if (sh.sus && (e = timed(8, s, [&] { return launch_sus(t, sh.max_p, s); })) != hipSuccess) return e;
         if ((e = timed(4, s, [&] { return launch_breed(t, sh.inds, parity, k, s); })) != hipSuccess) return e;
     }
     const int parity = G & 1;
     if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
-    if ((e = timed(3, s, [&] { return launch_rank(t, G, s); })) != hipSuccess) return e;
-    if (G & 1) {
-        if ((e = launch_copy_back(t, sh.inds, s)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if ((e = timed(3, s, [&] { return launch_rank(t, G, 1, s); })) != hipSuccess) return e;
+    return launch_copy_back(t, sh.inds, G, s);
 }
 
 }  // namespace
@@ -145,10 +205,11 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
 struct GraphKey {
     void *ws;
     int32_t *status;
-    int n_inst, form, G, tiles_fp64, tiles_mfma, inds, max_n;
+    int n_inst, form, G, tiles, inds, max_n, ipg, xcd, max_p, sus;
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, status, n_inst, form, G, tiles_fp64, tiles_mfma, inds, max_n) <
-               std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles_fp64, o.tiles_mfma, o.inds, o.max_n);
+        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, xcd, max_p, sus) <
+               std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles, o.inds, o.max_n, o.ipg, o.xcd,
+                        o.max_p, o.sus);
     }
 };
 
@@ -237,26 +298,52 @@ int pga_split(const double *C, int32_t N, uint16_t *C_hi, uint16_t *C_lo, void *
     return PGA_OK;
 }
 
+// ---- online EWMA correlation -------------------------------------------------------------
+size_t pga_ewma_ws_bytes(int32_t N, int32_t T) {
+    if (N < 1 || T < 1) return 0;
+    return align_up(sizeof(double) * (size_t)N * (size_t)T, 256);
+}
+
+int pga_ewma(const double *R, int32_t N, int32_t T, int32_t ld_r, double lambda, int32_t flags, double *S,
+             double *C, uint16_t *C_hi, uint16_t *C_lo, int32_t *status, void *ws, size_t ws_bytes,
+             void *stream) {
+    if (!R || !S || !C || N < 1 || T < 1 || ld_r < T) return PGA_ERR_ARG;
+    if (!(lambda >= 0.0 && lambda < 1.0)) return PGA_ERR_ARG;
+    if ((C_hi == nullptr) != (C_lo == nullptr)) return PGA_ERR_ARG;
+    if (flags & ~(PGA_EWMA_RESET | PGA_EWMA_MARKET)) return PGA_ERR_ARG;
+    if (C_hi && N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < pga_ewma_ws_bytes(N, T)) return PGA_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(timed(9, s, [&] {
+        return launch_ewma(R, N, T, ld_r, lambda, (flags & PGA_EWMA_RESET) ? 1 : 0,
+                           (flags & PGA_EWMA_MARKET) ? 1 : 0, S, C, (double *)ws, status, s);
+    }));
+    if (C_hi) HIP_TRY(timed(6, s, [&] { return launch_split(C, N, C_hi, C_lo, s); }));
+    return PGA_OK;
+}
+
 // ---- fitness -----------------------------------------------------------------------------
 size_t pga_fitness_ws_bytes(int32_t N, int32_t P, int32_t form) {
-    (void)form;
     if (N < 1 || P < 0) return 0;
-    const Layout L = make_layout(&N, &P, 1);
+    const Layout L = make_layout(&N, &P, 1, form);
     return L.total;
 }
 
-int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
-                const int32_t *labels, int32_t P, int32_t form, double *fitness, int32_t *n_s,
-                double *c_s, int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+namespace {
+// Checks, descriptor and (BF16x2) scaled split for a single-instance fitness
+// launch; run_fitness then evaluates labels into `fitness`.
+int prepare_single(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
+                   const int32_t *labels, int32_t P, int32_t form, double *fitness, int32_t *n_s,
+                   double *c_s, void *ws, size_t ws_bytes, hipStream_t s, Tables *t, Shape *sh,
+                   InstDesc *dd) {
     if (N < 1 || P < 0) return PGA_ERR_ARG;
     if (form != PGA_FORM_FP64 && form != PGA_FORM_BF16X2) return PGA_ERR_ARG;
     if (N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
     if (P == 0) return PGA_OK;
     if (!C || !labels || !fitness) return PGA_ERR_ARG;
     if (form == PGA_FORM_BF16X2 && (!C_hi || !C_lo)) return PGA_ERR_ARG;
-    const Layout L = make_layout(&N, &P, 1);
+    const Layout L = make_layout(&N, &P, 1, form);
     if (!ws || ws_bytes < L.total) return PGA_ERR_WORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
 
     InstDesc d{};
     d.N = N;
@@ -271,12 +358,136 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
     d.fitness = fitness;
     d.wsum = (double *)((char *)ws + L.wsum_off[0]);
     d.elite = (int32_t *)((char *)ws + L.elite_off[0]);
+    if (form == PGA_FORM_BF16X2) {
+        d.hs = (uint16_t *)((char *)ws + L.hs_off[0]);
+        d.ls = (uint16_t *)((char *)ws + L.ls_off[0]);
+    }
     d.n_s_out = n_s;
     d.c_s_out = c_s;
-    Tables t = tables_at(ws, L, 1);
-    HIP_TRY(launch_write_desc(d, (InstDesc *)t.desc, (int32_t *)t.tiles_fp64, s));
-    Shape sh{1, fp64_tiles(N, P), mfma_tiles(N, P), P, N};
+    *t = tables_at(ws, L, 1);
+    sh->n_inst = 1;
+    sh->inds = P;
+    sh->max_n = N;
+    sh->max_p = P;
+    sh->sus = 0;
+    *dd = d;
+    if (form == PGA_FORM_BF16X2) {
+        HIP_TRY(launch_write_desc(d, 0, (InstDesc *)t->desc, (int32_t *)t->tiles, s));
+        HIP_TRY(launch_scale_split(*t, d.ld_h, s));
+    }
+    return PGA_OK;
+}
+
+// Writes the tile prefix of variant v into the descriptor area and sets sh.
+hipError_t use_variant(const InstDesc &d, const Tables &t, int form, int vi, Shape *sh, hipStream_t s) {
+    sh->v = variant_at(form, vi);
+    sh->tiles = pair_tiles(d.N, d.P, sh->v);
+    return launch_write_desc(d, sh->tiles, (InstDesc *)t.desc, (int32_t *)t.tiles, s);
+}
+}  // namespace
+
+int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
+                const int32_t *labels, int32_t P, int32_t form, double *fitness, int32_t *n_s,
+                double *c_s, int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    Tables t;
+    Shape sh;
+    InstDesc d;
+    const int rc = prepare_single(C, C_hi, C_lo, N, labels, P, form, fitness, n_s, c_s, ws, ws_bytes, s,
+                                  &t, &sh, &d);
+    if (rc != PGA_OK || P == 0) return rc;
+    HIP_TRY(use_variant(d, t, form, pick_variant(form, N, P), &sh, s));
     HIP_TRY(run_fitness(t, sh, form, 0, status, s));
+    return PGA_OK;
+}
+
+// ---- autotuning ---------------------------------------------------------------------------
+int pga_variant_count(int32_t form) {
+    const int n = n_variants(form);
+    return n > 0 ? n : PGA_ERR_ARG;
+}
+
+int pga_variant_info(int32_t form, int32_t variant, int32_t *ipg, int32_t *xcd_order) {
+    if (variant < 0 || variant >= n_variants(form)) return PGA_ERR_ARG;
+    const Variant v = variant_at(form, variant);
+    if (ipg) *ipg = v.ipg;
+    if (xcd_order) *xcd_order = v.xcd;
+    return PGA_OK;
+}
+
+int pga_tune_get(int32_t form, int32_t N, int32_t P) {
+    if (n_variants(form) == 0 || N < 1 || P < 1) return PGA_ERR_ARG;
+    return pick_variant(form, N, P);
+}
+
+int pga_tune_set(int32_t form, int32_t N, int32_t P, int32_t variant) {
+    if (n_variants(form) == 0 || N < 1 || P < 1 || variant < -1 || variant >= n_variants(form))
+        return PGA_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (variant < 0) g_tune.erase(tune_key(form, N, P));
+    else g_tune[tune_key(form, N, P)] = variant;
+    return PGA_OK;
+}
+
+size_t pga_tune_ws_bytes(int32_t N, int32_t P, int32_t form) {
+    const size_t base = pga_fitness_ws_bytes(N, P, form);
+    if (base == 0) return 0;
+    return base + align_up(sizeof(double) * (size_t)P, 256) + align_up(sizeof(int32_t) * PGA_STATUS_WORDS, 256);
+}
+
+int pga_tune(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
+             const int32_t *labels, int32_t P, int32_t form, int32_t reps, void *ws, size_t ws_bytes,
+             int32_t *out_variant, float *out_ms, void *stream) {
+    if (reps < 1 || P < 1) return PGA_ERR_ARG;
+    const size_t need = pga_tune_ws_bytes(N, P, form);
+    if (need == 0) return N > PGA_N_MAX ? PGA_ERR_UNSUPPORTED : PGA_ERR_ARG;
+    if (!ws || ws_bytes < need) return PGA_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t base = pga_fitness_ws_bytes(N, P, form);
+    double *fit = (double *)((char *)ws + base);
+    int32_t *st = (int32_t *)((char *)ws + base + align_up(sizeof(double) * (size_t)P, 256));
+    Tables t;
+    Shape sh;
+    InstDesc d;
+    int rc = prepare_single(C, C_hi, C_lo, N, labels, P, form, fit, nullptr, nullptr, ws, base, s, &t, &sh, &d);
+    if (rc != PGA_OK) return rc;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    int best = -1;
+    float best_ms = 0.f;
+    for (int vi = 0; e == hipSuccess && vi < n_variants(form); ++vi) {
+        if (!variant_ok(variant_at(form, vi), N)) {
+            if (out_ms) out_ms[vi] = -1.f;
+            continue;
+        }
+        if ((e = use_variant(d, t, form, vi, &sh, s)) != hipSuccess) break;
+        if ((e = run_fitness(t, sh, form, 0, st, s)) != hipSuccess) break;      // warm-up
+        if ((e = hipEventRecord(a, s)) != hipSuccess) break;
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = run_fitness(t, sh, form, 0, st, s);
+        if (e != hipSuccess) break;
+        if ((e = hipEventRecord(b, s)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
+        ms /= (float)reps;
+        if (out_ms) out_ms[vi] = ms;
+        if (best < 0 || ms < best_ms) {
+            best = vi;
+            best_ms = ms;
+        }
+    }
+    hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        return PGA_ERR_HIP;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(form, N, P)] = best;
+    }
+    if (out_variant) *out_variant = best;
     return PGA_OK;
 }
 
@@ -290,20 +501,24 @@ static int check_instances(const pga_instance *inst, int32_t n, int32_t form) {
         if (!I.C || !I.pop || !I.pop_tmp || !I.fitness) return PGA_ERR_ARG;
         if (form == PGA_FORM_BF16X2 && (!I.C_hi || !I.C_lo)) return PGA_ERR_ARG;
         if (I.prm.elites < 0 || I.prm.elites >= I.P || I.prm.elites > PGA_E_MAX) return PGA_ERR_ARG;
-        if (I.prm.tournament != 2) return PGA_ERR_ARG;
+        if (I.prm.selection != PGA_SELECT_TOURNAMENT && I.prm.selection != PGA_SELECT_SUS) return PGA_ERR_ARG;
+        if (I.prm.selection == PGA_SELECT_TOURNAMENT && I.prm.tournament != 2) return PGA_ERR_ARG;
         if (I.prm.instance_id >= (1u << 28)) return PGA_ERR_ARG;
+        if (I.prm.stall_gens < 0 || std::isnan(I.prm.tol)) return PGA_ERR_ARG;
+        if (I.prm.stall_gens > 0 && !I.term) return PGA_ERR_ARG;
     }
     return PGA_OK;
 }
 
 size_t pga_evolve_ws_bytes(const pga_instance *inst, int32_t n_inst, int32_t form) {
     if (check_instances(inst, n_inst, form) != PGA_OK) return 0;
-    std::vector<int32_t> Ns(n_inst), Ps(n_inst);
+    std::vector<int32_t> Ns(n_inst), Ps(n_inst), Ss(n_inst);
     for (int k = 0; k < n_inst; ++k) {
         Ns[k] = inst[k].N;
         Ps[k] = inst[k].P;
+        Ss[k] = inst[k].prm.selection;
     }
-    return make_layout(Ns.data(), Ps.data(), n_inst).total;
+    return make_layout(Ns.data(), Ps.data(), n_inst, form, Ss.data()).total;
 }
 
 int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t generations,
@@ -312,12 +527,13 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
     if (form != PGA_FORM_FP64 && form != PGA_FORM_BF16X2) return PGA_ERR_ARG;
     int rc = check_instances(inst, n_inst, form);
     if (rc != PGA_OK) return rc;
-    std::vector<int32_t> Ns(n_inst), Ps(n_inst);
+    std::vector<int32_t> Ns(n_inst), Ps(n_inst), Ss(n_inst);
     for (int k = 0; k < n_inst; ++k) {
         Ns[k] = inst[k].N;
         Ps[k] = inst[k].P;
+        Ss[k] = inst[k].prm.selection;
     }
-    const Layout L = make_layout(Ns.data(), Ps.data(), n_inst);
+    const Layout L = make_layout(Ns.data(), Ps.data(), n_inst, form, Ss.data());
     if (!ws || ws_bytes < L.total) return PGA_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
 
@@ -337,10 +553,17 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
     char *hb = (char *)ctx->staging;
     InstDesc *hd = (InstDesc *)(hb + L.desc_off);
     int32_t *pf = (int32_t *)(hb + L.pre_off);
-    int32_t *pm = pf + (n_inst + 1);
-    int32_t *pi = pm + (n_inst + 1);
-    pf[0] = pm[0] = pi[0] = 0;
-    Shape sh{n_inst, 0, 0, 0, 0};
+    int32_t *pi = pf + (n_inst + 1);
+    pf[0] = pi[0] = 0;
+    Shape sh{n_inst, 0, 0, 0, Variant{form, 0, 0}, 0, 0};
+    int total_p = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        sh.max_n = std::max(sh.max_n, (int)inst[k].N);
+        sh.max_p = std::max(sh.max_p, (int)inst[k].P);
+        sh.sus |= inst[k].prm.selection == PGA_SELECT_SUS ? 1 : 0;
+        total_p += inst[k].P;
+    }
+    sh.v = variant_at(form, pick_variant(form, sh.max_n, total_p));
     for (int k = 0; k < n_inst; ++k) {
         const pga_instance &I = inst[k];
         InstDesc d{};
@@ -357,28 +580,36 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         d.stats = I.stats;
         d.wsum = (double *)((char *)ws + L.wsum_off[k]);
         d.elite = (int32_t *)((char *)ws + L.elite_off[k]);
+        if (form == PGA_FORM_BF16X2) {
+            d.hs = (uint16_t *)((char *)ws + L.hs_off[k]);
+            d.ls = (uint16_t *)((char *)ws + L.ls_off[k]);
+        }
         d.p_cross = I.prm.p_cross_thr;
         d.p_mut = I.prm.p_mut_thr;
         d.seed = I.prm.seed;
         d.inst_id = I.prm.instance_id;
         d.gen0 = I.prm.gen0;
-        d.tile0_fp64 = pf[k];
-        d.tile0_mfma = pm[k];
+        d.term = I.term;
+        d.stall_gens = I.prm.stall_gens;
+        d.tol = I.prm.tol;
+        d.selection = I.prm.selection;
+        if (I.prm.selection == PGA_SELECT_SUS) {
+            d.sus_rank = (int32_t *)((char *)ws + L.rank_off[k]);
+            d.sus_cum = (uint64_t *)((char *)ws + L.cum_off[k]);
+        }
         d.ind0 = pi[k];
         hd[k] = d;
-        pf[k + 1] = pf[k] + fp64_tiles(I.N, I.P);
-        pm[k + 1] = pm[k] + mfma_tiles(I.N, I.P);
+        pf[k + 1] = pf[k] + pair_tiles(I.N, I.P, sh.v);
         pi[k + 1] = pi[k] + I.P;
-        if (I.N > sh.max_n) sh.max_n = I.N;
     }
-    sh.tiles_fp64 = pf[n_inst];
-    sh.tiles_mfma = pm[n_inst];
+    sh.tiles = pf[n_inst];
     sh.inds = pi[n_inst];
     HIP_TRY(hipMemcpyAsync(ws, ctx->staging, head, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(ctx->upload_done, s));
     ctx->upload_pending = true;
 
     Tables t = tables_at(ws, L, n_inst);
+    if (form == PGA_FORM_BF16X2) HIP_TRY(launch_scale_split(t, split_ld(sh.max_n), s));
     if (flags & PGA_EVOLVE_INIT) HIP_TRY(timed(7, s, [&] { return launch_init(t, sh.inds, s); }));
 
     const bool eager = (flags & PGA_EVOLVE_EAGER) || timing_on();
@@ -386,7 +617,8 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         HIP_TRY(run_generations(t, sh, form, generations, status, s));
         return PGA_OK;
     }
-    GraphKey key{ws, status, n_inst, form, generations, sh.tiles_fp64, sh.tiles_mfma, sh.inds, sh.max_n};
+    GraphKey key{ws, status, n_inst, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.xcd,
+                 sh.max_p, sh.sus};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         hipGraph_t g = nullptr;
@@ -471,7 +703,7 @@ static int drain_timing() {
 int pga_timing_reset(void) {
     int rc = drain_timing();
     std::lock_guard<std::mutex> lk(g_tmu);
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < kTimers; ++i) {
         g_tsum[i] = 0.0;
         g_tcnt[i] = 0;
     }
@@ -479,7 +711,7 @@ int pga_timing_reset(void) {
 }
 
 int pga_timing_read(int kernel_id, double *total_ms, int64_t *count) {
-    if (kernel_id < 0 || kernel_id >= 8) return PGA_ERR_ARG;
+    if (kernel_id < 0 || kernel_id >= kTimers) return PGA_ERR_ARG;
     int rc = drain_timing();
     if (rc != PGA_OK) return rc;
     std::lock_guard<std::mutex> lk(g_tmu);

@@ -15,7 +15,8 @@ namespace pga {
 struct InstDesc {
     int32_t N, P, E, ld_h;
     const double *C;
-    const uint16_t *hi, *lo;
+    const uint16_t *hi, *lo;    // BF16 split parts (ld_h x ld_h)
+    uint16_t *hs, *ls;          // split parts times 2^125 (workspace; BF16x2 form only)
     int32_t *pop[2];            // ping-pong population buffers
     double *fitness;            // P
     double *stats;              // (G + 1) x 4 or null
@@ -26,42 +27,71 @@ struct InstDesc {
     uint32_t p_cross, p_mut;
     uint64_t seed;
     uint32_t inst_id, gen0;
-    int32_t tile0_fp64;         // first pair-sum tile (FP64 kernel) of this instance
-    int32_t tile0_mfma;         // first pair-sum tile (MFMA kernel)
+    pga_term_state *term;       // termination state or null
+    int32_t stall_gens;         // 0: no termination test
     int32_t ind0;               // first global individual index
+    double tol;
+    int32_t selection;          // PGA_SELECT_*
     int32_t pad_;
+    int32_t *sus_rank;          // P: 1-based rank (SUS only; workspace)
+    uint64_t *sus_cum;          // P: inclusive prefix of the SUS weights (workspace)
 };
 
 // Prefix tables: for n instances, arrays of n + 1 exclusive prefix sums.
 struct Tables {
     const InstDesc *desc;
-    const int32_t *tiles_fp64;  // prefix of FP64 pair-sum tiles
-    const int32_t *tiles_mfma;  // prefix of MFMA pair-sum tiles
+    const int32_t *tiles;       // prefix of pair-sum tiles (of the kernel variant in use)
     const int32_t *inds;        // prefix of individuals
     int32_t n_inst;
 };
 
 // ---- geometry of the pair-sum kernels --------------------------------------
-constexpr int kFp64Waves = 4;                      // waves per workgroup
-constexpr int kFp64B = 16;                         // individuals per wave
-constexpr int kFp64Cols = 64;                      // columns (stocks j) per workgroup
-constexpr int kFp64Inds = kFp64Waves * kFp64B;     // individuals per workgroup
-
+constexpr int kFp64Waves = 4;                      // waves per workgroup, one column (stock) per lane
+constexpr int kFp64Cols = 64;                      // columns per workgroup
 constexpr int kMfmaWaves = 4;                      // waves per workgroup, 16 columns each
 constexpr int kMfmaCols = 16 * kMfmaWaves;         // columns per workgroup
-constexpr int kMfmaB = 8;                          // individuals per workgroup
-constexpr int kMfmaRowChunk = 1024;                // rows of labels staged in LDS at a time
+constexpr int kMfmaRowCodes = 8192;                // row codes staged in LDS per workgroup (all individuals)
 constexpr int kMfmaFlushRows = 256;                // FP32 accumulators are flushed to FP64 every 256 rows
+constexpr int kMaxLdsBytes = 65536;                // LDS a workgroup may allocate
 
 inline int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 // Pair-sum tiles fold the triangle: column blocks jb and n_jb - 1 - jb share a workgroup.
 inline int32_t fold_pairs(int32_t N, int32_t cols) { return (ceil_div(N, cols) + 1) / 2; }
-inline int32_t fp64_tiles(int32_t N, int32_t P) { return fold_pairs(N, kFp64Cols) * ceil_div(P, kFp64Inds); }
-inline int32_t mfma_tiles(int32_t N, int32_t P) { return fold_pairs(N, kMfmaCols) * ceil_div(P, kMfmaB); }
 inline int32_t split_ld(int32_t N) { return (int32_t)(((int64_t)N + 31) / 32 * 32); }
 
+// A pair-sum kernel variant (what the autotuner chooses between):
+//   ipg  individuals per group: per wave in the FP64 kernel (the workgroup
+//        holds 4 x ipg), per workgroup in the MFMA kernel;
+//   xcd  1: tiles are renumbered so that each XCD gets a contiguous range.
+// Every variant performs the same arithmetic in the same order per
+// individual, so all of them give bitwise identical results.
+struct Variant {
+    int32_t form, ipg, xcd;
+};
+int n_variants(int form);
+Variant variant_at(int form, int idx);
+inline int32_t pair_tiles(int32_t N, int32_t P, const Variant &v) {
+    const int per = v.form == PGA_FORM_FP64 ? kFp64Waves * v.ipg : v.ipg;
+    return fold_pairs(N, 64) * ceil_div(P, per);
+}
+inline size_t mfma_code_stride(int max_n) { return ((size_t)max_n + 15) / 16 * 16; }
+inline size_t mfma_lds_bytes(int ipg, int max_n) {
+    return sizeof(uint16_t) * kMfmaRowCodes + (size_t)ipg * mfma_code_stride(max_n);
+}
+inline bool variant_ok(const Variant &v, int max_n) {
+    return v.form != PGA_FORM_BF16X2 || mfma_lds_bytes(v.ipg, max_n) <= (size_t)kMaxLdsBytes;
+}
+
+// Workgroup b of T runs tile xcd_tile(b, T): the hardware deals workgroups to
+// the 8 XCDs round-robin (b mod 8), so XCD x receives the contiguous tiles
+// [start_x, start_x + count_x) and shares their labels in its own L2.
+__device__ __forceinline__ int xcd_tile(int b, int T) {
+    const int q = T >> 3, r = T & 7, x = b & 7, i = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 // ---- Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) ---------------------
-enum : uint32_t { kTagInit = 0, kTagSel = 1, kTagXov = 2, kTagMut = 3 };
+enum : uint32_t { kTagInit = 0, kTagSel = 1, kTagXov = 2, kTagMut = 3, kTagSus = 4, kTagShuf = 5 };
 
 struct U4 { uint32_t x, y, z, w; };
 
@@ -118,6 +148,11 @@ __device__ __forceinline__ int find_inst(const int32_t *prefix, int n, int t) {
     return lo;
 }
 
+// A stopped instance (termination test fired) is skipped by every kernel.
+__device__ __forceinline__ bool inst_stopped(const InstDesc &d) {
+    return d.term != nullptr && gld(&d.term->stopped) != 0;
+}
+
 // Total order used for ranking, elites and tournaments: higher fitness first,
 // then lower index. -inf compares equal to -inf, so ties among invalid
 // individuals also go to the lower index.
@@ -131,16 +166,21 @@ hipError_t launch_row_stats(const double *R, int N, int T, int64_t ld, double *m
 hipError_t launch_corr(const double *R, int N, int T, int64_t ld, const double *mu, const double *ss,
                        double *C, hipStream_t s);
 hipError_t launch_split(const double *C, int N, uint16_t *hi, uint16_t *lo, hipStream_t s);
+hipError_t launch_ewma(const double *R, int N, int T, int64_t ld, double lam, int reset, int market, double *S,
+                       double *C, double *X, int32_t *status, hipStream_t s);
 
-hipError_t launch_write_desc(const InstDesc &d, InstDesc *dst, int32_t *prefix3, hipStream_t s);
-hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, hipStream_t s);
-hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, hipStream_t s);
+hipError_t launch_write_desc(const InstDesc &d, int32_t tiles, InstDesc *dst, int32_t *prefix2, hipStream_t s);
+hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, const Variant &v, hipStream_t s);
+hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Variant &v, int max_n,
+                               hipStream_t s);
+hipError_t launch_scale_split(Tables t, int max_ld, hipStream_t s);
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status, hipStream_t s);
 
 hipError_t launch_init(Tables t, int total_inds, hipStream_t s);
-hipError_t launch_rank(Tables t, int gen_off, hipStream_t s);
+hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s);
 hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, hipStream_t s);
-hipError_t launch_copy_back(Tables t, int total_inds, hipStream_t s);
+hipError_t launch_sus(Tables t, int max_p, hipStream_t s);
+hipError_t launch_copy_back(Tables t, int total_inds, int G, hipStream_t s);
 hipError_t launch_best(const double *fitness, const int32_t *labels, int P, int N, int32_t *out,
                        double *out_f, hipStream_t s);
 

@@ -22,6 +22,7 @@ PGA_OK = 0
 FORM_FP64 = 0
 FORM_BF16X2 = 1
 FORMS = {"fp64": FORM_FP64, "bf16x2": FORM_BF16X2}
+SELECTIONS = {"tournament": 0, "sus": 1}
 STATUS_WORDS = 8
 ST_LABEL, ST_DOMAIN, ST_ZEROVAR, ST_NONFINITE = 0, 1, 2, 3
 N_MAX = 4096
@@ -30,13 +31,16 @@ EVOLVE_INIT = 1
 EVOLVE_EAGER = 2
 P_CROSS_DEFAULT = int(0.9 * 2**32)
 KERNELS = {"pairsum_fp64": 0, "pairsum_mfma": 1, "finish": 2, "rank": 3, "breed": 4,
-           "correlate": 5, "split": 6, "init": 7}
+           "correlate": 5, "split": 6, "init": 7, "sus": 8, "ewma": 9}
+EWMA_RESET, EWMA_MARKET = 1, 2
 
 SYMBOLS = [
     "pga_ctx_create", "pga_ctx_destroy", "pga_strerror", "pga_last_hip_error",
     "pga_correlate_ws_bytes", "pga_correlate", "pga_split_ld", "pga_split",
     "pga_fitness_ws_bytes", "pga_fitness", "pga_evolve_ws_bytes", "pga_evolve",
     "pga_best_ws_bytes", "pga_best", "pga_timing_enable", "pga_timing_reset", "pga_timing_read",
+    "pga_variant_count", "pga_variant_info", "pga_tune_ws_bytes", "pga_tune", "pga_tune_set",
+    "pga_tune_get", "pga_ewma_ws_bytes", "pga_ewma",
 ]
 
 
@@ -47,13 +51,20 @@ class PgaError(RuntimeError):
 class Params(ct.Structure):
     _fields_ = [("elites", ct.c_int32), ("tournament", ct.c_int32), ("p_cross_thr", ct.c_uint32),
                 ("p_mut_thr", ct.c_uint32), ("seed", ct.c_uint64), ("instance_id", ct.c_uint32),
-                ("gen0", ct.c_uint32)]
+                ("gen0", ct.c_uint32), ("stall_gens", ct.c_int32), ("selection", ct.c_int32),
+                ("tol", ct.c_double)]
+
+
+class TermState(ct.Structure):
+    """pga_term_state (device memory; read back with Instance.term_state())."""
+    _fields_ = [("ref", ct.c_double), ("stall", ct.c_int32), ("stopped", ct.c_int32),
+                ("gens", ct.c_int32), ("call_gens", ct.c_int32)]
 
 
 class InstanceC(ct.Structure):
     _fields_ = [("N", ct.c_int32), ("P", ct.c_int32), ("C", ct.c_void_p), ("C_hi", ct.c_void_p),
                 ("C_lo", ct.c_void_p), ("pop", ct.c_void_p), ("pop_tmp", ct.c_void_p),
-                ("fitness", ct.c_void_p), ("stats", ct.c_void_p), ("prm", Params)]
+                ("fitness", ct.c_void_p), ("stats", ct.c_void_p), ("term", ct.c_void_p), ("prm", Params)]
 
 
 _lib = None
@@ -86,6 +97,15 @@ def load(path: str = LIB_PATH):
         "pga_timing_enable": ([ct.c_int], ct.c_int),
         "pga_timing_reset": ([], ct.c_int),
         "pga_timing_read": ([ct.c_int, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)], ct.c_int),
+        "pga_variant_count": ([i32], ct.c_int),
+        "pga_variant_info": ([i32, i32, ct.POINTER(i32), ct.POINTER(i32)], ct.c_int),
+        "pga_tune_ws_bytes": ([i32, i32, i32], sz),
+        "pga_tune": ([vp, vp, vp, i32, vp, i32, i32, i32, vp, sz, ct.POINTER(i32), ct.POINTER(ct.c_float), vp],
+                     ct.c_int),
+        "pga_tune_set": ([i32, i32, i32, i32], ct.c_int),
+        "pga_tune_get": ([i32, i32, i32], ct.c_int),
+        "pga_ewma_ws_bytes": ([i32, i32], sz),
+        "pga_ewma": ([vp, i32, i32, i32, ct.c_double, i32, vp, vp, vp, vp, vp, vp, sz, vp], ct.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -195,6 +215,70 @@ def fitness_ws_bytes(N: int, P: int, form: str = "fp64") -> int:
     return int(load().pga_fitness_ws_bytes(N, P, FORMS[form]))
 
 
+# ---------------------------------------------------------------- EWMA correlation
+def ewma(R: torch.Tensor, S: torch.Tensor, lam: float = 0.98, reset: bool = False, market: bool = True,
+         split: bool = False, status: torch.Tensor | None = None):
+    """Online EWMA correlation (pga_ewma). Updates S (N x N) in place; returns C [, hi, lo]."""
+    L = load()
+    dev = _dev()
+    N, T = R.shape
+    assert R.dtype == torch.float64 and R.stride(1) == 1 and S.shape == (N, N) and S.is_contiguous()
+    C = torch.empty((N, N), dtype=torch.float64, device=dev)
+    hi = lo = None
+    if split:
+        ld = split_ld(N)
+        hi = torch.empty((ld, ld), dtype=torch.int16, device=dev)
+        lo = torch.empty((ld, ld), dtype=torch.int16, device=dev)
+    ws = _workspace(L.pga_ewma_ws_bytes(N, T), dev)
+    flags = (EWMA_RESET if reset else 0) | (EWMA_MARKET if market else 0)
+    rc = L.pga_ewma(_ptr(R), N, T, R.stride(0), float(lam), flags, _ptr(S), _ptr(C), _ptr(hi), _ptr(lo),
+                    _ptr(status), _ptr(ws), ws.numel(), _stream())
+    _check(rc, "pga_ewma")
+    return (C, hi, lo) if split else C
+
+
+# ---------------------------------------------------------------- autotuning
+def variants(form: str = "fp64"):
+    """[(individuals per group, xcd order)] of the pair-sum kernel variants of a form."""
+    L = load()
+    n = L.pga_variant_count(FORMS[form])
+    out = []
+    for v in range(n):
+        ipg, xcd = ct.c_int32(), ct.c_int32()
+        _check(L.pga_variant_info(FORMS[form], v, ct.byref(ipg), ct.byref(xcd)), "pga_variant_info")
+        out.append((ipg.value, xcd.value))
+    return out
+
+
+def tune(C: torch.Tensor, labels: torch.Tensor, form: str = "fp64", hi=None, lo=None, reps: int = 5):
+    """SYNC. Time every variant on labels, record the fastest; returns (variant, [ms per variant])."""
+    L = load()
+    dev = _dev()
+    P, N = labels.shape
+    need = L.pga_tune_ws_bytes(N, P, FORMS[form])
+    if need == 0:
+        raise PgaError("pga_tune_ws_bytes: invalid shape or form")
+    ws = _workspace(need, dev)
+    n = L.pga_variant_count(FORMS[form])
+    ms = (ct.c_float * n)()
+    v = ct.c_int32(-1)
+    rc = L.pga_tune(_ptr(C), _ptr(hi), _ptr(lo), N, _ptr(labels), P, FORMS[form], reps, _ptr(ws),
+                    ws.numel(), ct.byref(v), ms, _stream())
+    _check(rc, "pga_tune")
+    return v.value, [float(x) for x in ms]
+
+
+def tune_set(form: str, N: int, P: int, variant: int):
+    _check(load().pga_tune_set(FORMS[form], N, P, variant), "pga_tune_set")
+
+
+def tune_get(form: str, N: int, P: int) -> int:
+    v = load().pga_tune_get(FORMS[form], N, P)
+    if v < 0:
+        _check(v, "pga_tune_get")
+    return v
+
+
 # ---------------------------------------------------------------- evolution
 @dataclass
 class Instance:
@@ -212,6 +296,10 @@ class Instance:
     seed: int = 0
     instance_id: int = 0
     gen0: int = 0
+    stall_gens: int = 0
+    tol: float = 1e-5
+    selection: str = "tournament"      # or "sus"
+    term: torch.Tensor | None = None   # pga_term_state bytes (uint8, device)
 
     @property
     def N(self) -> int:
@@ -223,12 +311,22 @@ class Instance:
 
     def to_c(self) -> InstanceC:
         pm = self.p_mut_thr if self.p_mut_thr is not None else mut_thr(self.N)
-        prm = Params(self.elites, 2, self.p_cross_thr, pm, self.seed, self.instance_id, self.gen0)
+        prm = Params(self.elites, 2, self.p_cross_thr, pm, self.seed, self.instance_id, self.gen0,
+                     self.stall_gens, SELECTIONS[self.selection], self.tol)
         return InstanceC(self.N, self.P, self.C.data_ptr(),
                          self.hi.data_ptr() if self.hi is not None else None,
                          self.lo.data_ptr() if self.lo is not None else None,
                          self.pop.data_ptr(), self.pop_tmp.data_ptr(), self.fitness.data_ptr(),
-                         self.stats.data_ptr() if self.stats is not None else None, prm)
+                         self.stats.data_ptr() if self.stats is not None else None,
+                         self.term.data_ptr() if self.term is not None else None, prm)
+
+    def term_state(self) -> dict:
+        """SYNC. The termination state {ref, stall, stopped, gens, call_gens}."""
+        if self.term is None:
+            raise PgaError("instance has no termination state")
+        raw = bytes(self.term.cpu().numpy().tobytes())
+        ts = TermState.from_buffer_copy(raw[: ct.sizeof(TermState)])
+        return {k: getattr(ts, k) for k, _ in TermState._fields_}
 
 
 def make_instance(C, P, hi=None, lo=None, pop=None, stats_rows=0, **kw) -> Instance:
@@ -237,7 +335,9 @@ def make_instance(C, P, hi=None, lo=None, pop=None, stats_rows=0, **kw) -> Insta
     if pop is None:
         pop = torch.empty((P, N), dtype=torch.int32, device=dev)
     st = torch.empty((stats_rows, 4), dtype=torch.float64, device=dev) if stats_rows else None
-    return Instance(C=C, hi=hi, lo=lo, pop=pop, pop_tmp=torch.empty_like(pop),
+    fresh = bytes(TermState(float("-inf"), 0, 0, 0, 0))
+    term = torch.frombuffer(bytearray(fresh), dtype=torch.uint8).to(dev)
+    return Instance(C=C, hi=hi, lo=lo, pop=pop, pop_tmp=torch.empty_like(pop), term=term,
                     fitness=torch.empty(P, dtype=torch.float64, device=dev), stats=st, **kw)
 
 

@@ -15,7 +15,10 @@ Scheduling (host side; every computation is a libpga kernel):
     pga_evolve call over the ragged set of instances (different N);
   * a request that has done its generations is retired with pga_best
     (canonical labels) and its latency (arrival -> result) is recorded;
-    new arrivals join at the next chunk boundary (continuous batching).
+    with the GA's termination test on (stall generations and tolerance,
+    Table 3) a request whose GA has stopped retires at the next chunk
+    boundary instead; new arrivals join at the next chunk boundary
+    (continuous batching).
 Random draws are keyed by (universe id, absolute generation), and evolving
 g1 then g2 generations equals g1 + g2 at once, so every result is bit-for-bit
 the same whether a request ran alone or in a mix.
@@ -57,11 +60,13 @@ class Result:
 
 def footprint_bytes(N: int, P: int, split_ld: int, form: str) -> int:
     """HBM bytes one in-flight request holds: C, BF16 split, two populations, fitness,
-    stats, and its share of the evolve workspace (pair sums P x N FP64, elites, descriptor)."""
+    stats, and its share of the evolve workspace (pair sums P x N FP64, elites, descriptor,
+    and for the BF16x2 form the scaled split copies)."""
     b = 8 * N * N + 8 * P + 8 * N * P + 4096
     b += 2 * 4 * P * N                      # population + ping-pong partner
     if form == "bf16x2":
-        b += 2 * 2 * split_ld * split_ld
+        b += 2 * 2 * split_ld * split_ld    # hi, lo
+        b += 2 * 2 * split_ld * split_ld    # their scaled workspace copies
     return b
 
 
@@ -81,6 +86,7 @@ class Scheduler:
     """Admission, chunking and retirement. `engine` does the device work:
        engine.start(req, gen0, warm_pop) -> (inst, C, hi, lo)
        engine.advance(list_of_inst, generations)
+       engine.progress(list_of_inst) -> [(stopped, generations bred so far)] (one sync)
        engine.finish(inst) -> (labels, fitness)
        engine.resident(universe) -> population tensor or None
        engine.keep(universe, inst) -> keeps the final population resident
@@ -130,17 +136,19 @@ class Scheduler:
         self.max_inflight = max(self.max_inflight, len(self.flights))
 
     def _advance(self):
-        self.engine.advance([f.inst for f in self.flights], self.chunk)
+        insts = [f.inst for f in self.flights]
+        self.engine.advance(insts, self.chunk)
         self.chunks_run += 1
+        prog = self.engine.progress(insts)
         still = []
-        for f in self.flights:
+        for f, (stopped, bred) in zip(self.flights, prog):
             f.remaining -= self.chunk
-            if f.remaining > 0:
+            if f.remaining > 0 and not stopped:
                 still.append(f)
                 continue
             labels, fit = self.engine.finish(f.inst)
             u = f.req.universe
-            self.gen_of[u] += self.G
+            self.gen_of[u] += bred if bred is not None else self.G
             self.engine.keep(u, f.inst)
             self.busy.discard(u)
             self.used -= f.bytes
@@ -190,7 +198,7 @@ class GpuEngine:
     """libpga-backed engine: correlation, warm-started ragged evolve, best."""
 
     def __init__(self, P: int = 1024, form: str = "fp64", elites: int = 2, seed: int = 0,
-                 eager: bool = True):
+                 eager: bool = True, stall_gens: int = 0, tol: float = 1e-5):
         import torch
 
         from . import pga
@@ -198,6 +206,7 @@ class GpuEngine:
         self.torch = torch
         self.P, self.form, self.E, self.seed = P, form, elites, seed
         self.eager = eager
+        self.stall_gens, self.tol = stall_gens, tol
         self.ctx = pga.Context()
         self.pops: dict[int, object] = {}
         self.status = pga.new_status()
@@ -213,7 +222,8 @@ class GpuEngine:
         init = warm_pop is None
         pop = torch.empty((self.P, req.N), dtype=torch.int32, device=C.device) if init else warm_pop
         inst = pga.make_instance(C, self.P, hi=hi, lo=lo, pop=pop, elites=self.E, seed=self.seed,
-                                 instance_id=req.universe, gen0=gen0)
+                                 instance_id=req.universe, gen0=gen0, stall_gens=self.stall_gens,
+                                 tol=self.tol)
         if init:
             self.ctx.evolve([inst], 0, form=self.form, init=True, eager=True, status=self.status)
         return inst, C, hi, lo
@@ -222,6 +232,17 @@ class GpuEngine:
         self.ctx.evolve(insts, generations, form=self.form, eager=self.eager, status=self.status)
         for inst in insts:
             inst.gen0 += generations
+
+    def progress(self, insts):
+        """[(stopped, generations bred since start)] of each instance; None counts without the test."""
+        if self.stall_gens <= 0:
+            return [(False, None)] * len(insts)
+        raw = self.torch.stack([i.term for i in insts]).cpu().numpy()
+        out = []
+        for row in raw:
+            ts = self.pga.TermState.from_buffer_copy(row.tobytes())
+            out.append((bool(ts.stopped), int(ts.gens)))
+        return out
 
     def finish(self, inst):
         labels, f, _ = self.pga.best(inst.fitness, inst.pop)

@@ -59,8 +59,8 @@ def test_host_side_argument_errors(lib):
     assert lib.pga_correlate(fake, 4, 8, 8, fake, fake, None, None, wsp, 1 << 16, None) == -1
     assert lib.pga_correlate(fake, 4, 8, 8, fake, None, None, None, None, 0, None) == -2
     # evolve: null ctx; bad instance parameters
-    inst = pga.InstanceC(8, 4, 0x1000, None, None, 0x1000, 0x1000, 0x1000, None,
-                         pga.Params(4, 2, 0, 0, 0, 0, 0))           # E >= P
+    inst = pga.InstanceC(8, 4, 0x1000, None, None, 0x1000, 0x1000, 0x1000, None, None,
+                         pga.Params(4, 2, 0, 0, 0, 0, 0, 0, 0, 1e-5))   # E >= P
     arr = (pga.InstanceC * 1)(inst)
     assert lib.pga_evolve(None, arr, 1, 1, 0, 0, wsp, 1 << 16, None, None) == -1
     assert lib.pga_evolve_ws_bytes(arr, 1, 0) == 0
@@ -70,8 +70,53 @@ def test_host_side_argument_errors(lib):
     arr[0].prm.tournament = 2
     assert lib.pga_evolve_ws_bytes(arr, 1, 0) > 8 * 4 * 8
     assert lib.pga_evolve_ws_bytes(arr, 1, 1) == 0      # MFMA form needs hi/lo
+    # termination test: needs a state buffer, a non-negative stall count, a known selection, a tolerance
+    arr[0].prm.stall_gens = 50
+    assert lib.pga_evolve_ws_bytes(arr, 1, 0) == 0
+    arr[0].term = 0x2000
+    assert lib.pga_evolve_ws_bytes(arr, 1, 0) > 0
+    arr[0].prm.stall_gens = -1
+    assert lib.pga_evolve_ws_bytes(arr, 1, 0) == 0
+    arr[0].prm.stall_gens = 50
+    arr[0].prm.selection = 2
+    assert lib.pga_evolve_ws_bytes(arr, 1, 0) == 0
+    arr[0].prm.selection = 1                            # SUS: tournament size is not used
+    arr[0].prm.tournament = 5
+    sus_bytes = lib.pga_evolve_ws_bytes(arr, 1, 0)
+    arr[0].prm.selection = 0
+    arr[0].prm.tournament = 2
+    assert sus_bytes >= lib.pga_evolve_ws_bytes(arr, 1, 0) + 4 * (4 + 8)
+    arr[0].prm.tol = float("nan")
+    assert lib.pga_evolve_ws_bytes(arr, 1, 0) == 0
     # best: P < 1
     assert lib.pga_best(fake, fake, 0, 4, None, None, None, wsp, 1 << 16, None) == -1
+
+
+def test_variant_table_host_side(lib):
+    # two forms, each with variant 0 as the default; the table is keyed by (form, N/64, log2 P)
+    assert lib.pga_variant_count(0) >= 2 and lib.pga_variant_count(1) >= 2
+    assert lib.pga_variant_count(7) == -1
+    ipg, xcd = ct.c_int32(), ct.c_int32()
+    assert lib.pga_variant_info(1, 0, ct.byref(ipg), ct.byref(xcd)) == 0 and xcd.value == 0
+    assert lib.pga_variant_info(1, lib.pga_variant_count(1), None, None) == -1
+    assert lib.pga_tune_get(1, 1024, 4096) == 0
+    assert lib.pga_tune_set(1, 1024, 4096, 2) == 0
+    assert lib.pga_tune_get(1, 1000, 3000) == 2           # same bucket
+    assert lib.pga_tune_get(1, 1100, 4096) == 0           # another N bucket
+    assert lib.pga_tune_get(0, 1024, 4096) == 0           # another form
+    assert lib.pga_tune_set(1, 1024, 4096, -1) == 0
+    assert lib.pga_tune_get(1, 1024, 4096) == 0
+    assert lib.pga_tune_set(1, 1024, 4096, 99) == -1
+    # a variant that cannot hold N falls back to variant 0
+    big = [v for v in range(lib.pga_variant_count(1))
+           if lib.pga_variant_info(1, v, ct.byref(ipg), ct.byref(xcd)) == 0 and ipg.value == 16][0]
+    assert lib.pga_tune_set(1, 4096, 512, big) == 0 and lib.pga_tune_get(1, 4096, 512) == 0
+    assert lib.pga_tune_set(1, 4096, 512, -1) == 0
+    # tune: argument and workspace errors come back before any GPU work
+    assert lib.pga_tune(None, None, None, 64, None, 64, 0, 0, None, 0, None, None, None) == -1
+    fake = ct.c_void_p(0x1000)
+    assert lib.pga_tune(fake, None, None, 64, fake, 64, 0, 3, None, 0, None, None, None) == -2
+    assert lib.pga_tune_ws_bytes(64, 64, 0) > lib.pga_fitness_ws_bytes(64, 64, 0)
 
 
 def test_workspace_sizes(lib):

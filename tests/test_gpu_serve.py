@@ -36,3 +36,37 @@ def test_serving_mix_equals_alone(form):
         gen[r.universe] = g0 + G
         assert np.array_equal(labels, res[r.rid].labels), r.rid
         assert f == res[r.rid].fitness, r.rid
+
+
+def test_serving_with_termination_mix_equals_alone():
+    """With the termination test on, a request retires when its GA stops; the mix still equals
+    each universe's requests run alone (same stop generation, same labels and fitness)."""
+    say("serving with termination, mix vs alone")
+    _, stream = synth.serving_stream(duration=0.4, rate=200.0, seed=5)
+    reqs = [Request(i, u, t, torch.from_numpy(R).cuda(), R.shape[0], R.shape[1])
+            for i, (t, u, R) in enumerate(stream)]
+    P, G, chunk, stall = 96, 60, 5, 6
+    mixed = Scheduler(GpuEngine(P=P, stall_gens=stall, tol=1e-3), P=P, generations=G, chunk=chunk,
+                      hbm_budget=4 << 30)
+    res = {r.rid: r for r in mixed.run(reqs)}
+    assert len(res) == len(reqs)
+    early = [r for r in res.values() if r.gen_end % G != 0]
+    say(f"  {len(reqs)} requests, {len(early)} stopped early, {mixed.summary()}")
+
+    eng = GpuEngine(P=P, stall_gens=stall, tol=1e-3)
+    gen = {}
+    for r in reqs:
+        g0 = gen.get(r.universe, 0)
+        inst, C, hi, lo = eng.start(r, g0, eng.resident(r.universe))
+        bred = 0
+        for _ in range(G // chunk):
+            eng.advance([inst], chunk)
+            stopped, bred = eng.progress([inst])[0]
+            if stopped:
+                break
+        labels, f = eng.finish(inst)
+        eng.keep(r.universe, inst)
+        gen[r.universe] = g0 + bred
+        assert gen[r.universe] == res[r.rid].gen_end, r.rid
+        assert np.array_equal(labels, res[r.rid].labels), r.rid
+        assert f == res[r.rid].fitness, r.rid

@@ -1,0 +1,85 @@
+"""Pair-sum kernel variants and the autotuner: every variant of a form gives bitwise
+identical fitness (FP64 also within tolerance of the oracle), pga_tune picks one of
+them, and evolve results do not depend on the variant in use."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1403_4099_amd import pga
+from gpu_cases import corr, fitness_tol, say
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+SHAPES = [(100, 70), (1024, 96), (300, 1), (4096, 9)]
+
+
+def _g(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+@pytest.mark.parametrize("N,P", SHAPES, ids=[f"N{n}-P{p}" for n, p in SHAPES])
+def test_every_variant_gives_identical_fitness(form, N, P):
+    say(f"variants {form} N={N} P={P}")
+    C, _ = corr(N, seed=N % 7)
+    Cg = _g(C)
+    hi, lo = pga.split(Cg)
+    rng = np.random.default_rng(N + P)
+    pop = rng.integers(0, max(2, N // 6), size=(P, N), dtype=np.int32)
+    popg = _g(pop)
+    ref = None
+    try:
+        for v in range(len(pga.variants(form))):
+            pga.tune_set(form, N, P, v)
+            f = pga.fitness(Cg, popg, form, hi=hi, lo=lo)
+            if ref is None:
+                ref = f.clone()
+            assert torch.equal(f, ref), f"variant {v} ({pga.variants(form)[v]})"
+    finally:
+        pga.tune_set(form, N, P, -1)
+    if form == "fp64":
+        f_o, mag = O.fitness(C, pop, want_mag=True)
+        assert np.all(np.abs(ref.cpu().numpy() - f_o) <= fitness_tol(mag))
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+def test_tune_picks_a_fitting_variant_and_records_it(form):
+    say(f"tune {form}")
+    N, P = 512, 256
+    C, _ = corr(N, seed=1)
+    Cg = _g(C)
+    hi, lo = pga.split(Cg)
+    pop = _g(np.random.default_rng(0).integers(0, N, size=(P, N), dtype=np.int32))
+    try:
+        v, ms = pga.tune(Cg, pop, form, hi=hi, lo=lo, reps=3)
+        say(f"  chosen {v} {pga.variants(form)[v]}; ms {['%.3f' % x for x in ms]}")
+        assert 0 <= v < len(ms) and ms[v] > 0 and ms[v] == min(x for x in ms if x > 0)
+        assert pga.tune_get(form, N, P) == v
+    finally:
+        pga.tune_set(form, N, P, -1)
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+def test_evolve_does_not_depend_on_the_variant(form):
+    say(f"evolve per variant {form}")
+    Ns, P, G = [70, 200, 33], 48, 5
+    Cs = [_g(corr(N, seed=i)[0]) for i, N in enumerate(Ns)]
+    splits = [pga.split(C) for C in Cs]
+    results = []
+    total_p, max_n = P * len(Ns), max(Ns)
+    try:
+        for v in range(len(pga.variants(form))):
+            pga.tune_set(form, max_n, total_p, v)
+            ctx = pga.Context()
+            insts = [pga.make_instance(C, P, hi=h, lo=l, stats_rows=G + 1, seed=2, instance_id=i)
+                     for i, (C, (h, l)) in enumerate(zip(Cs, splits))]
+            ctx.evolve(insts, G, form=form, init=True)
+            torch.cuda.synchronize()
+            results.append([(I.pop.clone(), I.fitness.clone(), I.stats.clone()) for I in insts])
+    finally:
+        pga.tune_set(form, max_n, total_p, -1)
+    for v, res in enumerate(results[1:], start=1):
+        for (a, fa, sa), (b, fb, sb) in zip(results[0], res):
+            assert torch.equal(a, b) and torch.equal(fa, fb) and torch.equal(sa, sb), f"variant {v}"

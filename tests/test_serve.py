@@ -14,24 +14,35 @@ class FakeClock:
 
 
 class FakeEngine:
-    def __init__(self, clock, cost_per_gen=1e-4):
+    def __init__(self, clock, cost_per_gen=1e-4, stop_after=None):
         self.clock = clock
         self.cost = cost_per_gen
         self.pops = {}
         self.log = []
+        self.stop_after = stop_after or {}     # rid -> generations after which the GA stops
 
     def resident(self, u):
         return self.pops.get(u)
 
     def start(self, req, gen0, warm):
         self.log.append(("start", req.rid, req.universe, gen0, warm is not None))
-        return {"req": req, "gen": gen0}, None, None, None
+        return {"req": req, "gen": gen0, "bred": 0}, None, None, None
 
     def advance(self, insts, g):
         self.log.append(("advance", tuple(i["req"].rid for i in insts), g))
         self.clock.t += self.cost * g * len(insts)
         for i in insts:
-            i["gen"] += g
+            lim = self.stop_after.get(i["req"].rid)
+            step = g if lim is None else max(0, min(g, lim - i["bred"]))
+            i["gen"] += step
+            i["bred"] += step
+
+    def progress(self, insts):
+        out = []
+        for i in insts:
+            lim = self.stop_after.get(i["req"].rid)
+            out.append((lim is not None and i["bred"] >= lim, i["bred"] if self.stop_after else None))
+        return out
 
     def finish(self, inst):
         return np.zeros(inst["req"].N, dtype=np.int32), float(inst["gen"])
@@ -82,3 +93,20 @@ def test_admission_respects_the_hbm_budget_and_rejects_oversize():
             assert len(e[1]) == 1
     summ = s.summary()
     assert summ["requests"] == 2 and summ["rejected"] == 1 and summ["max_in_flight"] == 1
+
+
+def test_stopped_requests_retire_early_and_the_next_window_continues_from_their_generation():
+    clk = FakeClock()
+    eng = FakeEngine(clk, stop_after={0: 12})
+    s = Scheduler(eng, P=64, generations=40, chunk=5, hbm_budget=1 << 30, clock=clk)
+    reqs = _reqs([(0.0, 0, 64), (0.0, 1, 64), (0.0, 0, 64)])
+    res = {r.rid: r for r in s.run(reqs)}
+    assert sorted(res) == [0, 1, 2]
+    # request 0 stopped after 12 generations: it retired at the chunk boundary at 15
+    adv0 = [e for e in eng.log if e[0] == "advance" and 0 in e[1]]
+    assert len(adv0) == 3
+    assert res[0].gen_end == 12
+    # the universe's next window warm-started at generation 12; request 1 ran all 40
+    starts = [e for e in eng.log if e[0] == "start" and e[2] == 0]
+    assert [e[3] for e in starts] == [0, 12]
+    assert res[1].gen_end == 40 and res[2].gen_end == 52
