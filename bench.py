@@ -49,6 +49,8 @@ def parse():
                     help="instances of the ragged batched run (0 = skip)")
     ap.add_argument("--tune-reps", type=int, default=5,
                     help="timed evaluations per pair-sum kernel variant in the autotuning pass")
+    ap.add_argument("--variants", default="",
+                    help="use these pair-sum kernel variants instead of autotuning, e.g. bf16x2=3,fp64=3")
     return ap.parse_args()
 
 
@@ -140,16 +142,18 @@ def source_sha(path):
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel_src: str, N: int, P: int):
-    """HBM bytes per launch from the committed counter summary, if it was taken on this kernel source."""
+def recorded_traffic(kernel_src: str, N: int, P: int, variant: int):
+    """HBM bytes per launch from the committed counter summary, if it was taken on this kernel source
+    and kernel variant."""
     fn = os.path.join(ROOT, "profiles", "traffic_per_launch.txt")
     if not os.path.exists(fn):
         return None
     sha = source_sha(kernel_src)
     for line in open(fn):
         f = line.split()
-        if len(f) >= 5 and not line.startswith("#") and f[0] == sha and int(f[1]) == N and int(f[2]) == P:
-            return float(f[3]) + float(f[4])
+        if (len(f) >= 6 and not line.startswith("#") and f[0] == sha and int(f[1]) == N and int(f[2]) == P
+                and int(f[3]) == variant):
+            return float(f[4]) + float(f[5])
     return None
 
 
@@ -258,12 +262,19 @@ def main():
     pga._check(rc, "pga_correlate")
     pop_tune = torch.from_numpy(synth.random_labelings(P, N, seed=7)).to(dev)
     tuned = {}
+    fixed = dict(kv.split("=") for kv in args.variants.split(",") if kv)
     for form in forms:
-        v, ms = pga.tune(C, pop_tune, form, hi=hi, lo=lo, reps=args.tune_reps)
+        if form in fixed:
+            v, ms = int(fixed[form]), None
+            pga.tune_set(form, N, P, v)
+        else:
+            v, ms = pga.tune(C, pop_tune, form, hi=hi, lo=lo, reps=args.tune_reps)
         tuned[form] = {"variant": v, "individuals_per_group": pga.variants(form)[v][0],
                        "xcd_order": pga.variants(form)[v][1],
-                       "ms_per_variant": {f"{a}x{b}": round(m, 4) for (a, b), m in zip(pga.variants(form), ms)}}
-        print(f"[bench] autotune {form}: {tuned[form]}", file=sys.stderr, flush=True)
+                       "ms_per_variant": None if ms is None else
+                       {f"{a}x{b}": round(m, 4) for (a, b), m in zip(pga.variants(form), ms)}}
+        print(f"[bench] {'variant' if ms is None else 'autotune'} {form}: {tuned[form]}", file=sys.stderr,
+              flush=True)
     del pop_tune
 
     results = {}
@@ -320,13 +331,13 @@ def main():
     if form == "bf16x2":
         achieved = mfma_issued_flops(N, P, tuned[form]["individuals_per_group"]) / t_launch / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_MFMA_BF16, "traffic": recorded_traffic(src, N, P),
+                "frac": achieved / PEAK_MFMA_BF16, "traffic": recorded_traffic(src, N, P, tuned[form]["variant"]),
                 "kernel": "k_pairsum_mfma", "avg_launch_us": k["avg_us"],
                 "work_per_launch": "issued v_mfma_f32_16x16x32_bf16 flops (hi and lo, 16x16 tile per 16 stocks)"}
     else:
         achieved = 2 * pair_visits(N, P) / t_launch / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU, "unit": "Tops/s",
-                "frac": achieved / PEAK_ALU, "traffic": recorded_traffic(src, N, P),
+                "frac": achieved / PEAK_ALU, "traffic": recorded_traffic(src, N, P, tuned[form]["variant"]),
                 "kernel": "k_pairsum_fp64", "avg_launch_us": k["avg_us"],
                 "work_per_launch": "2 ops (label compare, FP64 add) per unordered pair per individual"}
     other = {}

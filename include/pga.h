@@ -152,7 +152,7 @@ int32_t pga_split_ld(int32_t N);
  * pga_split_ld(N) x pga_split_ld(N) uint16 bit patterns. */
 int pga_split(const double *C, int32_t N, uint16_t *C_hi, uint16_t *C_lo, void *stream);
 
-/* ---- online EWMA correlation (Section 4.2.4, data pre-processing) ------ */
+/* ---- online EWMA correlation (Section 4.2.5, data pre-processing) ------ */
 /* The step before the path for streaming windows: the paper removes the
  * market mode, keeps an exponentially weighted moving-average covariance
  * with forgetting factor lambda (0.98 there), and takes the correlation of

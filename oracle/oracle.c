@@ -165,7 +165,7 @@ void oracle_fitness(const double *C, int N, const int32_t *pop, int P, double *f
 }
 
 /* ------------------------------------------------------------------ */
-/* Online EWMA correlation (Section 4.2.4, data pre-processing): market */
+/* Online EWMA correlation (Section 4.2.5, data pre-processing): market */
 /* mode removed, then an exponentially weighted covariance with         */
 /* forgetting factor lambda, then the correlation of that covariance.   */
 /* ------------------------------------------------------------------ */

@@ -255,7 +255,7 @@ def evolve_term(C, P, G, stall_gens, tol, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mu
 
 
 def ewma(R, lam=0.98, S=None, market=True, status=None):
-    """Online EWMA correlation (Section 4.2.4): returns (C, S). S=None starts from a zero state;
+    """Online EWMA correlation (Section 4.2.5): returns (C, S). S=None starts from a zero state;
     otherwise the recursion continues from the given state (not modified)."""
     R = _c64(R)
     N, T = R.shape

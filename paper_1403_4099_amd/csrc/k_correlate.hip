@@ -179,7 +179,7 @@ hipError_t launch_split(const double *C, int N, uint16_t *hi, uint16_t *lo, hipS
     return hipGetLastError();
 }
 
-// ---- online EWMA correlation (Section 4.2.4 pre-processing) ------------------
+// ---- online EWMA correlation (Section 4.2.5 pre-processing) ------------------
 // The recursion S <- lambda S + (1 - lambda) x_t x_t^T over t = 0 .. T-1 is
 // S <- lambda^T S + sum_t w_t x_t x_t^T with w_t = (1 - lambda) lambda^(T-1-t):
 //   prep : x_it = sqrt(w_t) (R_it - m_t), m_t the equal-weight market return

@@ -1,4 +1,4 @@
-"""Oracle pins for the online EWMA correlation (Section 4.2.4 pre-processing:
+"""Oracle pins for the online EWMA correlation (Section 4.2.5 pre-processing:
 market mode removed, exponentially weighted covariance, its correlation).
 
 Pins: closed forms for one observation and for lambda = 0, the zero column sums
