@@ -195,8 +195,11 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
 /* ---- kernel variants and autotuning ------------------------------------- */
 /* The pair-sum kernel of each form comes in variants that differ only in how
  * work is grouped: individuals per group (per wave for PGA_FORM_FP64, per
- * workgroup for PGA_FORM_BF16X2) and whether tiles are renumbered so that
- * each of the 8 XCDs receives a contiguous range. All variants of a form
+ * workgroup for PGA_FORM_BF16X2) and the tile order (xcd_order 0: as
+ * launched, column pairs fastest; 1: tiles renumbered so each of the 8 XCDs
+ * receives a contiguous range, column pairs fastest; 2: contiguous ranges
+ * per XCD with individual batches fastest, so each XCD reads few column
+ * blocks of C). All variants of a form
  * give bitwise identical results. pga_fitness and pga_evolve use the variant
  * the process-wide tuning table holds for (form, ceil(N / 64), ceil(log2 P))
  * (N: largest N of the call, P: its total number of individuals), variant 0

@@ -157,10 +157,10 @@ __device__ __forceinline__ double fp64_c(const double *__restrict__ C, int N, in
 }
 
 template <int B>
-__global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int xcd) {
+__global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int order) {
     __shared__ int4 lab_s[kFp64Waves][2][64][B / 4];
 
-    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int tile = order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const int k = find_inst(t.tiles, t.n_inst, tile);
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;
@@ -168,8 +168,8 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int 
     const int local = tile - t.tiles[k];
     const int n_jb = (N + kFp64Cols - 1) / kFp64Cols;
     const int n_pairs = (n_jb + 1) / 2;
-    const int jp = local % n_pairs;
-    const int pb = local / n_pairs;
+    const TilePos tp = tile_pos(local, n_pairs, (P + kFp64Waves * B - 1) / (kFp64Waves * B), order);
+    const int jp = tp.jp, pb = tp.pb;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, kept scalar
     const int lane = threadIdx.x & 63;
     const int pbase = pb * (kFp64Waves * B) + wave * B;
@@ -265,9 +265,9 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int 
 hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, const Variant &v, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
     if (v.ipg == 16)
-        hipLaunchKernelGGL(k_pairsum_fp64<16>, dim3(total_tiles), dim3(256), 0, s, t, parity, v.xcd);
+        hipLaunchKernelGGL(k_pairsum_fp64<16>, dim3(total_tiles), dim3(256), 0, s, t, parity, v.order);
     else if (v.ipg == 8)
-        hipLaunchKernelGGL(k_pairsum_fp64<8>, dim3(total_tiles), dim3(256), 0, s, t, parity, v.xcd);
+        hipLaunchKernelGGL(k_pairsum_fp64<8>, dim3(total_tiles), dim3(256), 0, s, t, parity, v.order);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

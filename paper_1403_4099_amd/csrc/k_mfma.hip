@@ -243,18 +243,18 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
 // The triangle is folded: column blocks n_jb-1-jp and jp share a workgroup, so every
 // workgroup processes the same number of row chunks.
 template <int B>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_pairsum_mfma(Tables t, int parity, int xcd,
-                                                                                     int cstride) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_pairsum_mfma(Tables t, int parity,
+                                                                                     int order, int cstride) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int tile = order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const int k = find_inst(t.tiles, t.n_inst, tile);
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;                              // uniform over the workgroup
     const int local = tile - t.tiles[k];
     const int n_jb = (d.N + kMfmaCols - 1) / kMfmaCols;
     const int n_pairs = (n_jb + 1) / 2;
-    const int jp = local % n_pairs;
-    const int pb = local / n_pairs;
+    const TilePos tp = tile_pos(local, n_pairs, (d.P + B - 1) / B, order);
+    const int jp = tp.jp, pb = tp.pb;
     const MfmaLds s{(uint16_t *)lds, lds + sizeof(uint16_t) * kMfmaRowCodes, cstride};
     {
         const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
@@ -278,11 +278,11 @@ hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Vari
     const int cstride = (int)mfma_code_stride(max_n);
     const size_t lds = mfma_lds_bytes(v.ipg, max_n);
     if (v.ipg == 8)
-        hipLaunchKernelGGL(k_pairsum_mfma<8>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.xcd, cstride);
+        hipLaunchKernelGGL(k_pairsum_mfma<8>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.order, cstride);
     else if (v.ipg == 4)
-        hipLaunchKernelGGL(k_pairsum_mfma<4>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.xcd, cstride);
+        hipLaunchKernelGGL(k_pairsum_mfma<4>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.order, cstride);
     else if (v.ipg == 16)
-        hipLaunchKernelGGL(k_pairsum_mfma<16>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.xcd, cstride);
+        hipLaunchKernelGGL(k_pairsum_mfma<16>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.order, cstride);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

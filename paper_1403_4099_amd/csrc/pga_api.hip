@@ -20,10 +20,11 @@ using namespace pga;
 // ---- pair-sum kernel variants ----------------------------------------------------
 namespace pga {
 namespace {
-const Variant kFp64Variants[] = {{PGA_FORM_FP64, 16, 0}, {PGA_FORM_FP64, 8, 0},
-                                 {PGA_FORM_FP64, 16, 1}, {PGA_FORM_FP64, 8, 1}};
+const Variant kFp64Variants[] = {{PGA_FORM_FP64, 16, 0}, {PGA_FORM_FP64, 8, 0}, {PGA_FORM_FP64, 16, 1},
+                                 {PGA_FORM_FP64, 8, 1},  {PGA_FORM_FP64, 16, 2}, {PGA_FORM_FP64, 8, 2}};
 const Variant kMfmaVariants[] = {{PGA_FORM_BF16X2, 8, 0}, {PGA_FORM_BF16X2, 4, 0}, {PGA_FORM_BF16X2, 16, 0},
-                                 {PGA_FORM_BF16X2, 8, 1}, {PGA_FORM_BF16X2, 4, 1}, {PGA_FORM_BF16X2, 16, 1}};
+                                 {PGA_FORM_BF16X2, 8, 1}, {PGA_FORM_BF16X2, 4, 1}, {PGA_FORM_BF16X2, 16, 1},
+                                 {PGA_FORM_BF16X2, 8, 2}, {PGA_FORM_BF16X2, 4, 2}, {PGA_FORM_BF16X2, 16, 2}};
 }  // namespace
 
 int n_variants(int form) {
@@ -205,10 +206,10 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
 struct GraphKey {
     void *ws;
     int32_t *status;
-    int n_inst, form, G, tiles, inds, max_n, ipg, xcd, max_p, sus;
+    int n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus;
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, xcd, max_p, sus) <
-               std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles, o.inds, o.max_n, o.ipg, o.xcd,
+        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus) <
+               std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles, o.inds, o.max_n, o.ipg, o.order,
                         o.max_p, o.sus);
     }
 };
@@ -411,7 +412,7 @@ int pga_variant_info(int32_t form, int32_t variant, int32_t *ipg, int32_t *xcd_o
     if (variant < 0 || variant >= n_variants(form)) return PGA_ERR_ARG;
     const Variant v = variant_at(form, variant);
     if (ipg) *ipg = v.ipg;
-    if (xcd_order) *xcd_order = v.xcd;
+    if (xcd_order) *xcd_order = v.order;
     return PGA_OK;
 }
 
@@ -617,7 +618,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         HIP_TRY(run_generations(t, sh, form, generations, status, s));
         return PGA_OK;
     }
-    GraphKey key{ws, status, n_inst, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.xcd,
+    GraphKey key{ws, status, n_inst, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.order,
                  sh.max_p, sh.sus};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {

@@ -60,13 +60,17 @@ inline int32_t fold_pairs(int32_t N, int32_t cols) { return (ceil_div(N, cols) +
 inline int32_t split_ld(int32_t N) { return (int32_t)(((int64_t)N + 31) / 32 * 32); }
 
 // A pair-sum kernel variant (what the autotuner chooses between):
-//   ipg  individuals per group: per wave in the FP64 kernel (the workgroup
-//        holds 4 x ipg), per workgroup in the MFMA kernel;
-//   xcd  1: tiles are renumbered so that each XCD gets a contiguous range.
+//   ipg    individuals per group: per wave in the FP64 kernel (the workgroup
+//          holds 4 x ipg), per workgroup in the MFMA kernel;
+//   order  tile order: 0 workgroup b runs tile b, column pairs fastest;
+//          1 tiles renumbered so each XCD gets a contiguous range, column
+//          pairs fastest (an XCD sees few individual batches, all columns);
+//          2 as 1 with individual batches fastest (an XCD sees few column
+//          pairs, so their C rows stay in its L2).
 // Every variant performs the same arithmetic in the same order per
 // individual, so all of them give bitwise identical results.
 struct Variant {
-    int32_t form, ipg, xcd;
+    int32_t form, ipg, order;
 };
 int n_variants(int form);
 Variant variant_at(int form, int idx);
@@ -80,6 +84,15 @@ inline size_t mfma_lds_bytes(int ipg, int max_n) {
 }
 inline bool variant_ok(const Variant &v, int max_n) {
     return v.form != PGA_FORM_BF16X2 || mfma_lds_bytes(v.ipg, max_n) <= (size_t)kMaxLdsBytes;
+}
+
+struct TilePos {
+    int jp, pb;
+};
+// (column pair, individual batch) of tile `local` of an instance.
+__device__ __forceinline__ TilePos tile_pos(int local, int n_pairs, int n_pb, int order) {
+    if (order == 2) return TilePos{local / n_pb, local % n_pb};
+    return TilePos{local % n_pairs, local / n_pairs};
 }
 
 // Workgroup b of T runs tile xcd_tile(b, T): the hardware deals workgroups to
