@@ -14,6 +14,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace pga {
 
 // ---------------------------------------------------------------------------
@@ -214,7 +216,15 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int 
         __builtin_amdgcn_wave_barrier();                 // previous block's reads of buffer 0 are done
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         store_labels(0, nxt);
-        for (int ch = 0; ch < nchunks; ++ch) {
+        // Chunks before the last hold rows i < 64 jb <= j (and i < N) only, so their C
+        // loads need no test; lanes past N read column N - 1 and are never stored.
+        const int jc = jok ? j : N - 1;
+        auto chunk = [&](auto checked_tag, int ch) {
+            constexpr bool checked = decltype(checked_tag)::value;
+            auto cload = [&](int i) -> double {
+                if constexpr (checked) return fp64_c(C, N, i, j);
+                else return gld(C + (size_t)i * N + jc);
+            };
             const int i0 = ch * 64;
             const int buf = ch & 1;
             if (ch + 1 < nchunks) fetch_labels(i0 + 64, nxt);   // in flight during this chunk
@@ -224,14 +234,14 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int 
 
             double cq[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) cq[q] = fp64_c(C, N, i0 + q, j);
+            for (int q = 0; q < 4; ++q) cq[q] = cload(i0 + q);
             for (int r = 0; r < 64; r += 4) {
                 double cur[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) cur[q] = cq[q];
                 if (r + 4 < 64) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) cq[q] = fp64_c(C, N, i0 + r + 4 + q, j);
+                    for (int q = 0; q < 4; ++q) cq[q] = cload(i0 + r + 4 + q);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -250,7 +260,9 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int 
                 }
             }
             if (ch + 1 < nchunks) store_labels(buf ^ 1, nxt);
-        }
+        };
+        for (int ch = 0; ch + 1 < nchunks; ++ch) chunk(std::false_type{}, ch);
+        chunk(std::true_type{}, nchunks - 1);
         if (jok) {
             const double cjj = gld(C + (size_t)j * N + j);
 #pragma unroll
@@ -295,7 +307,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Per-wave LDS region of the finish kernel: csum (int64), cnt (int32) and the
-// list of non-singleton labels (int32). Each array is padded to 16 bytes, so
+// list of non-singleton labels (uint16). Each array is padded to 16 bytes, so
 // every region and every array in it starts 16-byte aligned (64-bit LDS
 // atomics need naturally aligned addresses).
 __host__ __device__ __forceinline__ size_t finish_csum_bytes(int max_n) {
@@ -305,8 +317,10 @@ __host__ __device__ __forceinline__ size_t finish_cnt_bytes(int max_n) {
     return ((size_t)max_n * sizeof(int) + 15) / 16 * 16;
 }
 __host__ __device__ __forceinline__ size_t finish_wave_bytes(int max_n) {
-    // csum, cnt, and the list of labels with n_s > 1 (at most max_n / 2 of them)
-    return finish_csum_bytes(max_n) + finish_cnt_bytes(max_n) + ((size_t)(max_n / 2 + 1) * sizeof(int) + 15) / 16 * 16;
+    // csum, cnt, and the list of labels with n_s > 1 (at most max_n / 2 of them, 16-bit since
+    // labels are below PGA_N_MAX): 13.3 KB at N = 1024, so three 4-wave workgroups share a CU
+    return finish_csum_bytes(max_n) + finish_cnt_bytes(max_n) +
+           ((size_t)(max_n / 2 + 1) * sizeof(uint16_t) + 15) / 16 * 16;
 }
 
 constexpr int kFinCache = 16;
@@ -327,7 +341,7 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
     unsigned char *base = smem + (size_t)wave * finish_wave_bytes(max_n);
     long long *csum = (long long *)base;
     int *cnt = (int *)(base + finish_csum_bytes(max_n));
-    int *lst = (int *)(base + finish_csum_bytes(max_n) + finish_cnt_bytes(max_n));
+    uint16_t *lst = (uint16_t *)(base + finish_csum_bytes(max_n) + finish_cnt_bytes(max_n));
 
     // The first kFinCache * 64 labels and values stay in registers (all loads issued
     // together); stocks beyond that are read again in the accumulation pass.
@@ -414,7 +428,7 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
             if (d.c_s_out) gst(d.c_s_out + (size_t)p * N + s, ldexp((double)csum[s], -sc));
         }
         const uint64_t m = __ballot(n > 1);
-        if (n > 1) lst[nlist + __popcll(m & ((1ull << lane) - 1ull))] = s;
+        if (n > 1) lst[nlist + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)s;
         nlist += __popcll(m);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
