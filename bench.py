@@ -88,10 +88,12 @@ def batched_run(n_inst, form, generations=200, reps=2):
             "workload": "256 instances, N ~ U{32..512}, T=1024, 2-12 planted clusters, P=512, G=200"}
 
 
-def serving_run(seconds, rate, form):
+def serving_run(seconds, rate, form, stall_gens=0, tol=1e-5):
     """Continuous-batching run over a Poisson stream of correlation windows (N in {64, 256, 1024}
-    at 6:3:1, T = 390, P = 1024 resident and warm-started per universe, 100 generations per
-    request in chunks of 10, 8 GiB admission budget). Windows are staged in HBM beforehand."""
+    at 6:3:1, T = 390, P = 1024 resident and warm-started per universe, up to 100 generations per
+    request in chunks of 10, 8 GiB admission budget). Windows are staged in HBM beforehand. With
+    stall_gens > 0 a request also ends when its GA's termination test fires (Table 3)."""
+    import numpy as np
     import torch
 
     from paper_1403_4099_amd import synth
@@ -101,13 +103,26 @@ def serving_run(seconds, rate, form):
     reqs = [Request(i, u, t, torch.from_numpy(R).cuda(), R.shape[0], R.shape[1])
             for i, (t, u, R) in enumerate(stream)]
     torch.cuda.synchronize()
-    sch = Scheduler(GpuEngine(P=1024, form=form), P=1024, generations=100, chunk=10,
-                    hbm_budget=8 << 30, form=form)
-    sch.run(reqs)
+    sch = Scheduler(GpuEngine(P=1024, form=form, stall_gens=stall_gens, tol=tol), P=1024, generations=100,
+                    chunk=10, hbm_budget=8 << 30, form=form)
+    res = sch.run(reqs)
     out = sch.summary()
     out.update({"offered_rate_per_s": rate, "stream_seconds": seconds, "form": form,
+                "termination": {"stall_gens": stall_gens, "tol": tol} if stall_gens else None,
                 "workload": "Poisson windows, N in {64,256,1024} 6:3:1 over 16 universes, T=390, "
-                            "P=1024, 100 generations, 5% drift per window"})
+                            "P=1024, up to 100 generations, 5% drift per window"})
+    if stall_gens:
+        out["mean_generations_per_request"] = float(np.mean(_gens_per_request(res)))
+    return out
+
+
+def _gens_per_request(results):
+    """Generations each request ran (the difference of its universe's generation counter)."""
+    last = {}
+    out = []
+    for r in sorted(results, key=lambda r: r.done):
+        out.append(r.gen_end - last.get(r.universe, 0))
+        last[r.universe] = r.gen_end
     return out
 
 
@@ -300,19 +315,43 @@ def main():
 
     # ---- precision: BF16x2 vs FP64 fitness on the same populations
     prec = {}
+    pop0 = torch.from_numpy(synth.random_labelings(P, N, seed=123)).to(dev)
     if "bf16x2" in results and "fp64" in results:
-        I = insts["bf16x2"]
-        f64 = pga.fitness(C, I.pop, "fp64")
-        fbf = pga.fitness(C, I.pop, "bf16x2", hi=hi, lo=lo)
-        rel_final = float(((fbf - f64).abs() / f64.abs().clamp_min(1e-300)).max())
-        pop0 = torch.from_numpy(synth.random_labelings(P, N, seed=123)).to(dev)
-        g64 = pga.fitness(C, pop0, "fp64")
-        gbf = pga.fitness(C, pop0, "bf16x2", hi=hi, lo=lo)
-        rel_init = float(((gbf - g64).abs() / g64.abs().clamp_min(1e-300)).max())
-        same_best = bool(np.array_equal(results["bf16x2"]["labels"], results["fp64"]["labels"]))
-        prec = {"max_rel_err_converged_pop": rel_final, "max_rel_err_random_pop": rel_init,
-                "identical_best_labeling": same_best,
-                "best_Lc": {f: results[f]["best"] for f in results}}
+        def both(pop):
+            f64 = pga.fitness(C, pop, "fp64")
+            fbf = pga.fitness(C, pop, "bf16x2", hi=hi, lo=lo)
+            rel = float(((fbf - f64).abs() / f64.abs().clamp_min(1e-300)).max())
+            l64, _, _ = pga.best(f64, pop)
+            lbf, _, _ = pga.best(fbf, pop)
+            return rel, bool(np.array_equal(l64, lbf))
+        rel_final, same_final = both(insts["bf16x2"].pop)
+        rel_f64run, same_f64run = both(insts["fp64"].pop)
+        rel_init, same_init = both(pop0)
+        prec = {"max_rel_err_converged_pop": max(rel_final, rel_f64run), "max_rel_err_random_pop": rel_init,
+                "same_population_identical_best": same_final and same_f64run,
+                "ga_runs_identical_best": bool(np.array_equal(results["bf16x2"]["labels"],
+                                                              results["fp64"]["labels"])),
+                "best_Lc": {f: results[f]["best"] for f in results},
+                "note": "same_population: each GA run's final population evaluated by both forms, same argmax "
+                        "labeling; ga_runs: the two forms' separate GA runs (trajectories part at near-ties)"}
+
+    # ---- pair-sum time at the random (generation 0) and converged populations, with their mean K
+    def kbar(pop):
+        srt = pop.sort(dim=1).values
+        return float(((srt[:, 1:] != srt[:, :-1]).sum(dim=1) + 1).double().mean())
+    by_pop = {}
+    pga.timing_enable(True)
+    for form in forms:
+        kname = "pairsum_mfma" if form == "bf16x2" else "pairsum_fp64"
+        for tag, pop in (("random", pop0), ("converged", insts[form].pop)):
+            pga.fitness(C, pop, form, hi=hi, lo=lo)
+            pga.timing_reset()
+            for _ in range(5):
+                pga.fitness(C, pop, form, hi=hi, lo=lo)
+            torch.cuda.synchronize()
+            ms, n = pga.timing_read(kname)
+            by_pop.setdefault(form, {})[tag] = {"pairsum_us": 1e3 * ms / n, "mean_K": kbar(pop)}
+    pga.timing_enable(False)
 
     # ---- calibration copy for the HBM counters (plain device-to-device copy of known size)
     nb = args.calib_copy_mib << 20
@@ -372,6 +411,7 @@ def main():
         "other_forms": other,
         "kernels_us": kern,
         "precision": prec,
+        "pairsum_by_population": by_pop,
         "autotune": tuned,
         "roofline": roof,
     }
@@ -381,6 +421,10 @@ def main():
     if args.serve_seconds > 0:
         line["serving"] = serving_run(args.serve_seconds, args.serve_rate, form)
         print(f"[bench] serving: {line['serving']}", file=sys.stderr, flush=True)
+        line["serving_with_termination"] = serving_run(args.serve_seconds, args.serve_rate, form,
+                                                       stall_gens=10, tol=1e-5)
+        print(f"[bench] serving with termination: {line['serving_with_termination']}", file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, P, w.seed)
         line["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}
