@@ -22,7 +22,7 @@
 // with a one-hot of 1.0.
 //
 // The i < j mask is applied only in the chunk that reaches the diagonal. A is
-// loaded once per (wave, chunk), one chunk ahead, and reused by the B (4, 8
+// loaded once per (wave, chunk), two chunks ahead, and reused by the B (4, 8
 // or 16) individuals of the workgroup, whose row codes are staged in LDS
 // 8192 / B rows at a time. FP32 accumulation is flushed into FP64 at every 256-row
 // boundary, so no FP32 partial sum spans more than 256 rows.
@@ -113,10 +113,14 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         }
     };
     // Only waves with jt0 < N load A, and then j < ld for every lane (ld is a
-    // multiple of 32 and jt0 a multiple of 16), so the loads need no guard.
+    // multiple of 32 and jt0 a multiple of 16), so the loads need no guard. The
+    // scaled copies are tile-major (a_tile_offset): the wave's 16 x 32 A block is
+    // 1 KB of consecutive bytes in lane order.
+    const size_t a_row = (size_t)(jt0 >> 4) * (size_t)(ld >> 5);
     auto load_a = [&](int i0, uint4 &ah, uint4 &al) {
-        ah = gld_u4(hs + (size_t)j * ld + i0 + 8 * g);
-        al = gld_u4(ls + (size_t)j * ld + i0 + 8 * g);
+        const size_t off = (a_row + (size_t)(i0 >> 5)) * 512 + (size_t)lane * 8;
+        ah = gld_u4(hs + off);
+        al = gld_u4(ls + off);
     };
     auto chunk = [&](auto masked_tag, int i0, int c0, uint4 ah, uint4 al) {
         constexpr bool masked = decltype(masked_tag)::value;
@@ -155,23 +159,18 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         }
         if (((i0 + 32) % kMfmaFlushRows) == 0) flush();
     };
-    // Chunks [i0, end) of one kind, two per iteration so the prefetch ping-pongs
-    // between (ah, al) and (nh, nl) without register copies; on return the next
-    // chunk's A (if any, below cend) is in (ah, al).
-    auto run = [&](auto masked_tag, int &i0, int end, int cend, int c0, uint4 &ah, uint4 &al) {
-        uint4 nh, nl;
-        while (i0 < end) {
-            if (i0 + 32 < cend) load_a(i0 + 32, nh, nl);
+    // Chunks [i0, end) of one kind; (ah, al) holds the A of chunk i0 and (bh, bl)
+    // the A of i0 + 32, so the loads run two chunks ahead of their use.
+    auto run = [&](auto masked_tag, int &i0, int end, int cend, int c0, uint4 &ah, uint4 &al, uint4 &bh,
+                   uint4 &bl) {
+        for (; i0 < end; i0 += 32) {
+            uint4 nh, nl;
+            if (i0 + 64 < cend) load_a(i0 + 64, nh, nl);
             chunk(masked_tag, i0, c0, ah, al);
-            i0 += 32;
-            if (i0 >= end) {
-                ah = nh;
-                al = nl;
-                return;
-            }
-            if (i0 + 32 < cend) load_a(i0 + 32, ah, al);
-            chunk(masked_tag, i0, c0, nh, nl);
-            i0 += 32;
+            ah = bh;
+            al = bl;
+            bh = nh;
+            bl = nl;
         }
     };
 
@@ -214,12 +213,13 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         __syncthreads();
         const int cend = min(c0 + RC, my_iend);
         if (c0 < cend) {
-            uint4 ah, al;
+            uint4 ah, al, bh, bl;
             load_a(c0, ah, al);
+            if (c0 + 32 < cend) load_a(c0 + 32, bh, bl);
             int i0 = c0;
             const int uend = min(cend, max(c0, i_diag));        // chunks entirely below the diagonal
-            run(std::false_type{}, i0, uend, cend, c0, ah, al);
-            run(std::true_type{}, i0, cend, cend, c0, ah, al);
+            run(std::false_type{}, i0, uend, cend, c0, ah, al, bh, bl);
+            run(std::true_type{}, i0, cend, cend, c0, ah, al, bh, bl);
         }
         __syncthreads();
     }
@@ -289,9 +289,13 @@ hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Vari
 }
 
 // ---- scaled split parts ----------------------------------------------------------
-// hs = hi * 2^125, ls = lo * 2^125, elementwise over the ld x ld split of every
-// instance (blockIdx.y). The scaling is exact: |hi|, |lo| <= 1, so the result
-// is a normal bf16 with the same significand (NaN and infinities stay so).
+// hs = hi * 2^125, ls = lo * 2^125 over the ld x ld split of every instance
+// (blockIdx.y), stored tile-major: the 16 x 32 block of rows 16 tj.. and columns
+// 32 ti.. is 512 consecutive elements at (tj * ld / 32 + ti) * 512, element
+// (16 tj + n, 32 ti + 8 g + e) at (16 g + n) * 8 + e, i.e. in the order the
+// lanes (16 g + n) of the pair-sum wave read them. The scaling is exact:
+// |hi|, |lo| <= 1, so the result is a normal bf16 with the same significand
+// (NaN and infinities stay so).
 __device__ __forceinline__ uint32_t scale2(uint32_t w) {
     const float a = __uint_as_float(w << 16) * 0x1p125f;
     const float b = __uint_as_float(w & 0xFFFF0000u) * 0x1p125f;
@@ -301,13 +305,16 @@ __device__ __forceinline__ uint32_t scale2(uint32_t w) {
 __global__ __launch_bounds__(256) void k_scale_split(Tables t) {
     const InstDesc &d = t.desc[blockIdx.y];
     const size_t n8 = (size_t)d.ld_h * d.ld_h / 8;            // ld is a multiple of 32
+    const size_t ld = (size_t)d.ld_h;
     for (size_t v = (size_t)blockIdx.x * 256 + threadIdx.x; v < n8; v += (size_t)gridDim.x * 256) {
+        const size_t row = 8 * v / ld, col = 8 * v % ld;   // 8 consecutive columns of one row
+        const size_t dst = ((row >> 4) * (ld >> 5) + (col >> 5)) * 512 + ((((col & 31) >> 3) << 4) + (row & 15)) * 8;
         const uint4 h = gld_u4(d.hi + 8 * v);
         const uint4 l = gld_u4(d.lo + 8 * v);
         const pga_u32x4 hs = {scale2(h.x), scale2(h.y), scale2(h.z), scale2(h.w)};
         const pga_u32x4 ls = {scale2(l.x), scale2(l.y), scale2(l.z), scale2(l.w)};
-        *(PGA_GLOBAL pga_u32x4 *)(d.hs + 8 * v) = hs;
-        *(PGA_GLOBAL pga_u32x4 *)(d.ls + 8 * v) = ls;
+        *(PGA_GLOBAL pga_u32x4 *)(d.hs + dst) = hs;
+        *(PGA_GLOBAL pga_u32x4 *)(d.ls + dst) = ls;
     }
 }
 

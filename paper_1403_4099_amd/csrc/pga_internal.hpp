@@ -16,7 +16,7 @@ struct InstDesc {
     int32_t N, P, E, ld_h;
     const double *C;
     const uint16_t *hi, *lo;    // BF16 split parts (ld_h x ld_h)
-    uint16_t *hs, *ls;          // split parts times 2^125 (workspace; BF16x2 form only)
+    uint16_t *hs, *ls;          // split parts times 2^125, tile-major (workspace; BF16x2 form only)
     int32_t *pop[2];            // ping-pong population buffers
     double *fitness;            // P
     double *stats;              // (G + 1) x 4 or null
