@@ -286,14 +286,16 @@ hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, const Vari
 }
 
 // ---------------------------------------------------------------------------
-// Finish: one wave per individual, up to four individuals per workgroup.
+// Finish: one 256-thread workgroup per individual.
 //   1. validity of labels and of v_j; max |v_j| (order-free);
 //   2. n_s and sum_{j in s} v_j by integer LDS atomics, v_j scaled by 2^sc and
 //      rounded to int64 (sc chosen per individual so N max|v| 2^sc < 2^62:
 //      the integer sums are exact and order-free, error <= n_s 2^-(sc+1));
 //   3. per label s with n_s > 1: c_s, domain check, the two FP64 log terms
-//      of Eq. 8 in literal form; per-lane sums in ascending s, then a
-//      butterfly over the wave (a fixed order).
+//      of Eq. 8 in literal form. Wave w owns the labels of the w-th quarter of
+//      [0, N): it lists its labels with n_s > 1 in ascending order (ballot +
+//      prefix), sums the terms per lane in list order and over the wave by a
+//      butterfly; the four wave sums are added in wave order (a fixed order).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -306,50 +308,54 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Per-wave LDS region of the finish kernel: csum (int64), cnt (int32) and the
-// list of non-singleton labels (uint16). Each array is padded to 16 bytes, so
-// every region and every array in it starts 16-byte aligned (64-bit LDS
-// atomics need naturally aligned addresses).
+constexpr int kFinWaves = 4;
+constexpr int kFinThreads = 64 * kFinWaves;
+constexpr int kFinCache = 8;                       // stocks per thread kept in registers (N <= 2048)
+
+// LDS of the finish workgroup: csum (int64) [N], cnt (int32) [N], the label
+// lists (uint16, a quarter of N per wave), then per-wave reduction slots.
+// Arrays are padded to 16 bytes (64-bit LDS atomics need aligned addresses).
 __host__ __device__ __forceinline__ size_t finish_csum_bytes(int max_n) {
     return ((size_t)max_n * sizeof(long long) + 15) / 16 * 16;
 }
 __host__ __device__ __forceinline__ size_t finish_cnt_bytes(int max_n) {
     return ((size_t)max_n * sizeof(int) + 15) / 16 * 16;
 }
-__host__ __device__ __forceinline__ size_t finish_wave_bytes(int max_n) {
-    // csum, cnt, and the list of labels with n_s > 1 (at most max_n / 2 of them, 16-bit since
-    // labels are below PGA_N_MAX): 13.3 KB at N = 1024, so three 4-wave workgroups share a CU
-    return finish_csum_bytes(max_n) + finish_cnt_bytes(max_n) +
-           ((size_t)(max_n / 2 + 1) * sizeof(uint16_t) + 15) / 16 * 16;
+__host__ __device__ __forceinline__ int finish_quarter(int max_n) {
+    return (max_n + kFinWaves - 1) / kFinWaves;
+}
+__host__ __device__ __forceinline__ size_t finish_lst_bytes(int max_n) {
+    return ((size_t)kFinWaves * finish_quarter(max_n) * sizeof(uint16_t) + 15) / 16 * 16;
+}
+__host__ __device__ __forceinline__ size_t finish_lds_bytes(int max_n) {
+    // 14.1 KB at N = 1024 (eight workgroups per CU), 57 KB at N = 4096
+    return finish_csum_bytes(max_n) + finish_cnt_bytes(max_n) + finish_lst_bytes(max_n) +
+           2 * kFinWaves * sizeof(double);
 }
 
-constexpr int kFinCache = 16;
-
-__global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int max_n, int parity,
-                                                int32_t *status) {
+__global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int parity, int32_t *status) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = blockIdx.x * (int)(blockDim.x >> 6) + wave;
-    if (g >= total_inds) return;                     // whole wave leaves; no workgroup barrier below
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
+    const int g = blockIdx.x;
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
-    if (inst_stopped(d)) return;
+    if (inst_stopped(d)) return;                     // uniform over the workgroup
     const int N = d.N;
     const int p = g - t.inds[k];
     const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
     const double *__restrict__ v = d.wsum + (size_t)p * N;
-    unsigned char *base = smem + (size_t)wave * finish_wave_bytes(max_n);
-    long long *csum = (long long *)base;
-    int *cnt = (int *)(base + finish_csum_bytes(max_n));
-    uint16_t *lst = (uint16_t *)(base + finish_csum_bytes(max_n) + finish_cnt_bytes(max_n));
+    long long *csum = (long long *)smem;
+    int *cnt = (int *)(smem + finish_csum_bytes(max_n));
+    uint16_t *lst = (uint16_t *)(smem + finish_csum_bytes(max_n) + finish_cnt_bytes(max_n));
+    double *red = (double *)(smem + finish_csum_bytes(max_n) + finish_cnt_bytes(max_n) + finish_lst_bytes(max_n));
 
-    // The first kFinCache * 64 labels and values stay in registers (all loads issued
-    // together); stocks beyond that are read again in the accumulation pass.
+    // Stocks j = tid + 256 u; the first kFinCache per thread stay in registers (all
+    // loads issued together), later ones are read again in the accumulation pass.
     int lr[kFinCache];
     double vr[kFinCache];
 #pragma unroll
     for (int u = 0; u < kFinCache; ++u) {
-        const int j = lane + 64 * u;
+        const int j = tid + kFinThreads * u;
         lr[u] = j < N ? gld(lab + j) : 0;
         vr[u] = j < N ? gld(v + j) : 0.0;
     }
@@ -361,86 +367,94 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
         if (!isfinite(vr[u])) bad |= 2;
         else mx = fmax(mx, fabs(vr[u]));
     }
-    for (int j = lane + 64 * kFinCache; j < N; j += 64) {
+    for (int j = tid + kFinThreads * kFinCache; j < N; j += kFinThreads) {
         const int l = gld(lab + j);
         if (l < 0 || l >= N) bad |= 1;
         const double x = gld(v + j);
         if (!isfinite(x)) bad |= 2;
         else mx = fmax(mx, fabs(x));
     }
-    const bool any_label = __any(bad & 1);
-    const bool any_nonfinite = __any(bad & 2);
-    mx = wave_max(mx);
-
-    if (any_label || any_nonfinite) {
+    for (int s = tid; s < N; s += kFinThreads) {
+        csum[s] = 0;
+        cnt[s] = 0;
+    }
+    {
+        const double wmx = wave_max(mx);
+        const double wbad = (double)((__any(bad & 1) ? 1 : 0) | (__any(bad & 2) ? 2 : 0));
         if (lane == 0) {
+            red[wave] = wmx;
+            red[kFinWaves + wave] = wbad;
+        }
+    }
+    __syncthreads();
+    int any_bad = 0;
+#pragma unroll
+    for (int w = 0; w < kFinWaves; ++w) {
+        mx = fmax(mx, red[w]);
+        any_bad |= (int)red[kFinWaves + w];
+    }
+    if (any_bad) {
+        if (tid == 0) {
             d.fitness[p] = -INFINITY;
             if (status) {
-                if (any_label) atomicAdd(&status[PGA_ST_LABEL], 1);
+                if (any_bad & 1) atomicAdd(&status[PGA_ST_LABEL], 1);
                 atomicAdd(&status[PGA_ST_NONFINITE], 1);
             }
         }
         if (d.n_s_out)
-            for (int s = lane; s < N; s += 64) d.n_s_out[(size_t)p * N + s] = 0;
+            for (int s = tid; s < N; s += kFinThreads) d.n_s_out[(size_t)p * N + s] = 0;
         if (d.c_s_out)
-            for (int s = lane; s < N; s += 64) d.c_s_out[(size_t)p * N + s] = 0.0;
-        return;
-    }
-
-    for (int s = lane; s < N; s += 64) {
-        csum[s] = 0;
-        cnt[s] = 0;
+            for (int s = tid; s < N; s += kFinThreads) d.c_s_out[(size_t)p * N + s] = 0.0;
+        return;                                      // uniform: any_bad is the same for every thread
     }
     int sc = 0;
     if (mx > 0.0) {
         int e;
-        frexp(mx * (double)N, &e);   // N max|v| < 2^e
+        frexp(mx * (double)N, &e);                   // N max|v| < 2^e
         sc = 61 - e;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
     for (int u = 0; u < kFinCache; ++u) {
-        if (lane + 64 * u < N) {
+        if (tid + kFinThreads * u < N) {
             atomicAdd(&cnt[lr[u]], 1);
             atomicAdd((unsigned long long *)&csum[lr[u]], (unsigned long long)llrint(ldexp(vr[u], sc)));
         }
     }
-    for (int j = lane + 64 * kFinCache; j < N; j += 64) {
+    for (int j = tid + kFinThreads * kFinCache; j < N; j += kFinThreads) {
         const int l = gld(lab + j);
         const long long q = llrint(ldexp(gld(v + j), sc));
         atomicAdd(&cnt[l], 1);
         atomicAdd((unsigned long long *)&csum[l], (unsigned long long)q);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __syncthreads();
 
-    // Pass A: per-label outputs, and the labels with n_s > 1 compacted in ascending order
-    // (wave ballot + prefix), so the log terms below run with every lane busy.
+    // Pass A (wave w, labels [w Q, (w + 1) Q)): per-label outputs, and the labels
+    // with n_s > 1 compacted in ascending order, so the log terms run with every
+    // lane busy.
+    const int QN = finish_quarter(N);                // this instance's quarter; storage is sized by max_n
+    const int s_lo = wave * QN, s_hi = min(N, s_lo + QN);
+    uint16_t *wl = lst + (size_t)wave * finish_quarter(max_n);
     int nlist = 0;
-    for (int s0 = 0; s0 < N; s0 += 64) {
+    for (int s0 = s_lo; s0 < s_hi; s0 += 64) {
         const int s = s0 + lane;
-        const int n = s < N ? cnt[s] : 0;
-        if (s < N) {
+        const int n = s < s_hi ? cnt[s] : 0;
+        if (s < s_hi) {
             if (d.n_s_out) gst(d.n_s_out + (size_t)p * N + s, n);
             if (d.c_s_out) gst(d.c_s_out + (size_t)p * N + s, ldexp((double)csum[s], -sc));
         }
         const uint64_t m = __ballot(n > 1);
-        if (n > 1) lst[nlist + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)s;
+        if (n > 1) wl[nlist + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)s;
         nlist += __popcll(m);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // Pass B: the two FP64 log terms of Eq. 8 for each listed cluster; per-lane sums in list
-    // order, then a butterfly over the wave (a fixed order).
+    // Pass B: the two FP64 log terms of Eq. 8 for each listed cluster.
     double L = 0.0;
     int nbad = 0;
     for (int m = lane; m < nlist; m += 64) {
-        const int s = lst[m];
+        const int s = wl[m];
         const double nd = (double)cnt[s];
         const double c = ldexp((double)csum[s], -sc);
         const double n2 = nd * nd;
@@ -450,9 +464,21 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
             L += log(nd / c) + (nd - 1.0) * log((n2 - nd) / (n2 - c));
         }
     }
-    const double Ltot = wave_sum(L);
-    const double badtot = wave_sum((double)nbad);
-    if (lane == 0) {
+    {
+        const double wl_sum = wave_sum(L);
+        const double wb_sum = wave_sum((double)nbad);
+        if (lane == 0) {
+            red[wave] = wl_sum;                      // every read of red above precedes the
+            red[kFinWaves + wave] = wb_sum;          // barrier that closed the atomics
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double Ltot = 0.0, badtot = 0.0;
+        for (int w = 0; w < kFinWaves; ++w) {
+            Ltot += red[w];
+            badtot += red[kFinWaves + w];
+        }
         if (badtot > 0.0) {
             d.fitness[p] = -INFINITY;
             if (status) {
@@ -468,12 +494,8 @@ __global__ __launch_bounds__(256) void k_finish(Tables t, int total_inds, int ma
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status,
                          hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
-    // one wave per individual; as many waves per workgroup as fit in 64 KB of LDS (at most 4)
-    const size_t per_wave = finish_wave_bytes(max_n);
-    int wpg = (int)((64u << 10) / per_wave);
-    wpg = wpg < 1 ? 1 : wpg > 4 ? 4 : wpg;
-    hipLaunchKernelGGL(k_finish, dim3((total_inds + wpg - 1) / wpg), dim3(64 * wpg), per_wave * wpg, s, t,
-                       total_inds, max_n, parity, status);
+    hipLaunchKernelGGL(k_finish, dim3(total_inds), dim3(kFinThreads), finish_lds_bytes(max_n), s, t, max_n,
+                       parity, status);
     return hipGetLastError();
 }
 

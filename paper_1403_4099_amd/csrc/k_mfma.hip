@@ -24,11 +24,16 @@
 // The i < j mask is applied only in the chunk that reaches the diagonal. A is
 // loaded once per (wave, chunk), two chunks ahead, and reused by the B (4, 8
 // or 16) individuals of the workgroup, whose row codes are staged in LDS
-// 8192 / B rows at a time. FP32 accumulation is flushed into FP64 at every 256-row
+// 8192 / B rows at a time. In a chunk the 16 lanes of a row group need the
+// same 8 row codes per individual; instead of 16 identical LDS reads, each
+// lane reads B/4 different dwords (two row codes each) and the xor takes its
+// row operand from the lane that holds it (DPP row broadcast), so a chunk
+// costs one B*64-byte LDS read per wave. FP32 accumulation is flushed into FP64 at every 256-row
 // boundary, so no FP32 partial sum spans more than 256 rows.
 #include "pga_internal.hpp"
 
 #include <type_traits>
+#include <utility>
 
 namespace pga {
 
@@ -47,10 +52,31 @@ __device__ __forceinline__ uint32_t onehot2(uint32_t rows2, uint32_t col2) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(one, x));
 }
 
-// LDS of one workgroup (dynamic): row codes [B][kMfmaRowCodes / B] (16-bit,
-// shifted), then the label -> code tables [B][cstride] (bytes, cstride >= N).
+// Row codes in the xor of lane t of a row group come from lane T of that
+// group (DPP row broadcast; T a compile-time constant).
+template <int T>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + T, 0xF, 0xF, false);
+}
+
+template <int... I, typename F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &&f) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+// Position of individual b's dword within a staged row pair: lane t of a row
+// group reads positions (B/4)(t/4) .. +B/4-1, i.e. individuals t/4, t/4 + 4, ...
+template <int B>
+__host__ __device__ constexpr int mfma_pos(int b) {
+    return (B / 4) * (b & 3) + (b >> 2);
+}
+
+// LDS of one workgroup (dynamic): row codes, kMfmaRowCodes 16-bit words (the
+// code shifted into bits 8..15), as dwords [row pair][mfma_pos(b)] holding the
+// rows 2q (low half) and 2q + 1 of individual b; then the label -> code
+// tables [B][cstride] (bytes, cstride >= N).
 struct MfmaLds {
-    uint16_t *rows;
+    uint32_t *rows;
     uint8_t *code;
     int cstride;
 };
@@ -72,7 +98,6 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
     const uint16_t *__restrict__ hs = d.hs;
     const uint16_t *__restrict__ ls = d.ls;
     auto code = [&](int b, int l) -> uint8_t & { return s.code[(size_t)b * s.cstride + l]; };
-    auto rowc = [&](int b, int r) -> uint16_t * { return s.rows + (size_t)b * RC + r; };
 
     // Column labels; lanes with g == 0 register them in the code table.
     int32_t lj[B];
@@ -122,7 +147,24 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         ah = gld_u4(hs + off);
         al = gld_u4(ls + off);
     };
-    auto chunk = [&](auto masked_tag, int i0, int c0, uint4 ah, uint4 al) {
+    // Lane t of row group g reads, into R[k], rows i0 + 8g + 2(t%4), +1 of individual 4k + t/4.
+    auto read_r = [&](int i0, int c0, uint32_t (&R)[B / 4]) {
+        const uint32_t *rp = s.rows + (size_t)(((i0 - c0) >> 1) + 4 * g + (n & 3)) * B + (B / 4) * (n >> 2);
+        if constexpr (B == 4) {
+            R[0] = *rp;
+        } else if constexpr (B == 8) {
+            const uint2 q2 = *(const uint2 *)rp;
+            R[0] = q2.x;
+            R[1] = q2.y;
+        } else {
+            const uint4 q4 = *(const uint4 *)rp;
+            R[0] = q4.x;
+            R[1] = q4.y;
+            R[2] = q4.z;
+            R[3] = q4.w;
+        }
+    };
+    auto chunk = [&](auto masked_tag, int i0, int c0, uint4 ah, uint4 al, const uint32_t (&R)[B / 4]) {
         constexpr bool masked = decltype(masked_tag)::value;
         const int ik = i0 + 8 * g;                            // first of this lane's 8 rows
         uint32_t m[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
@@ -133,32 +175,33 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         }
         const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah);
         const bf16x8 Al = __builtin_bit_cast(bf16x8, al);
-#pragma unroll
-        for (int b = 0; b < B; b += 2) {
-            const uint4 l0 = *(const uint4 *)rowc(b, ik - c0);
-            const uint4 l1 = *(const uint4 *)rowc(b + 1, ik - c0);
-            uint4 v0, v1;
-            v0.x = onehot2(l0.x, col2[b]);
-            v0.y = onehot2(l0.y, col2[b]);
-            v0.z = onehot2(l0.z, col2[b]);
-            v0.w = onehot2(l0.w, col2[b]);
-            v1.x = onehot2(l1.x, col2[b + 1]);
-            v1.y = onehot2(l1.y, col2[b + 1]);
-            v1.z = onehot2(l1.z, col2[b + 1]);
-            v1.w = onehot2(l1.w, col2[b + 1]);
+        // B column of individual b: its dword e (rows ik + 2e, +1) is in R[b/4] of lane 4(b%4) + e.
+        auto bcol = [&](auto bc) -> bf16x8 {
+            constexpr int b = decltype(bc)::value;
+            constexpr int t = 4 * (b & 3);
+            uint4 v;
+            v.x = onehot2(row_bcast<t + 0>(R[b >> 2]), col2[b]);
+            v.y = onehot2(row_bcast<t + 1>(R[b >> 2]), col2[b]);
+            v.z = onehot2(row_bcast<t + 2>(R[b >> 2]), col2[b]);
+            v.w = onehot2(row_bcast<t + 3>(R[b >> 2]), col2[b]);
             if constexpr (masked) {
-                v0.x &= m[0]; v0.y &= m[1]; v0.z &= m[2]; v0.w &= m[3];
-                v1.x &= m[0]; v1.y &= m[1]; v1.z &= m[2]; v1.w &= m[3];
+                v.x &= m[0]; v.y &= m[1]; v.z &= m[2]; v.w &= m[3];
             }
-            const bf16x8 B0 = __builtin_bit_cast(bf16x8, v0);
-            const bf16x8 B1 = __builtin_bit_cast(bf16x8, v1);
+            return __builtin_bit_cast(bf16x8, v);
+        };
+        static_for(std::make_integer_sequence<int, B / 2>{}, [&](auto hb) {
+            constexpr int b = 2 * decltype(hb)::value;
+            const bf16x8 B0 = bcol(std::integral_constant<int, b>{});
+            const bf16x8 B1 = bcol(std::integral_constant<int, b + 1>{});
             acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B0, acc[b], 0, 0, 0);
             acc[b + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B1, acc[b + 1], 0, 0, 0);
             acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B0, acc[b], 0, 0, 0);
             acc[b + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B1, acc[b + 1], 0, 0, 0);
-        }
+        });
         if (((i0 + 32) % kMfmaFlushRows) == 0) flush();
     };
+    // Chunks [i0, end) of one kind; (ah, al) holds the A of chunk i0 and (bh, bl)
+    // the A of i0 + 32, so the loads run two chunks ahead of their use.
     // Chunks [i0, end) of one kind; (ah, al) holds the A of chunk i0 and (bh, bl)
     // the A of i0 + 32, so the loads run two chunks ahead of their use.
     auto run = [&](auto masked_tag, int &i0, int end, int cend, int c0, uint4 &ah, uint4 &al, uint4 &bh,
@@ -166,7 +209,9 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         for (; i0 < end; i0 += 32) {
             uint4 nh, nl;
             if (i0 + 64 < cend) load_a(i0 + 64, nh, nl);
-            chunk(masked_tag, i0, c0, ah, al);
+            uint32_t R[B / 4];
+            read_r(i0, c0, R);
+            chunk(masked_tag, i0, c0, ah, al, R);
             ah = bh;
             al = bl;
             bh = nh;
@@ -181,33 +226,43 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
     for (int c0 = 0; c0 < wg_iend; c0 += RC) {
         const int rows = min(RC, wg_iend - c0);
         const int rows32 = (rows + 31) & ~31;                 // chunks read whole 32-row groups
-        // Thread t stages rows t + 256k of every individual: all RK * B labels are
-        // loaded before the first table lookup, so the pass costs one memory latency.
-        constexpr int RK = RC / 256;
-        int32_t lab[RK][B];
+        // Thread t stages row pairs t + 256k of every individual: all 2 * PK * B
+        // labels are loaded before the first table lookup, so the pass costs one
+        // memory latency; each row pair is written as B consecutive dwords.
+        constexpr int PK = RC / 512;
+        int32_t lab[PK][2][B];
 #pragma unroll
-        for (int k = 0; k < RK; ++k) {
-            const int r = threadIdx.x + 256 * k;
+        for (int k = 0; k < PK; ++k) {
+            const int r = 2 * (threadIdx.x + 256 * k);
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 const int p = pbase + b;
-                lab[k][b] = (r < rows && p < P) ? gld(labels + (size_t)p * N + c0 + r) : -1;
+                const int32_t *lp = labels + (size_t)p * N + c0 + r;
+                lab[k][0][b] = (r < rows && p < P) ? gld(lp) : -1;
+                lab[k][1][b] = (r + 1 < rows && p < P) ? gld(lp + 1) : -1;
             }
         }
 #pragma unroll
-        for (int k = 0; k < RK; ++k)                          // all table reads (index clamped, in range), then all writes
+        for (int k = 0; k < PK; ++k)                          // all table reads (index clamped, in range), then all writes
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const bool ok = (uint32_t)lab[k][b] < (uint32_t)N;
-                const int32_t c = code(b, ok ? lab[k][b] : 0);
-                lab[k][b] = ok ? c : (int32_t)kCodeNone;
-            }
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int k = 0; k < RK; ++k) {
-            const int r = threadIdx.x + 256 * k;
-            if (r < rows32) {
+                for (int b = 0; b < B; ++b) {
+                    const bool ok = (uint32_t)lab[k][h][b] < (uint32_t)N;
+                    const int32_t c = code(b, ok ? lab[k][h][b] : 0);
+                    lab[k][h][b] = ok ? c : (int32_t)kCodeNone;
+                }
 #pragma unroll
-                for (int b = 0; b < B; ++b) *rowc(b, r) = (uint16_t)(lab[k][b] << kCodeShift);
+        for (int k = 0; k < PK; ++k) {
+            const int q = threadIdx.x + 256 * k;
+            if (2 * q < rows32) {
+                uint32_t w[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+                    w[mfma_pos<B>(b)] = ((uint32_t)lab[k][0][b] << kCodeShift) | ((uint32_t)lab[k][1][b] << (16 + kCodeShift));
+#pragma unroll
+                for (int v = 0; v < B / 4; ++v)
+                    *(uint4 *)(s.rows + (size_t)q * B + 4 * v) = uint4{w[4 * v], w[4 * v + 1], w[4 * v + 2], w[4 * v + 3]};
             }
         }
         __syncthreads();
@@ -255,7 +310,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int n_pairs = (n_jb + 1) / 2;
     const TilePos tp = tile_pos(local, n_pairs, (d.P + B - 1) / B, order);
     const int jp = tp.jp, pb = tp.pb;
-    const MfmaLds s{(uint16_t *)lds, lds + sizeof(uint16_t) * kMfmaRowCodes, cstride};
+    const MfmaLds s{(uint32_t *)lds, lds + sizeof(uint16_t) * kMfmaRowCodes, cstride};
     {
         const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
         for (int e = threadIdx.x; e < B * words; e += 256) {
