@@ -109,24 +109,30 @@ __global__ __launch_bounds__(kRankThreads) void k_rank(Tables t, int gen_off, in
     __shared__ double wf[kRankWaves];
     __shared__ int wi[kRankWaves];
     const InstDesc &d = t.desc[blockIdx.x];
-    if (d.term) {
-        const bool stopped = inst_stopped(d);
-        __syncthreads();                                   // every thread has read the flag
-        if (gen_off == 0 && threadIdx.x == 0) gst(&d.term->call_gens, 0);
-        if (stopped) return;
-    }
     const int P = d.P, E = d.E;
     const double *__restrict__ f = d.fitness;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (d.selection == PGA_SELECT_SUS)                     // the SUS rank kernel adds into these
-        for (int p = threadIdx.x; p < P; p += kRankThreads) gst(d.sus_rank + p, 1);
-
+    // The fitness values, the stop flag and (thread 0) the termination state are
+    // all requested before any of them is used.
     double fr[kRankCache];
 #pragma unroll
     for (int v = 0; v < kRankCache; ++v) {
         const int p = threadIdx.x + v * kRankThreads;
         fr[v] = p < P ? gld(f + p) : -INFINITY;
     }
+    pga_term_state st{};
+    if (d.term) {
+        const bool stopped = inst_stopped(d);
+        if (threadIdx.x == 0) st = *d.term;
+        __syncthreads();                                   // every thread has read the flag
+        if (gen_off == 0 && threadIdx.x == 0) {
+            gst(&d.term->call_gens, 0);
+            st.call_gens = 0;
+        }
+        if (stopped) return;
+    }
+    if (d.selection == PGA_SELECT_SUS)                     // the SUS rank kernel adds into these
+        for (int p = threadIdx.x; p < P; p += kRankThreads) gst(d.sus_rank + p, 1);
 
     auto block_best = [&](Cand c) -> Cand {
         c = wave_best(c);
@@ -170,17 +176,20 @@ __global__ __launch_bounds__(kRankThreads) void k_rank(Tables t, int gen_off, in
 
     Cand prev{0.0, -1};
     int argbest = 0;
+    double fbest = -INFINITY;
     const int rounds = E > 1 ? E : 1;
     for (int r = 0; r < rounds; ++r) {
         const Cand b = block_best(thread_best(prev));
-        if (r == 0) argbest = b.i;
+        if (r == 0) {
+            argbest = b.i;
+            fbest = b.f;
+        }
         if (r < E && threadIdx.x == 0) d.elite[r] = b.i;
         prev = b;
     }
     if (d.term && threadIdx.x == 0) {
         // termination test on this generation's best; count the generation about to be bred
-        pga_term_state st = *d.term;
-        const double b = gld(f + argbest);
+        const double b = fbest;
         const bool improved = isfinite(st.ref) ? (b > st.ref + d.tol * fmax(1.0, fabs(st.ref))) : isfinite(b);
         if (improved) {
             st.ref = b;
@@ -214,7 +223,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank(Tables t, int gen_off, in
         if (threadIdx.x == 0) {
             double *row = d.stats + 4 * (size_t)gen_off;
             const double nfin = (double)P - inv;
-            row[0] = gld(f + argbest);
+            row[0] = fbest;
             row[1] = nfin > 0.0 ? total / nfin : -INFINITY;
             row[2] = inv;
             row[3] = (double)argbest;

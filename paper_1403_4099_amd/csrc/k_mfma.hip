@@ -74,10 +74,13 @@ __host__ __device__ constexpr int mfma_pos(int b) {
 // LDS of one workgroup (dynamic): row codes, kMfmaRowCodes 16-bit words (the
 // code shifted into bits 8..15), as dwords [row pair][mfma_pos(b)] holding the
 // rows 2q (low half) and 2q + 1 of individual b; then the label -> code
-// tables [B][cstride] (bytes, cstride >= N).
+// tables [B][cstride] (bytes, cstride >= N); then the FP64 partial sums
+// [wave][B][lane] (kept in LDS rather than registers: they change only once
+// per 256 rows, and the registers they free let more waves share a SIMD).
 struct MfmaLds {
     uint32_t *rows;
     uint8_t *code;
+    double *acc64;
     int cstride;
 };
 
@@ -120,11 +123,11 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
     }
 
     floatx4 acc[B];
-    double acc64[B];
+    double *acc64 = s.acc64 + (size_t)wave * B * 64 + lane;  // individual b at acc64[64 b]
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
-        acc64[b] = 0.0;
+        acc64[64 * b] = 0.0;
     }
     const int dreg = n & 3;                                   // lane holds D[n][n] in register n & 3 ...
     const bool diag_lane = (n >> 2) == g;                     // ... when its 4-row group contains row n
@@ -133,7 +136,7 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const float v = dreg == 0 ? acc[b][0] : dreg == 1 ? acc[b][1] : dreg == 2 ? acc[b][2] : acc[b][3];
-            acc64[b] += (double)v;
+            acc64[64 * b] += (double)v;
             acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
     };
@@ -284,7 +287,7 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int p = pbase + b;
-            if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[b], cjj));
+            if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[64 * b], cjj));
         }
     }
     // Restore the table (every reader passed the barrier that closes the row loop).
@@ -310,7 +313,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int n_pairs = (n_jb + 1) / 2;
     const TilePos tp = tile_pos(local, n_pairs, (d.P + B - 1) / B, order);
     const int jp = tp.jp, pb = tp.pb;
-    const MfmaLds s{(uint32_t *)lds, lds + sizeof(uint16_t) * kMfmaRowCodes, cstride};
+    const MfmaLds s{(uint32_t *)lds, lds + sizeof(uint16_t) * kMfmaRowCodes,
+                    (double *)(lds + sizeof(uint16_t) * kMfmaRowCodes + (size_t)B * cstride), cstride};
     {
         const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
         for (int e = threadIdx.x; e < B * words; e += 256) {
