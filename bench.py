@@ -335,30 +335,76 @@ def main():
                 "note": "same_population: each GA run's final population evaluated by both forms, same argmax "
                         "labeling; ga_runs: the two forms' separate GA runs (trajectories part at near-ties)"}
 
-    # ---- pair-sum time at the random (generation 0) and converged populations, with their mean K
+    # ---- pga_fitness on a resident population: median of 20 timed calls after 3 warm-ups (HIP
+    # events on the calling stream), at the random (generation 0) and converged populations, with
+    # the pair-sum kernel's own time (library timing, same calls) and the population's mean K
     def kbar(pop):
         srt = pop.sort(dim=1).values
         return float(((srt[:, 1:] != srt[:, :-1]).sum(dim=1) + 1).double().mean())
     by_pop = {}
-    pga.timing_enable(True)
     for form in forms:
         kname = "pairsum_mfma" if form == "bf16x2" else "pairsum_fp64"
         for tag, pop in (("random", pop0), ("converged", insts[form].pop)):
-            pga.fitness(C, pop, form, hi=hi, lo=lo)
+            for _ in range(3):
+                pga.fitness(C, pop, form, hi=hi, lo=lo)
+            torch.cuda.synchronize()
+            calls = []
+            for _ in range(20):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                pga.fitness(C, pop, form, hi=hi, lo=lo)
+                e1.record()
+                torch.cuda.synchronize()
+                calls.append(e0.elapsed_time(e1) * 1e-3)
+            pga.timing_enable(True)
             pga.timing_reset()
             for _ in range(5):
                 pga.fitness(C, pop, form, hi=hi, lo=lo)
             torch.cuda.synchronize()
             ms, n = pga.timing_read(kname)
-            by_pop.setdefault(form, {})[tag] = {"pairsum_us": 1e3 * ms / n, "mean_K": kbar(pop)}
-    pga.timing_enable(False)
+            pga.timing_enable(False)
+            t_call = float(np.median(calls))
+            t_ps = 1e-3 * ms / n
+            if form == "bf16x2":
+                frac = mfma_issued_flops(N, P, tuned[form]["individuals_per_group"]) / t_ps / 1e12 / PEAK_MFMA_BF16
+            else:
+                frac = 2 * pair_visits(N, P) / t_ps / 1e12 / PEAK_ALU
+            by_pop.setdefault(form, {})[tag] = {
+                "fitness_call_us": 1e6 * t_call, "fitness_evals_per_s": P / t_call,
+                "pair_equivalent_per_s": pair_visits(N, P) / t_call,
+                "pairsum_us": 1e6 * t_ps, "pairsum_roofline_frac": frac, "mean_K": kbar(pop)}
 
-    # ---- calibration copy for the HBM counters (plain device-to-device copy of known size)
+    # ---- the generation loop: wall time per generation minus the kernels it runs
+    loop = {}
+    for f in results:
+        kk = kern.get(f, {})
+        per_gen_us = 1e6 * results[f]["wall_s"] / (args.steps * G)
+        ksum = sum(kk[k]["avg_us"] for k in ("pairsum_mfma" if f == "bf16x2" else "pairsum_fp64", "finish",
+                                              "rank", "breed") if k in kk)
+        loop[f] = {"wall_us_per_generation": per_gen_us, "kernel_us_per_generation": ksum,
+                   "note": "wall includes correlate, split, init and best once per step; kernel times are "
+                           "eager launches with events, slightly above their graph-replay durations"}
+
+    # ---- calibration copy for the HBM counters (plain device-to-device copy of known size), timed
+    # as the measured HBM ceiling (read + write bytes over the best of 5 copies), and the measured
+    # bf16 MFMA ceiling (the library's register-operand MFMA loop)
     nb = args.calib_copy_mib << 20
     a = torch.empty(nb, dtype=torch.uint8, device=dev)
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
+    t_copy = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        t_copy = min(t_copy, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    peaks = {"hbm_copy_GBps": 2 * nb / t_copy / 1e9, "mfma_bf16_TFLOPs": pga.peak_mfma_bf16(),
+             "published": {"hbm_GBps": 8000.0, "mfma_bf16_TFLOPs": PEAK_MFMA_BF16, "alu_Tops": PEAK_ALU},
+             "note": "sustained rates measured on this GPU; roofline.frac uses the published peak"}
 
     form = args.form
     res = results[form]
@@ -379,6 +425,8 @@ def main():
                 "frac": achieved / PEAK_ALU, "traffic": recorded_traffic(src, N, P, tuned[form]["variant"]),
                 "kernel": "k_pairsum_fp64", "avg_launch_us": k["avg_us"],
                 "work_per_launch": "2 ops (label compare, FP64 add) per unordered pair per individual"}
+    if form == "bf16x2":
+        roof["frac_of_measured_peak"] = achieved / peaks["mfma_bf16_TFLOPs"]
     other = {}
     for f in results:
         if f == form:
@@ -411,7 +459,9 @@ def main():
         "other_forms": other,
         "kernels_us": kern,
         "precision": prec,
-        "pairsum_by_population": by_pop,
+        "fitness_call": by_pop,
+        "generation_loop": loop,
+        "peaks_measured": peaks,
         "autotune": tuned,
         "roofline": roof,
     }

@@ -283,6 +283,16 @@ int pga_timing_enable(int on);
 int pga_timing_reset(void);
 int pga_timing_read(int kernel_id, double *total_ms, int64_t *count);
 
+/* Measurement aid (not part of the method): sustained bf16 MFMA throughput.
+ * Launches n_workgroups x 256 threads; every wave issues iters rounds of 16
+ * independent v_mfma_f32_16x16x32_bf16 on register operands and writes one
+ * float per wave to out (device, caller-owned, 4 * n_workgroups floats; the
+ * values only keep the work from being removed). *flops (host, may be NULL)
+ * receives the issued flops, n_workgroups * 4 * iters * 16 * 16384; the caller
+ * times the launch with events on `stream`. PGA_ERR_ARG for out == NULL,
+ * n_workgroups < 1 or iters < 1. Async. */
+int pga_peak_mfma_bf16(float *out, int32_t n_workgroups, int32_t iters, double *flops, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -223,6 +223,12 @@ struct pga_ctx {
     std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
+// Measured-ceiling kernel (k_peaks.hip), outside the method's kernels.
+namespace pga {
+hipError_t launch_peak_mfma(float *out, int n_workgroups, int iters, hipStream_t s);
+double peak_mfma_flops(int n_workgroups, int iters);
+}  // namespace pga
+
 extern "C" {
 
 int pga_ctx_create(pga_ctx **out) {
@@ -709,6 +715,13 @@ int pga_timing_reset(void) {
         g_tcnt[i] = 0;
     }
     return rc;
+}
+
+int pga_peak_mfma_bf16(float *out, int32_t n_workgroups, int32_t iters, double *flops, void *stream) {
+    if (!out || n_workgroups < 1 || iters < 1) return PGA_ERR_ARG;
+    if (flops) *flops = pga::peak_mfma_flops(n_workgroups, iters);
+    HIP_TRY(pga::launch_peak_mfma(out, n_workgroups, iters, (hipStream_t)stream));
+    return PGA_OK;
 }
 
 int pga_timing_read(int kernel_id, double *total_ms, int64_t *count) {

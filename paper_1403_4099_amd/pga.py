@@ -40,7 +40,7 @@ SYMBOLS = [
     "pga_fitness_ws_bytes", "pga_fitness", "pga_evolve_ws_bytes", "pga_evolve",
     "pga_best_ws_bytes", "pga_best", "pga_timing_enable", "pga_timing_reset", "pga_timing_read",
     "pga_variant_count", "pga_variant_info", "pga_tune_ws_bytes", "pga_tune", "pga_tune_set",
-    "pga_tune_get", "pga_ewma_ws_bytes", "pga_ewma",
+    "pga_tune_get", "pga_ewma_ws_bytes", "pga_ewma", "pga_peak_mfma_bf16",
 ]
 
 
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "pga_tune_get": ([i32, i32, i32], ct.c_int),
         "pga_ewma_ws_bytes": ([i32, i32], sz),
         "pga_ewma": ([vp, i32, i32, i32, ct.c_double, i32, vp, vp, vp, vp, vp, vp, sz, vp], ct.c_int),
+        "pga_peak_mfma_bf16": ([vp, i32, i32, ct.POINTER(ct.c_double), vp], ct.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -393,6 +394,27 @@ def best(fitness_t: torch.Tensor, labels: torch.Tensor):
                     ct.byref(f), ct.byref(idx), _ptr(ws), ws.numel(), _stream())
     _check(rc, "pga_best")
     return out, f.value, idx.value
+
+
+# ---------------------------------------------------------------- measured ceiling
+def peak_mfma_bf16(n_workgroups: int = 4096, iters: int = 1000, reps: int = 5) -> float:
+    """Sustained bf16 MFMA throughput in TFLOP/s (best of `reps` timed launches of the library's
+    register-operand MFMA loop on the current stream)."""
+    out = torch.empty(4 * n_workgroups, dtype=torch.float32, device="cuda")
+    flops = ct.c_double()
+    L = load()
+    _check(L.pga_peak_mfma_bf16(_ptr(out), n_workgroups, iters, ct.byref(flops), _stream()), "pga_peak_mfma_bf16")
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _check(L.pga_peak_mfma_bf16(_ptr(out), n_workgroups, iters, None, _stream()), "pga_peak_mfma_bf16")
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    if not bool(torch.isfinite(out).all()):
+        raise PgaError("pga_peak_mfma_bf16: non-finite sink values")
+    return flops.value / best / 1e12
 
 
 # ---------------------------------------------------------------- timing

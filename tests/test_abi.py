@@ -125,3 +125,13 @@ def test_workspace_sizes(lib):
     assert lib.pga_correlate_ws_bytes(100) >= 1600
     assert lib.pga_best_ws_bytes(18) >= 19 * 4
     assert lib.pga_strerror(-2).decode().startswith("workspace")
+
+
+def test_peak_mfma_rejects_bad_arguments():
+    """The measurement aid checks its arguments before touching the GPU."""
+    L = pga.load()
+    flops = ct.c_double()
+    assert L.pga_peak_mfma_bf16(None, 1, 1, ct.byref(flops), None) == -1  # PGA_ERR_ARG
+    buf = ct.create_string_buffer(64)
+    assert L.pga_peak_mfma_bf16(ct.cast(buf, ct.c_void_p), 0, 1, None, None) == -1  # PGA_ERR_ARG
+    assert L.pga_peak_mfma_bf16(ct.cast(buf, ct.c_void_p), 1, 0, None, None) == -1  # PGA_ERR_ARG
