@@ -208,11 +208,15 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
  *
  * pga_variant_count: number of variants of `form` (PGA_ERR_ARG for a bad form).
  * pga_variant_info: individuals per group and XCD ordering of one variant.
- * pga_tune (SYNC): times every variant that fits N on `labels` (P x N, device)
- *   with `reps` evaluations after one warm-up, each timed by HIP events on
- *   `stream`; stores the fastest in the table and returns it in out_variant;
- *   out_ms (nullable, pga_variant_count(form) floats, host) receives the
- *   mean milliseconds per evaluation, -1 for variants that do not fit.
+ * pga_tune (SYNC): times every variant that fits N on `labels` (P x N, device):
+ *   after 2 reps + 2 warm-up evaluations, three rounds in which each variant
+ *   in turn runs `reps` evaluations, all back to back on `stream` and timed
+ *   by HIP events (the GPU's clock rises under load, so no variant gains from
+ *   its place in the order); stores the fastest in the table (the lowest
+ *   variant index among those within 1% of the fastest) and returns it in
+ *   out_variant; out_ms (nullable, pga_variant_count(form) floats, host)
+ *   receives each variant's best round in milliseconds per evaluation, -1 for
+ *   variants that do not fit.
  *   Workspace: pga_tune_ws_bytes(N, P, form). Errors as pga_fitness.
  * pga_tune_set: sets (variant >= 0) or clears (-1) the table entry.
  * pga_tune_get: the variant a call with this (form, N, P) would use. */

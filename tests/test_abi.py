@@ -97,7 +97,9 @@ def test_variant_table_host_side(lib):
     assert lib.pga_variant_count(0) >= 2 and lib.pga_variant_count(1) >= 2
     assert lib.pga_variant_count(7) == -1
     ipg, xcd = ct.c_int32(), ct.c_int32()
-    assert lib.pga_variant_info(1, 0, ct.byref(ipg), ct.byref(xcd)) == 0 and xcd.value == 0
+    # variant 0 (the default) deals tiles to the XCDs in contiguous ranges, column pairs fastest
+    assert lib.pga_variant_info(1, 0, ct.byref(ipg), ct.byref(xcd)) == 0 and xcd.value == 1 and ipg.value == 8
+    assert lib.pga_variant_info(0, 0, ct.byref(ipg), ct.byref(xcd)) == 0 and xcd.value == 1 and ipg.value == 8
     assert lib.pga_variant_info(1, lib.pga_variant_count(1), None, None) == -1
     assert lib.pga_tune_get(1, 1024, 4096) == 0
     assert lib.pga_tune_set(1, 1024, 4096, 2) == 0
