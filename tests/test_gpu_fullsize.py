@@ -1,0 +1,108 @@
+"""Parity at the benchmark's full size: N = 1024 stocks, T = 4096 returns, P = 4096 labelings,
+in the launch configuration bench.py times (variant 0, the tuner's choice at this shape).
+
+* pga_correlate of the full window against the oracle's correlation;
+* every individual's n_s, and sampled individuals' c_s and L_c, against the oracle, in both
+  forms (the oracle computes the sampled individuals one by one);
+* one generation of the whole population in lockstep with the oracle: the oracle breeds from the
+  GPU's population and fitness, and the GPU's next population must match bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1403_4099_amd import pga, synth
+from gpu_cases import bf16_emulated, cs_bound_fp32, fitness_tol, l_bound_from_cs, say
+
+pytestmark = pytest.mark.gpu
+
+N, T, P = 1024, 4096, 4096
+N_SAMPLE = 48
+
+
+def _g(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def full():
+    say(f"full-size inputs N={N} T={T} P={P}")
+    w = synth.config3(N=N, T=T)
+    C = O.correlate(w.R)
+    # random labelings (generation 0) and labelings near the planted partition (a converged GA)
+    pop = synth.random_labelings(P, N, seed=11)
+    pop[P // 2:] = synth.perturbed_labelings(w.planted, P - P // 2, 0.05, seed=12)
+    rng = np.random.default_rng(13)
+    sample = np.sort(np.concatenate([rng.choice(P // 2, N_SAMPLE // 2, replace=False),
+                                     P // 2 + rng.choice(P - P // 2, N_SAMPLE // 2, replace=False)]))
+    return w, C, pop, sample
+
+
+@pytest.fixture()
+def variant0():
+    for form in ("fp64", "bf16x2"):
+        pga.tune_set(form, N, P, 0)
+    yield
+    for form in ("fp64", "bf16x2"):
+        pga.tune_set(form, N, P, -1)
+
+
+def test_correlate_full_window(full):
+    w, C, _, _ = full
+    Cg = pga.correlate(_g(w.R)).cpu().numpy()
+    assert np.max(np.abs(Cg - C)) <= 1e-12
+    assert np.array_equal(Cg, Cg.T) and np.all(np.diag(Cg) == 1.0)
+
+
+def test_fitness_fp64_full_population(full, variant0):
+    _, C, pop, sample = full
+    f_g, ns_g, cs_g = pga.fitness(_g(C), _g(pop), "fp64", want_ns=True, want_cs=True)
+    f_g, ns_g, cs_g = f_g.cpu().numpy(), ns_g.cpu().numpy(), cs_g.cpu().numpy()
+    # n_s of every individual is integer counting: bit-exact
+    ns_all = np.stack([np.bincount(row, minlength=N) for row in pop]).astype(np.int32)
+    assert np.array_equal(ns_g, ns_all)
+    f_o, ns_o, cs_o, mag = O.fitness(C, pop[sample], want_ns=True, want_cs=True, want_mag=True)
+    assert np.array_equal(ns_g[sample], ns_o)
+    assert np.all(np.abs(cs_g[sample] - cs_o) <= 1e-9 * np.maximum(np.abs(cs_o), 1.0))
+    assert np.all(np.abs(f_g[sample] - f_o) <= fitness_tol(mag))
+    say(f"  fp64: max |dL|/M = {np.max(np.abs(f_g[sample] - f_o) / np.maximum(mag, 1e-300)):.2e}")
+
+
+def test_fitness_bf16x2_full_population(full, variant0):
+    _, C, pop, sample = full
+    Cg = _g(C)
+    hi, lo = pga.split(Cg)
+    hi_o, lo_o = O.split_bf16(C)
+    assert np.array_equal(hi.cpu().numpy().view(np.uint16)[:N, :N], hi_o)
+    assert np.array_equal(lo.cpu().numpy().view(np.uint16)[:N, :N], lo_o)
+    f_g, ns_g, cs_g = pga.fitness(Cg, _g(pop), "bf16x2", hi=hi, lo=lo, want_ns=True, want_cs=True)
+    f_g, ns_g, cs_g = f_g.cpu().numpy(), ns_g.cpu().numpy(), cs_g.cpu().numpy()
+    sub = pop[sample]
+    Ce = bf16_emulated(C, hi_o, lo_o)
+    f_e, ns_e, cs_e = O.fitness(Ce, sub, want_ns=True, want_cs=True)
+    assert np.array_equal(ns_g[sample], ns_e)
+    bnd = cs_bound_fp32(Ce, sub)
+    assert np.all(np.abs(cs_g[sample] - cs_e) <= bnd)
+    assert np.all(np.abs(f_g[sample] - f_e) <= l_bound_from_cs(ns_e, cs_e, bnd))
+    f_o, mag = O.fitness(C, sub, want_mag=True)
+    rel = np.abs(f_g[sample] - f_o) / np.maximum(mag, 1e-300)
+    say(f"  bf16x2 vs fp64 oracle: max |dL|/M = {rel.max():.2e}")
+    assert rel.max() < 1e-4
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+def test_one_generation_lockstep_full_population(full, variant0, form):
+    _, C, pop, _ = full
+    Cg = _g(C)
+    hi = lo = None
+    if form == "bf16x2":
+        hi, lo = pga.split(Cg)
+    I = pga.make_instance(Cg, P, hi=hi, lo=lo, pop=_g(pop), stats_rows=2, elites=2, seed=0, instance_id=0)
+    f_g = pga.fitness(Cg, I.pop, form, hi=hi, lo=lo)
+    I.gen0 = 0
+    pga.Context().evolve([I], 1, form=form)
+    torch.cuda.synchronize()
+    nxt = O.breed(pop, f_g.cpu().numpy(), E=2, seed=0, inst=0, gen=0, selection=0)
+    assert np.array_equal(I.pop.cpu().numpy(), nxt)
+    # the final fitness of the call is that of the new population
+    assert torch.equal(I.fitness, pga.fitness(Cg, I.pop, form, hi=hi, lo=lo))
