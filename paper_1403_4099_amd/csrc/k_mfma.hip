@@ -232,37 +232,39 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         // Thread t stages row pairs t + 256k of every individual: all 2 * PK * B
         // labels are loaded before the first table lookup, so the pass costs one
         // memory latency; each row pair is written as B consecutive dwords.
+        // Nothing here needs a validity test, only in-bounds addresses: rows past
+        // the pass (only past N, in its last 32-row chunk) meet zero-padded A;
+        // individuals past P are not stored; a label outside [0, N) makes the
+        // finish kernel give its individual -inf whatever its sums. So row and
+        // individual indices are clamped into range, and labels to N - 1.
         constexpr int PK = RC / 512;
-        int32_t lab[PK][2][B];
+        const uint32_t rlast = (uint32_t)(rows - 1), lmax = (uint32_t)(N - 1);
+        uint32_t lab[PK][2][B];
 #pragma unroll
         for (int k = 0; k < PK; ++k) {
-            const int r = 2 * (threadIdx.x + 256 * k);
+            const uint32_t r = 2u * (uint32_t)(threadIdx.x + 256 * k);
+            const uint32_t r0 = min(r, rlast), r1 = min(r + 1u, rlast);
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const int p = pbase + b;
-                const int32_t *lp = labels + (size_t)p * N + c0 + r;
-                lab[k][0][b] = (r < rows && p < P) ? gld(lp) : -1;
-                lab[k][1][b] = (r + 1 < rows && p < P) ? gld(lp + 1) : -1;
+                const int32_t *lp = labels + (size_t)min(pbase + b, P - 1) * N + c0;   // uniform
+                lab[k][0][b] = (uint32_t)gld(lp + r0);
+                lab[k][1][b] = (uint32_t)gld(lp + r1);
             }
         }
 #pragma unroll
-        for (int k = 0; k < PK; ++k)                          // all table reads (index clamped, in range), then all writes
+        for (int k = 0; k < PK; ++k)                          // all table reads, then all writes
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const bool ok = (uint32_t)lab[k][h][b] < (uint32_t)N;
-                    const int32_t c = code(b, ok ? lab[k][h][b] : 0);
-                    lab[k][h][b] = ok ? c : (int32_t)kCodeNone;
-                }
+                for (int b = 0; b < B; ++b) lab[k][h][b] = code(b, (int)min(lab[k][h][b], lmax));
 #pragma unroll
         for (int k = 0; k < PK; ++k) {
             const int q = threadIdx.x + 256 * k;
             if (2 * q < rows32) {
                 uint32_t w[B];
 #pragma unroll
-                for (int b = 0; b < B; ++b)
-                    w[mfma_pos<B>(b)] = ((uint32_t)lab[k][0][b] << kCodeShift) | ((uint32_t)lab[k][1][b] << (16 + kCodeShift));
+                for (int b = 0; b < B; ++b)                       // code of row 2q in bits 8..15, of 2q+1 in 24..31
+                    w[mfma_pos<B>(b)] = __builtin_amdgcn_perm(lab[k][1][b], lab[k][0][b], 0x040C000Cu);
 #pragma unroll
                 for (int v = 0; v < B / 4; ++v)
                     *(uint4 *)(s.rows + (size_t)q * B + 4 * v) = uint4{w[4 * v], w[4 * v + 1], w[4 * v + 2], w[4 * v + 3]};
