@@ -44,7 +44,6 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 constexpr int kCodeShift = 8;
 constexpr uint16_t kOneHot = 0x0100;        // bf16 2^-125
 constexpr uint8_t kCodeNone = 0xFF;         // row label not present in the column block
-constexpr uint8_t kCodeBadCol = 0xFE;       // column beyond N, beyond P, or label out of range
 
 __device__ __forceinline__ uint32_t onehot2(uint32_t rows2, uint32_t col2) {
     const u16x2 x = __builtin_bit_cast(u16x2, rows2 ^ col2);
@@ -102,23 +101,26 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
     const uint16_t *__restrict__ ls = d.ls;
     auto code = [&](int b, int l) -> uint8_t & { return s.code[(size_t)b * s.cstride + l]; };
 
-    // Column labels; lanes with g == 0 register them in the code table.
-    int32_t lj[B];
+    // Column labels; lanes with g == 0 register them in the code table. Stock,
+    // individual and label are clamped into range as in the staging below: a
+    // column past N or an individual past P is not stored, and a clamped
+    // duplicate only writes a consistent code (the position of some stock with
+    // that label) into its own individual's table.
+    const uint32_t lmax = (uint32_t)(N - 1);
+    const int jc = min(j, N - 1);
+    uint32_t lj[B];
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const int p = pbase + b;
-        lj[b] = (j < N && p < P) ? gld(labels + (size_t)p * N + j) : -1;
-    }
+    for (int b = 0; b < B; ++b)
+        lj[b] = min((uint32_t)gld(labels + (size_t)min(pbase + b, P - 1) * N + jc), lmax);
     if (g == 0) {
 #pragma unroll
-        for (int b = 0; b < B; ++b)
-            if ((uint32_t)lj[b] < (uint32_t)N) code(b, lj[b]) = (uint8_t)q;
+        for (int b = 0; b < B; ++b) code(b, (int)lj[b]) = (uint8_t)q;
     }
     __syncthreads();
     uint32_t col2[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const uint32_t c = (uint32_t)lj[b] < (uint32_t)N ? (uint32_t)code(b, lj[b]) : kCodeBadCol;
+        const uint32_t c = code(b, (int)lj[b]);
         col2[b] = (c << kCodeShift) | (c << (16 + kCodeShift));
     }
 
@@ -295,8 +297,7 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
     // Restore the table (every reader passed the barrier that closes the row loop).
     if (g == 0) {
 #pragma unroll
-        for (int b = 0; b < B; ++b)
-            if ((uint32_t)lj[b] < (uint32_t)N) code(b, lj[b]) = kCodeNone;
+        for (int b = 0; b < B; ++b) code(b, (int)lj[b]) = kCodeNone;
     }
 }
 
@@ -319,10 +320,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     (double *)(lds + sizeof(uint16_t) * kMfmaRowCodes + (size_t)B * cstride), cstride};
     {
         const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
-        for (int e = threadIdx.x; e < B * words; e += 256) {
-            const int b = e / words, w = e - b * words;
-            *(uint32_t *)(s.code + (size_t)b * cstride + 4 * w) = 0xFFFFFFFFu;
-        }
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            for (int w = threadIdx.x; w < words; w += 256) *(uint32_t *)(s.code + (size_t)b * cstride + 4 * w) = 0xFFFFFFFFu;
     }
     __syncthreads();
     mfma_block<B>(d, n_jb - 1 - jp, pb, parity, s);
