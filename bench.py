@@ -336,7 +336,8 @@ def main():
                         "labeling; ga_runs: the two forms' separate GA runs (trajectories part at near-ties)"}
 
     # ---- pga_fitness on a resident population: median of 20 timed calls after 3 warm-ups (HIP
-    # events on the calling stream), at the random (generation 0) and converged populations, with
+    # events on the calling stream, calls back to back), at the random (generation 0) and converged
+    # populations, with
     # the pair-sum kernel's own time (library timing, same calls) and the population's mean K
     def kbar(pop):
         srt = pop.sort(dim=1).values
@@ -347,15 +348,16 @@ def main():
         for tag, pop in (("random", pop0), ("converged", insts[form].pop)):
             for _ in range(3):
                 pga.fitness(C, pop, form, hi=hi, lo=lo)
-            torch.cuda.synchronize()
-            calls = []
-            for _ in range(20):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            # back to back, one synchronisation at the end: the GPU stays busy as in a serving loop
+            # (with a host round trip after every call its clock does not settle at the loaded rate)
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(20)]
+            for e0, e1 in evs:
                 e0.record()
                 pga.fitness(C, pop, form, hi=hi, lo=lo)
                 e1.record()
-                torch.cuda.synchronize()
-                calls.append(e0.elapsed_time(e1) * 1e-3)
+            torch.cuda.synchronize()
+            calls = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs]
             pga.timing_enable(True)
             pga.timing_reset()
             for _ in range(5):

@@ -213,7 +213,7 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
  *   in turn runs `reps` evaluations, all back to back on `stream` and timed
  *   by HIP events (the GPU's clock rises under load, so no variant gains from
  *   its place in the order); stores the fastest in the table (the lowest
- *   variant index among those within 1% of the fastest) and returns it in
+ *   variant index among those within 3% of the fastest, the run-to-run spread) and returns it in
  *   out_variant; out_ms (nullable, pga_variant_count(form) floats, host)
  *   receives each variant's best round in milliseconds per evaluation, -1 for
  *   variants that do not fit.

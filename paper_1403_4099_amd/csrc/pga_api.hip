@@ -470,7 +470,7 @@ int pga_tune(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_
     // kTuneRounds rounds after a warm-up, back to back with no host synchronisation between
     // them, and each keeps its fastest round: no variant is favoured by its place in the order.
     constexpr int kTuneRounds = 3;
-    constexpr float kTuneTie = 0.01f;
+    constexpr float kTuneTie = 0.03f;
     int valid[kMaxVariants];
     int nvalid = 0;
     for (int vi = 0; vi < n_variants(form); ++vi) {

@@ -55,10 +55,10 @@ def test_tune_picks_a_fitting_variant_and_records_it(form):
     try:
         v, ms = pga.tune(Cg, pop, form, hi=hi, lo=lo, reps=3)
         say(f"  chosen {v} {pga.variants(form)[v]}; ms {['%.3f' % x for x in ms]}")
-        # the lowest-index variant within 1% of the fastest (near-ties go to the preferred order)
+        # the lowest-index variant within 3% of the fastest (near-ties go to the preferred order)
         # (compared in float32, as the library does)
         fastest = min(np.float32(x) for x in ms if x > 0)
-        tie = fastest * (np.float32(1.0) + np.float32(0.01))
+        tie = fastest * (np.float32(1.0) + np.float32(0.03))
         within = [i for i, x in enumerate(ms) if x > 0 and np.float32(x) <= tie]
         assert 0 <= v < len(ms) and ms[v] > 0 and v == within[0]
         assert pga.tune_get(form, N, P) == v
