@@ -214,3 +214,36 @@ def test_fitness_bf16x2_matches_oracle_on_split_matrix(N, P, K, seed):
     rel = np.abs(f_g - f_o) / np.maximum(mag, 1e-300)
     say(f"  bf16x2 vs fp64 oracle: max |dL|/M = {rel.max():.3e}")
     assert rel.max() < 1e-4
+
+
+@pytest.mark.parametrize("N,P", [(100, 40), (257, 19)], ids=["N100-P40", "N257-P19"])
+def test_bf16x2_invalid_labels_do_not_disturb_other_individuals(N, P):
+    """Individuals with labels outside [0, N) share workgroups with valid ones: they come out -inf
+    (status counted as by the oracle), and every valid individual still matches the oracle, in
+    every kernel variant (the pair-sum clamps labels for addressing only)."""
+    say(f"bf16x2 invalid labels mixed N={N} P={P}")
+    C, _ = corr(N, seed=40 + N)
+    pop = synth.random_labelings(P, N, seed=N, K=max(2, N // 8))
+    rng = np.random.default_rng(N)
+    bad = rng.choice(P, size=P // 4, replace=False)
+    for k, p in enumerate(bad):
+        pop[p, rng.integers(0, N)] = (N + 3) if k % 2 == 0 else -7
+    st_o = O.status_zero()
+    f_o, ns_o, cs_o, mag = O.fitness(C, pop, want_ns=True, want_cs=True, want_mag=True, status=st_o)
+    assert np.all(np.isinf(f_o[bad]))
+    Cg = _g(C)
+    hi, lo = pga.split(Cg)
+    ok = np.isfinite(f_o)
+    try:
+        for v in range(len(pga.variants("bf16x2"))):
+            pga.tune_set("bf16x2", N, P, v)
+            st = pga.new_status()
+            f_g, ns_g, cs_g = pga.fitness(Cg, _g(pop), "bf16x2", hi=hi, lo=lo, want_ns=True, want_cs=True, status=st)
+            f_g, ns_g, cs_g = f_g.cpu().numpy(), ns_g.cpu().numpy(), cs_g.cpu().numpy()
+            assert np.array_equal(np.isinf(f_g), ~ok), v
+            assert np.array_equal(st.cpu().numpy(), st_o), v
+            assert np.array_equal(ns_g, ns_o), v                     # zeros for the invalid individuals
+            assert np.all(cs_g[~ok] == 0.0), v
+            assert np.all(np.abs(f_g[ok] - f_o[ok]) <= 1e-4 * mag[ok] + 1e-9), v
+    finally:
+        pga.tune_set("bf16x2", N, P, -1)
