@@ -98,10 +98,12 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-// 16 waves; each thread keeps up to kRankCache of its fitness values in registers
-// (all loads issued at once), so the E selection rounds and the statistics pass
-// cost one memory latency; values past 16 * 64 * kRankCache are re-read.
-constexpr int kRankThreads = 1024;
+// 8 waves (fewer, longer per-thread scans beat wider reductions on the one CU
+// this runs on); each thread keeps up to kRankCache of its fitness values in
+// registers (all loads issued at once), so the E selection rounds and the
+// statistics pass cost one memory latency; values past 8 * 64 * kRankCache are
+// re-read.
+constexpr int kRankThreads = 512;
 constexpr int kRankWaves = kRankThreads / 64;
 constexpr int kRankCache = 8;
 
