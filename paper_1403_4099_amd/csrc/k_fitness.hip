@@ -351,10 +351,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int
 
     // Stocks j = tid + 256 u; the first kFinCache per thread stay in registers (all
     // loads issued together), later ones are read again in the accumulation pass.
+    // ucache: cached slots in use, uniform over the workgroup, so the slots past N
+    // cost nothing (not even masked-off instructions).
+    const int ucache = min(kFinCache, (N + kFinThreads - 1) / kFinThreads);
     int lr[kFinCache];
     double vr[kFinCache];
 #pragma unroll
     for (int u = 0; u < kFinCache; ++u) {
+        if (u >= ucache) break;
         const int j = tid + kFinThreads * u;
         lr[u] = j < N ? gld(lab + j) : 0;
         vr[u] = j < N ? gld(v + j) : 0.0;
@@ -363,6 +367,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int
     double mx = 0.0;
 #pragma unroll
     for (int u = 0; u < kFinCache; ++u) {
+        if (u >= ucache) break;
         if (lr[u] < 0 || lr[u] >= N) bad |= 1;
         if (!isfinite(vr[u])) bad |= 2;
         else mx = fmax(mx, fabs(vr[u]));
@@ -415,6 +420,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int
     }
 #pragma unroll
     for (int u = 0; u < kFinCache; ++u) {
+        if (u >= ucache) break;
         if (tid + kFinThreads * u < N) {
             atomicAdd(&cnt[lr[u]], 1);
             atomicAdd((unsigned long long *)&csum[lr[u]], (unsigned long long)llrint(ldexp(vr[u], sc)));
