@@ -183,7 +183,7 @@ int pga_ewma(const double *R, int32_t N, int32_t T, int32_t ld_r, double lambda,
  * (P x N FP64), nullable, receive the per-label values (index = label); for
  * an individual with an out-of-range label both rows are zero.
  * form PGA_FORM_FP64: FP64 throughout. form PGA_FORM_BF16X2: the pair sums
- * use C_hi + C_lo on MFMA with FP32 accumulation (flushed to FP64 every 256
+ * use C_hi + C_lo on MFMA with FP32 accumulation (flushed to FP64 every 512
  * stocks); diagonal, c_s, logs and the sum over clusters stay FP64.
  * C_hi/C_lo may be NULL for PGA_FORM_FP64. P = 0 is a no-op. */
 size_t pga_fitness_ws_bytes(int32_t N, int32_t P, int32_t form);

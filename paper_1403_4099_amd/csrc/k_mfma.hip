@@ -28,8 +28,8 @@
 // same 8 row codes per individual; instead of 16 identical LDS reads, each
 // lane reads B/4 different dwords (two row codes each) and the xor takes its
 // row operand from the lane that holds it (DPP row broadcast), so a chunk
-// costs one B*64-byte LDS read per wave. FP32 accumulation is flushed into FP64 at every 256-row
-// boundary, so no FP32 partial sum spans more than 256 rows.
+// costs one B*64-byte LDS read per wave. FP32 accumulation is flushed into FP64 at every 512-row
+// boundary, so no FP32 partial sum spans more than 512 rows.
 #include "pga_internal.hpp"
 
 #include <type_traits>
@@ -75,7 +75,7 @@ __host__ __device__ constexpr int mfma_pos(int b) {
 // rows 2q (low half) and 2q + 1 of individual b; then the label -> code
 // tables [B][cstride] (bytes, cstride >= N); then the FP64 partial sums
 // [wave][B][lane] (kept in LDS rather than registers: they change only once
-// per 256 rows, and the registers they free let more waves share a SIMD).
+// per 512 rows, and the registers they free let more waves share a SIMD).
 struct MfmaLds {
     uint32_t *rows;
     uint8_t *code;

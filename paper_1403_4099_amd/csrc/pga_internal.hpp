@@ -51,7 +51,7 @@ constexpr int kFp64Cols = 64;                      // columns per workgroup
 constexpr int kMfmaWaves = 4;                      // waves per workgroup, 16 columns each
 constexpr int kMfmaCols = 16 * kMfmaWaves;         // columns per workgroup
 constexpr int kMfmaRowCodes = 8192;                // row codes staged in LDS per workgroup (all individuals)
-constexpr int kMfmaFlushRows = 256;                // FP32 accumulators are flushed to FP64 every 256 rows
+constexpr int kMfmaFlushRows = 512;                // FP32 accumulators are flushed to FP64 every 512 rows
 constexpr int kMaxLdsBytes = 65536;                // LDS a workgroup may allocate
 
 inline int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }

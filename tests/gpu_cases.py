@@ -51,7 +51,7 @@ def bf16_emulated(C, hi, lo):
     return Ce
 
 
-def cs_bound_fp32(Ce, pop, flush=256):
+def cs_bound_fp32(Ce, pop, flush=512):
     """Rigorous bound on |c_s(BF16x2 GPU) - c_s(oracle on Ce)| per (individual, label).
 
     The GPU sums 2 * sum_{i<j} products in FP32 over chunks of at most `flush`
