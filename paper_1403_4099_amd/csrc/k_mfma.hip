@@ -22,14 +22,19 @@
 // with a one-hot of 1.0.
 //
 // The i < j mask is applied only in the chunk that reaches the diagonal. A is
-// loaded once per (wave, chunk), two chunks ahead, and reused by the B (4, 8
-// or 16) individuals of the workgroup, whose row codes are staged in LDS
-// 8192 / B rows at a time. In a chunk the 16 lanes of a row group need the
-// same 8 row codes per individual; instead of 16 identical LDS reads, each
-// lane reads B/4 different dwords (two row codes each) and the xor takes its
-// row operand from the lane that holds it (DPP row broadcast), so a chunk
-// costs one B*64-byte LDS read per wave. FP32 accumulation is flushed into FP64 at every 512-row
-// boundary, so no FP32 partial sum spans more than 512 rows.
+// loaded once per (wave, chunk), one chunk ahead, by direct global-to-LDS
+// loads into a two-slot ring per wave (no registers hold it in flight, so
+// nothing is copied from chunk to chunk), and reused by the B (4, 8 or 16)
+// individuals of the workgroup, whose row codes are staged in LDS 8192 / B
+// rows at a time. In a chunk the 16 lanes of a row group need the same 8 row
+// codes per individual; instead of 16 identical LDS reads, each lane reads
+// B/4 different dwords (two row codes each) and the xor takes its row operand
+// from the lane that holds it (DPP row broadcast), so a chunk costs one
+// B*64-byte LDS read per wave. FP32 accumulation is flushed into FP64 at
+// every 512-row boundary, so no FP32 partial sum spans more than 512 rows.
+// The 4- and 8-individual kernels are held to 128 registers (four waves per
+// SIMD): MFMA and VALU work of a SIMD serialise on this GPU, and the fourth
+// wave hides the latency between them.
 #include "pga_internal.hpp"
 
 #include <type_traits>
@@ -73,13 +78,13 @@ __host__ __device__ constexpr int mfma_pos(int b) {
 // LDS of one workgroup (dynamic): row codes, kMfmaRowCodes 16-bit words (the
 // code shifted into bits 8..15), as dwords [row pair][mfma_pos(b)] holding the
 // rows 2q (low half) and 2q + 1 of individual b; then the label -> code
-// tables [B][cstride] (bytes, cstride >= N); then the FP64 partial sums
-// [wave][B][lane] (kept in LDS rather than registers: they change only once
-// per 512 rows, and the registers they free let more waves share a SIMD).
+// tables [B][cstride] (bytes, cstride >= N); then each wave's ring of
+// kMfmaASlots A slots, 2 KB each (the 16 x 32 hi tile, then the lo tile, in
+// lane order), filled by direct global-to-LDS loads one chunk ahead.
 struct MfmaLds {
     uint32_t *rows;
     uint8_t *code;
-    double *acc64;
+    unsigned char *aring;
     int cstride;
 };
 
@@ -125,11 +130,11 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
     }
 
     floatx4 acc[B];
-    double *acc64 = s.acc64 + (size_t)wave * B * 64 + lane;  // individual b at acc64[64 b]
+    double acc64[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
-        acc64[64 * b] = 0.0;
+        acc64[b] = 0.0;
     }
     const int dreg = n & 3;                                   // lane holds D[n][n] in register n & 3 ...
     const bool diag_lane = (n >> 2) == g;                     // ... when its 4-row group contains row n
@@ -138,7 +143,7 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const float v = dreg == 0 ? acc[b][0] : dreg == 1 ? acc[b][1] : dreg == 2 ? acc[b][2] : acc[b][3];
-            acc64[64 * b] += (double)v;
+            acc64[b] += (double)v;
             acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
     };
@@ -146,11 +151,23 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
     // multiple of 32 and jt0 a multiple of 16), so the loads need no guard. The
     // scaled copies are tile-major (a_tile_offset): the wave's 16 x 32 A block is
     // 1 KB of consecutive bytes in lane order.
+    // Chunk i0's A goes to ring slot ((i0 - c0) / 32) % kMfmaASlots of this wave:
+    // a direct global-to-LDS load puts lane l's 16 bytes at slot + 16 l, exactly
+    // where the same lane reads them back.
     const size_t a_row = (size_t)(jt0 >> 4) * (size_t)(ld >> 5);
-    auto load_a = [&](int i0, uint4 &ah, uint4 &al) {
+    unsigned char *const my_ring = s.aring + (size_t)wave * kMfmaASlots * 2048;
+    auto slot_of = [&](int i0, int c0) { return my_ring + (size_t)(((i0 - c0) >> 5) % kMfmaASlots) * 2048; };
+    auto load_a = [&](int i0, int c0) {
         const size_t off = (a_row + (size_t)(i0 >> 5)) * 512 + (size_t)lane * 8;
-        ah = gld_u4(hs + off);
-        al = gld_u4(ls + off);
+        unsigned char *sl = slot_of(i0, c0);
+        __builtin_amdgcn_global_load_lds((const void *)(hs + off), (__attribute__((address_space(3))) void *)sl, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)(ls + off), (__attribute__((address_space(3))) void *)(sl + 1024), 16,
+                                         0, 0);
+    };
+    auto read_a = [&](int i0, int c0, uint4 &ah, uint4 &al) {
+        const unsigned char *sl = slot_of(i0, c0);
+        ah = *(const uint4 *)(sl + 16 * lane);
+        al = *(const uint4 *)(sl + 1024 + 16 * lane);
     };
     // Lane t of row group g reads, into R[k], rows i0 + 8g + 2(t%4), +1 of individual 4k + t/4.
     auto read_r = [&](int i0, int c0, uint32_t (&R)[B / 4]) {
@@ -205,22 +222,17 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         });
         if (((i0 + 32) % kMfmaFlushRows) == 0) flush();
     };
-    // Chunks [i0, end) of one kind; (ah, al) holds the A of chunk i0 and (bh, bl)
-    // the A of i0 + 32, so the loads run two chunks ahead of their use.
-    // Chunks [i0, end) of one kind; (ah, al) holds the A of chunk i0 and (bh, bl)
-    // the A of i0 + 32, so the loads run two chunks ahead of their use.
-    auto run = [&](auto masked_tag, int &i0, int end, int cend, int c0, uint4 &ah, uint4 &al, uint4 &bh,
-                   uint4 &bl) {
+    // Chunks [i0, end) of one kind. A chunk first reads its A and row codes from
+    // LDS (its A was loaded during the previous chunk), then starts the load of
+    // the next chunk's A into the other slot, then computes.
+    auto run = [&](auto masked_tag, int &i0, int end, int cend, int c0) {
         for (; i0 < end; i0 += 32) {
-            uint4 nh, nl;
-            if (i0 + 64 < cend) load_a(i0 + 64, nh, nl);
+            uint4 ah, al;
+            read_a(i0, c0, ah, al);
             uint32_t R[B / 4];
             read_r(i0, c0, R);
+            if (i0 + 32 < cend) load_a(i0 + 32, c0);
             chunk(masked_tag, i0, c0, ah, al, R);
-            ah = bh;
-            al = bl;
-            bh = nh;
-            bl = nl;
         }
     };
 
@@ -275,13 +287,11 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         __syncthreads();
         const int cend = min(c0 + RC, my_iend);
         if (c0 < cend) {
-            uint4 ah, al, bh, bl;
-            load_a(c0, ah, al);
-            if (c0 + 32 < cend) load_a(c0 + 32, bh, bl);
+            load_a(c0, c0);
             int i0 = c0;
             const int uend = min(cend, max(c0, i_diag));        // chunks entirely below the diagonal
-            run(std::false_type{}, i0, uend, cend, c0, ah, al, bh, bl);
-            run(std::true_type{}, i0, cend, cend, c0, ah, al, bh, bl);
+            run(std::false_type{}, i0, uend, cend, c0);
+            run(std::true_type{}, i0, cend, cend, c0);
         }
         __syncthreads();
     }
@@ -291,7 +301,7 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int p = pbase + b;
-            if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[64 * b], cjj));
+            if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[b], cjj));
         }
     }
     // Restore the table (every reader passed the barrier that closes the row loop).
@@ -304,7 +314,7 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
 // The triangle is folded: column blocks n_jb-1-jp and jp share a workgroup, so every
 // workgroup processes the same number of row chunks.
 template <int B>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_pairsum_mfma(Tables t, int parity,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(B == 16 ? 2 : 4))) void k_pairsum_mfma(Tables t, int parity,
                                                                                      int order, int cstride) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int tile = order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -317,7 +327,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const TilePos tp = tile_pos(local, n_pairs, (d.P + B - 1) / B, order);
     const int jp = tp.jp, pb = tp.pb;
     const MfmaLds s{(uint32_t *)lds, lds + sizeof(uint16_t) * kMfmaRowCodes,
-                    (double *)(lds + sizeof(uint16_t) * kMfmaRowCodes + (size_t)B * cstride), cstride};
+                    lds + sizeof(uint16_t) * kMfmaRowCodes + (size_t)B * cstride, cstride};
     {
         const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
 #pragma unroll

@@ -79,9 +79,10 @@ inline int32_t pair_tiles(int32_t N, int32_t P, const Variant &v) {
     return fold_pairs(N, 64) * ceil_div(P, per);
 }
 inline size_t mfma_code_stride(int max_n) { return ((size_t)max_n + 15) / 16 * 16; }
+constexpr int kMfmaASlots = 2;                     // A ring slots per wave (2 KB each) in the MFMA kernel
 inline size_t mfma_lds_bytes(int ipg, int max_n) {
     return sizeof(uint16_t) * kMfmaRowCodes + (size_t)ipg * mfma_code_stride(max_n) +
-           sizeof(double) * kMfmaWaves * 64 * (size_t)ipg;
+           (size_t)kMfmaWaves * kMfmaASlots * 2048;
 }
 inline bool variant_ok(const Variant &v, int max_n) {
     return v.form != PGA_FORM_BF16X2 || mfma_lds_bytes(v.ipg, max_n) <= (size_t)kMaxLdsBytes;
