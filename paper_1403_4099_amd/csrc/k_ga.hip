@@ -98,30 +98,143 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-// 8 waves (fewer, longer per-thread scans beat wider reductions on the one CU
-// this runs on); each thread keeps up to kRankCache of its fitness values in
-// registers (all loads issued at once), so the E selection rounds and the
-// statistics pass cost one memory latency; values past 8 * 64 * kRankCache are
-// re-read.
-constexpr int kRankThreads = 512;
+// Elite selection, termination state and statistics of one instance by one
+// workgroup of kRankThreads threads: the rank kernel, and, when the breed
+// kernel does the ranking itself (no SUS, no early stop), the breed workgroups
+// of the elite slots. Both use this code with the same thread count, so their
+// statistics agree bit for bit. Each thread keeps up to CACHE of its fitness
+// values in registers (all loads issued at once) and re-reads the rest; every
+// thread visits its values in the same order whatever CACHE is, so CACHE
+// changes no result.
+constexpr int kRankThreads = 256;
 constexpr int kRankWaves = kRankThreads / 64;
-constexpr int kRankCache = 8;
+constexpr int kRankCache = 16;
+
+struct RankLds {
+    double wf[kRankWaves];
+    int wi[kRankWaves];
+};
+
+template <int CACHE>
+struct RankBlock {
+    const double *__restrict__ f;
+    int P;
+    RankLds &sh;
+    double fr[CACHE];
+
+    __device__ void load() {
+#pragma unroll
+        for (int v = 0; v < CACHE; ++v) {
+            const int p = threadIdx.x + v * kRankThreads;
+            fr[v] = p < P ? gld(f + p) : -INFINITY;
+        }
+    }
+    // Best candidate of this thread ranked after prev (prev.i < 0: no bound).
+    __device__ Cand thread_best(Cand prev) const {
+        Cand c{0.0, -1};
+#pragma unroll
+        for (int v = 0; v < CACHE; ++v) {
+            const int p = threadIdx.x + v * kRankThreads;
+            if (p >= P) break;
+            if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fr[v], p)) continue;
+            if (c.i < 0 || ranks_before(fr[v], p, c.f, c.i)) c = Cand{fr[v], p};
+        }
+        for (int p = threadIdx.x + CACHE * kRankThreads; p < P; p += kRankThreads) {
+            const double fp = gld(f + p);
+            if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fp, p)) continue;
+            if (c.i < 0 || ranks_before(fp, p, c.f, c.i)) c = Cand{fp, p};
+        }
+        return c;
+    }
+    __device__ Cand block_best(Cand c) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        c = wave_best(c);
+        if (lane == 0) {
+            sh.wf[wave] = c.f;
+            sh.wi[wave] = c.i;
+        }
+        __syncthreads();
+        Cand b{0.0, -1};
+        for (int w = 0; w < kRankWaves; ++w)
+            if (sh.wi[w] >= 0 && (b.i < 0 || ranks_before(sh.wf[w], sh.wi[w], b.f, b.i))) b = Cand{sh.wf[w], sh.wi[w]};
+        __syncthreads();
+        return b;
+    }
+    __device__ double block_sum(double v) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        v = wave_sum_d(v);
+        if (lane == 0) sh.wf[wave] = v;
+        __syncthreads();
+        double r = 0.0;
+        for (int w = 0; w < kRankWaves; ++w) r += sh.wf[w];
+        __syncthreads();
+        return r;
+    }
+    // The r-th ranked individual for r = 0 .. rounds-1: calls visit(r, cand) in order.
+    template <typename F>
+    __device__ void ranked(int rounds, F &&visit) {
+        Cand prev{0.0, -1};
+        for (int r = 0; r < rounds; ++r) {
+            const Cand b = block_best(thread_best(prev));
+            visit(r, b);
+            prev = b;
+        }
+    }
+    // Statistics row gen_off: {best, mean of finite fitnesses (-inf if none), #-inf, argbest}.
+    __device__ void write_stats(const InstDesc &d, int gen_off, Cand best) {
+        double sum = 0.0, ninv = 0.0;
+#pragma unroll
+        for (int v = 0; v < CACHE; ++v) {
+            const int p = threadIdx.x + v * kRankThreads;
+            if (p >= P) break;
+            if (isfinite(fr[v])) sum += fr[v];
+            else ninv += 1.0;
+        }
+        for (int p = threadIdx.x + CACHE * kRankThreads; p < P; p += kRankThreads) {
+            const double fp = gld(f + p);
+            if (isfinite(fp)) sum += fp;
+            else ninv += 1.0;
+        }
+        const double total = block_sum(sum);
+        const double inv = block_sum(ninv);
+        if (threadIdx.x == 0) {
+            double *row = d.stats + 4 * (size_t)gen_off;
+            const double nfin = (double)P - inv;
+            row[0] = best.f;
+            row[1] = nfin > 0.0 ? total / nfin : -INFINITY;
+            row[2] = inv;
+            row[3] = (double)best.i;
+        }
+    }
+};
+
+// Termination state after this generation's best b (thread 0 of the ranking
+// workgroup): improvement, stall count, stop flag; the generation about to be
+// bred is counted unless this is the final evaluation or the run stopped.
+__device__ void term_update(const InstDesc &d, pga_term_state st, double b, int final) {
+    const bool improved = isfinite(st.ref) ? (b > st.ref + d.tol * fmax(1.0, fabs(st.ref))) : isfinite(b);
+    if (improved) {
+        st.ref = b;
+        st.stall = 0;
+    } else {
+        st.stall += 1;
+    }
+    if (d.stall_gens > 0 && st.stall >= d.stall_gens) st.stopped = 1;
+    if (!final && !st.stopped) {
+        st.gens += 1;
+        st.call_gens += 1;
+    }
+    *d.term = st;
+}
 
 __global__ __launch_bounds__(kRankThreads) void k_rank(Tables t, int gen_off, int final) {
-    __shared__ double wf[kRankWaves];
-    __shared__ int wi[kRankWaves];
+    __shared__ RankLds sh;
     const InstDesc &d = t.desc[blockIdx.x];
     const int P = d.P, E = d.E;
-    const double *__restrict__ f = d.fitness;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // The fitness values, the stop flag and (thread 0) the termination state are
     // all requested before any of them is used.
-    double fr[kRankCache];
-#pragma unroll
-    for (int v = 0; v < kRankCache; ++v) {
-        const int p = threadIdx.x + v * kRankThreads;
-        fr[v] = p < P ? gld(f + p) : -INFINITY;
-    }
+    RankBlock<kRankCache> rb{d.fitness, P, sh};
+    rb.load();
     pga_term_state st{};
     if (d.term) {
         const bool stopped = inst_stopped(d);
@@ -135,102 +248,13 @@ __global__ __launch_bounds__(kRankThreads) void k_rank(Tables t, int gen_off, in
     }
     if (d.selection == PGA_SELECT_SUS)                     // the SUS rank kernel adds into these
         for (int p = threadIdx.x; p < P; p += kRankThreads) gst(d.sus_rank + p, 1);
-
-    auto block_best = [&](Cand c) -> Cand {
-        c = wave_best(c);
-        if (lane == 0) {
-            wf[wave] = c.f;
-            wi[wave] = c.i;
-        }
-        __syncthreads();
-        Cand b{0.0, -1};
-        for (int w = 0; w < kRankWaves; ++w)
-            if (wi[w] >= 0 && (b.i < 0 || ranks_before(wf[w], wi[w], b.f, b.i))) b = Cand{wf[w], wi[w]};
-        __syncthreads();
-        return b;
-    };
-    auto block_sum = [&](double v) -> double {
-        v = wave_sum_d(v);
-        if (lane == 0) wf[wave] = v;
-        __syncthreads();
-        double r = 0.0;
-        for (int w = 0; w < kRankWaves; ++w) r += wf[w];
-        __syncthreads();
-        return r;
-    };
-    // Best candidate of this thread ranked after prev (prev.i < 0: no bound).
-    auto thread_best = [&](Cand prev) -> Cand {
-        Cand c{0.0, -1};
-#pragma unroll
-        for (int v = 0; v < kRankCache; ++v) {
-            const int p = threadIdx.x + v * kRankThreads;
-            if (p >= P) break;
-            if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fr[v], p)) continue;
-            if (c.i < 0 || ranks_before(fr[v], p, c.f, c.i)) c = Cand{fr[v], p};
-        }
-        for (int p = threadIdx.x + kRankCache * kRankThreads; p < P; p += kRankThreads) {
-            const double fp = gld(f + p);
-            if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fp, p)) continue;
-            if (c.i < 0 || ranks_before(fp, p, c.f, c.i)) c = Cand{fp, p};
-        }
-        return c;
-    };
-
-    Cand prev{0.0, -1};
-    int argbest = 0;
-    double fbest = -INFINITY;
-    const int rounds = E > 1 ? E : 1;
-    for (int r = 0; r < rounds; ++r) {
-        const Cand b = block_best(thread_best(prev));
-        if (r == 0) {
-            argbest = b.i;
-            fbest = b.f;
-        }
+    Cand best{-INFINITY, 0};
+    rb.ranked(E > 1 ? E : 1, [&](int r, Cand b) {
+        if (r == 0) best = b;
         if (r < E && threadIdx.x == 0) d.elite[r] = b.i;
-        prev = b;
-    }
-    if (d.term && threadIdx.x == 0) {
-        // termination test on this generation's best; count the generation about to be bred
-        const double b = fbest;
-        const bool improved = isfinite(st.ref) ? (b > st.ref + d.tol * fmax(1.0, fabs(st.ref))) : isfinite(b);
-        if (improved) {
-            st.ref = b;
-            st.stall = 0;
-        } else {
-            st.stall += 1;
-        }
-        if (d.stall_gens > 0 && st.stall >= d.stall_gens) st.stopped = 1;
-        if (!final && !st.stopped) {
-            st.gens += 1;
-            st.call_gens += 1;
-        }
-        *d.term = st;
-    }
-    if (d.stats) {
-        double sum = 0.0, ninv = 0.0;
-#pragma unroll
-        for (int v = 0; v < kRankCache; ++v) {
-            const int p = threadIdx.x + v * kRankThreads;
-            if (p >= P) break;
-            if (isfinite(fr[v])) sum += fr[v];
-            else ninv += 1.0;
-        }
-        for (int p = threadIdx.x + kRankCache * kRankThreads; p < P; p += kRankThreads) {
-            const double fp = gld(f + p);
-            if (isfinite(fp)) sum += fp;
-            else ninv += 1.0;
-        }
-        const double total = block_sum(sum);
-        const double inv = block_sum(ninv);
-        if (threadIdx.x == 0) {
-            double *row = d.stats + 4 * (size_t)gen_off;
-            const double nfin = (double)P - inv;
-            row[0] = fbest;
-            row[1] = nfin > 0.0 ? total / nfin : -INFINITY;
-            row[2] = inv;
-            row[3] = (double)argbest;
-        }
-    }
+    });
+    if (d.term && threadIdx.x == 0) term_update(d, st, best.f, final);
+    if (d.stats) rb.write_stats(d, gen_off, best);
 }
 
 hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s) {
@@ -365,7 +389,14 @@ __device__ int sus_pick(const InstDesc &d, uint32_t k, uint32_t n, uint64_t u, u
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off) {
+// With `fold` set (no instance selects by SUS or can stop early), the breed
+// workgroups of the elite slots rank the population themselves: workgroup
+// c < E finds the c-th ranked individual and copies it, and workgroup 0 also
+// keeps the termination state and writes the statistics row, so the rank
+// kernel is not launched between fitness and breeding. Children need only the
+// fitness values (tournaments), so the result is the same as with the rank
+// kernel before breed.
+__global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off, int fold) {
     const int g = blockIdx.x;
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
@@ -375,8 +406,33 @@ __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off
     const int32_t *__restrict__ src = d.pop[parity];
     int32_t *__restrict__ out = d.pop[parity ^ 1] + (size_t)c * N;
 
+    // Ranking work of the fold: workgroup c < E finds the c-th ranked individual;
+    // workgroup 0 (an elite slot, or child 0 when E = 0) keeps the termination
+    // state and writes the statistics row. The condition is uniform per workgroup.
+    int ec = -1;
+    if (fold && (c < E || (c == 0 && (d.term || d.stats)))) {
+        __shared__ RankLds sh;
+        RankBlock<4> rb{d.fitness, P, sh};                    // few registers: the child slots share the kernel
+        rb.load();
+        pga_term_state st{};
+        if (c == 0 && d.term && threadIdx.x == 0) st = *d.term;
+        Cand best{-INFINITY, 0}, pick{-INFINITY, 0};
+        rb.ranked(c + 1, [&](int r, Cand b) {
+            if (r == 0) best = b;
+            pick = b;
+        });
+        if (c == 0) {
+            if (d.term && threadIdx.x == 0) {
+                if (gen_off == 0) st.call_gens = 0;
+                term_update(d, st, best.f, 0);
+            }
+            if (d.stats) rb.write_stats(d, gen_off, best);
+        }
+        ec = pick.i;
+    }
     if (c < E) {
-        const int32_t *__restrict__ e = src + (size_t)d.elite[c] * N;
+        if (!fold) ec = d.elite[c];
+        const int32_t *__restrict__ e = src + (size_t)ec * N;
         for (int j = threadIdx.x; j < N; j += 256) out[j] = e[j];
         return;
     }
@@ -430,9 +486,9 @@ __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off
     }
 }
 
-hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, hipStream_t s) {
+hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_breed, dim3(total_inds), dim3(256), 0, s, t, parity, gen_off);
+    hipLaunchKernelGGL(k_breed, dim3(total_inds), dim3(256), 0, s, t, parity, gen_off, fold);
     return hipGetLastError();
 }
 

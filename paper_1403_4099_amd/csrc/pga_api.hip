@@ -179,6 +179,7 @@ struct Shape {
     int n_inst, tiles, inds, max_n;
     Variant v;
     int max_p, sus;      // largest P; 1 if an instance selects by SUS
+    int stop;            // 1 if an instance may stop early (termination test on)
 };
 
 hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, int32_t *status,
@@ -198,9 +199,13 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
     for (int k = 0; k < G; ++k) {
         const int parity = k & 1;
         if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
-        if ((e = timed(3, s, [&] { return launch_rank(t, k, 0, s); })) != hipSuccess) return e;
+        // Without SUS or an early stop, breeding needs the ranking only for the elite
+        // slots, and the breed kernel does it there (fold); otherwise rank first.
+        const int fold = (!sh.sus && !sh.stop) ? 1 : 0;
+        if (!fold && (e = timed(3, s, [&] { return launch_rank(t, k, 0, s); })) != hipSuccess) return e;
         if (sh.sus && (e = timed(8, s, [&] { return launch_sus(t, sh.max_p, s); })) != hipSuccess) return e;
-        if ((e = timed(4, s, [&] { return launch_breed(t, sh.inds, parity, k, s); })) != hipSuccess) return e;
+        if ((e = timed(4, s, [&] { return launch_breed(t, sh.inds, parity, k, fold, s); })) != hipSuccess)
+            return e;
     }
     const int parity = G & 1;
     if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
@@ -214,11 +219,11 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
 struct GraphKey {
     void *ws;
     int32_t *status;
-    int n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus;
+    int n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus, stop;
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus) <
+        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus, stop) <
                std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles, o.inds, o.max_n, o.ipg, o.order,
-                        o.max_p, o.sus);
+                        o.max_p, o.sus, o.stop);
     }
 };
 
@@ -385,6 +390,7 @@ int prepare_single(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, 
     sh->max_n = N;
     sh->max_p = P;
     sh->sus = 0;
+    sh->stop = 0;
     *dd = d;
     if (form == PGA_FORM_BF16X2) {
         HIP_TRY(launch_write_desc(d, 0, (InstDesc *)t->desc, (int32_t *)t->tiles, s));
@@ -587,12 +593,13 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
     int32_t *pf = (int32_t *)(hb + L.pre_off);
     int32_t *pi = pf + (n_inst + 1);
     pf[0] = pi[0] = 0;
-    Shape sh{n_inst, 0, 0, 0, Variant{form, 0, 0}, 0, 0};
+    Shape sh{n_inst, 0, 0, 0, Variant{form, 0, 0}, 0, 0, 0};
     int total_p = 0;
     for (int k = 0; k < n_inst; ++k) {
         sh.max_n = std::max(sh.max_n, (int)inst[k].N);
         sh.max_p = std::max(sh.max_p, (int)inst[k].P);
         sh.sus |= inst[k].prm.selection == PGA_SELECT_SUS ? 1 : 0;
+        sh.stop |= inst[k].prm.stall_gens > 0 ? 1 : 0;
         total_p += inst[k].P;
     }
     sh.v = variant_at(form, pick_variant(form, sh.max_n, total_p));
@@ -650,7 +657,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         return PGA_OK;
     }
     GraphKey key{ws, status, n_inst, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.order,
-                 sh.max_p, sh.sus};
+                 sh.max_p, sh.sus, sh.stop};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         hipGraph_t g = nullptr;

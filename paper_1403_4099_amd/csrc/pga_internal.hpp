@@ -193,7 +193,7 @@ hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_
 
 hipError_t launch_init(Tables t, int total_inds, hipStream_t s);
 hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s);
-hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, hipStream_t s);
+hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, hipStream_t s);
 hipError_t launch_sus(Tables t, int max_p, hipStream_t s);
 hipError_t launch_copy_back(Tables t, int total_inds, int G, hipStream_t s);
 hipError_t launch_best(const double *fitness, const int32_t *labels, int P, int N, int32_t *out,
