@@ -185,12 +185,27 @@ int pga_ewma(const double *R, int32_t N, int32_t T, int32_t ld_r, double lambda,
  * form PGA_FORM_FP64: FP64 throughout. form PGA_FORM_BF16X2: the pair sums
  * use C_hi + C_lo on MFMA with FP32 accumulation (flushed to FP64 every 512
  * stocks); diagonal, c_s, logs and the sum over clusters stay FP64.
- * C_hi/C_lo may be NULL for PGA_FORM_FP64. P = 0 is a no-op. */
+ * C_hi/C_lo may be NULL for PGA_FORM_FP64. P = 0 is a no-op.
+ * Route (both forms, also inside pga_evolve): c_s only involves the pairs
+ * within each cluster, so an individual whose clusters hold at most
+ * frac * N (N - 1) / 2 pairs (frac: pga_route_get) and N <= 2048 is
+ * evaluated from those pairs alone: FP64 entries of C (diagonal and i < j)
+ * summed exactly in 64-bit fixed point, in either form. An individual with a
+ * larger pair count, or whose cluster pairs meet an entry with |C_ij| > 1 or
+ * not finite, takes the O(N^2) pair-sum of the form as described above. */
 size_t pga_fitness_ws_bytes(int32_t N, int32_t P, int32_t form);
 int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
                 const int32_t *labels, int32_t P, int32_t form, double *fitness,
                 int32_t *n_s, double *c_s, int32_t *status, void *ws, size_t ws_bytes,
                 void *stream);
+
+/* Cluster-pair route limit (process-wide, read at each call; pga_evolve's
+ * cached graphs are keyed by it): frac in [0, 1]; 0 sends every individual to
+ * the pair-sum kernels; 1 sends every individual with N <= 2048 to the
+ * cluster-pair kernel. PGA_ERR_ARG outside [0, 1] or NaN. */
+#define PGA_ROUTE_FRAC_DEFAULT (1.0 / 64.0)
+int pga_route_set(double frac);
+double pga_route_get(void);
 
 /* ---- kernel variants and autotuning ------------------------------------- */
 /* The pair-sum kernel of each form comes in variants that differ only in how
@@ -282,7 +297,7 @@ int pga_best(const double *fitness, const int32_t *labels, int32_t P, int32_t N,
  * elapsed milliseconds and launch count for kernel id
  *   0 pair-sum FP64, 1 pair-sum BF16x2 MFMA, 2 finish (n_s, c_s, L_c),
  *   3 rank/stats, 4 breed, 5 correlate, 6 split, 7 init, 8 SUS ranks and
- *   weights, 9 EWMA correlation. */
+ *   weights, 9 EWMA correlation, 10 cluster-pair fitness. */
 int pga_timing_enable(int on);
 int pga_timing_reset(void);
 int pga_timing_read(int kernel_id, double *total_ms, int64_t *count);

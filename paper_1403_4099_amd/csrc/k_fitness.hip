@@ -175,6 +175,13 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, kept scalar
     const int lane = threadIdx.x & 63;
     const int pbase = pb * (kFp64Waves * B) + wave * B;
+    if (d.route) {                                   // wave-uniform: the waves share no barrier
+        int any = 0;
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (pbase + b < P) any |= gld(d.route + pbase + b);
+        if (!any) return;
+    }
     const int32_t *__restrict__ labels = d.pop[parity];
     const double *__restrict__ C = d.C;
 
@@ -333,6 +340,77 @@ __host__ __device__ __forceinline__ size_t finish_lds_bytes(int max_n) {
            2 * kFinWaves * sizeof(double);
 }
 
+// Per-label outputs and the log terms of Eq. 8 from n_s (cnt) and c_s held in
+// 64-bit fixed point (csum, scale 2^sc); thread 0 writes fitness[p]. Called by
+// all threads of a kFinThreads workgroup after the barrier that closed the
+// writes to cnt and csum. lst holds kFinWaves lists of lst_stride labels.
+__device__ __forceinline__ void finish_terms(const InstDesc &d, int p, int N, const int *cnt,
+                                             const long long *csum, int sc, uint16_t *lst, int lst_stride,
+                                             double *red, int32_t *status) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
+    // Pass A (wave w, labels [w Q, (w + 1) Q)): per-label outputs, and the labels
+    // with n_s > 1 compacted in ascending order, so the log terms run with every
+    // lane busy.
+    const int QN = finish_quarter(N);                // this instance's quarter; storage is sized by max_n
+    const int s_lo = wave * QN, s_hi = min(N, s_lo + QN);
+    uint16_t *wl = lst + (size_t)wave * lst_stride;
+    int nlist = 0;
+    for (int s0 = s_lo; s0 < s_hi; s0 += 64) {
+        const int s = s0 + lane;
+        const int n = s < s_hi ? cnt[s] : 0;
+        if (s < s_hi) {
+            if (d.n_s_out) gst(d.n_s_out + (size_t)p * N + s, n);
+            if (d.c_s_out) gst(d.c_s_out + (size_t)p * N + s, ldexp((double)csum[s], -sc));
+        }
+        const uint64_t m = __ballot(n > 1);
+        if (n > 1) wl[nlist + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)s;
+        nlist += __popcll(m);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // Pass B: the two FP64 log terms of Eq. 8 for each listed cluster.
+    double L = 0.0;
+    int nbad = 0;
+    for (int m = lane; m < nlist; m += 64) {
+        const int s = wl[m];
+        const double nd = (double)cnt[s];
+        const double c = ldexp((double)csum[s], -sc);
+        const double n2 = nd * nd;
+        if (!(c > 0.0 && c < n2)) {
+            nbad += 1;
+        } else {
+            L += log(nd / c) + (nd - 1.0) * log((n2 - nd) / (n2 - c));
+        }
+    }
+    {
+        const double wl_sum = wave_sum(L);
+        const double wb_sum = wave_sum((double)nbad);
+        if (lane == 0) {
+            red[wave] = wl_sum;                      // every read of red above precedes the
+            red[kFinWaves + wave] = wb_sum;          // barrier that closed the atomics
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double Ltot = 0.0, badtot = 0.0;
+        for (int w = 0; w < kFinWaves; ++w) {
+            Ltot += red[w];
+            badtot += red[kFinWaves + w];
+        }
+        if (badtot > 0.0) {
+            d.fitness[p] = -INFINITY;
+            if (status) {
+                atomicAdd(&status[PGA_ST_DOMAIN], (int)badtot);
+                atomicAdd(&status[PGA_ST_NONFINITE], 1);
+            }
+        } else {
+            d.fitness[p] = 0.5 * Ltot;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int parity, int32_t *status) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
@@ -342,6 +420,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int
     if (inst_stopped(d)) return;                     // uniform over the workgroup
     const int N = d.N;
     const int p = g - t.inds[k];
+    if (d.route && gld(d.route + p) == 0) return;    // evaluated by the cluster-pair kernel
     const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
     const double *__restrict__ v = d.wsum + (size_t)p * N;
     long long *csum = (long long *)smem;
@@ -434,67 +513,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int
     }
     __syncthreads();
 
-    // Pass A (wave w, labels [w Q, (w + 1) Q)): per-label outputs, and the labels
-    // with n_s > 1 compacted in ascending order, so the log terms run with every
-    // lane busy.
-    const int QN = finish_quarter(N);                // this instance's quarter; storage is sized by max_n
-    const int s_lo = wave * QN, s_hi = min(N, s_lo + QN);
-    uint16_t *wl = lst + (size_t)wave * finish_quarter(max_n);
-    int nlist = 0;
-    for (int s0 = s_lo; s0 < s_hi; s0 += 64) {
-        const int s = s0 + lane;
-        const int n = s < s_hi ? cnt[s] : 0;
-        if (s < s_hi) {
-            if (d.n_s_out) gst(d.n_s_out + (size_t)p * N + s, n);
-            if (d.c_s_out) gst(d.c_s_out + (size_t)p * N + s, ldexp((double)csum[s], -sc));
-        }
-        const uint64_t m = __ballot(n > 1);
-        if (n > 1) wl[nlist + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)s;
-        nlist += __popcll(m);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    // Pass B: the two FP64 log terms of Eq. 8 for each listed cluster.
-    double L = 0.0;
-    int nbad = 0;
-    for (int m = lane; m < nlist; m += 64) {
-        const int s = wl[m];
-        const double nd = (double)cnt[s];
-        const double c = ldexp((double)csum[s], -sc);
-        const double n2 = nd * nd;
-        if (!(c > 0.0 && c < n2)) {
-            nbad += 1;
-        } else {
-            L += log(nd / c) + (nd - 1.0) * log((n2 - nd) / (n2 - c));
-        }
-    }
-    {
-        const double wl_sum = wave_sum(L);
-        const double wb_sum = wave_sum((double)nbad);
-        if (lane == 0) {
-            red[wave] = wl_sum;                      // every read of red above precedes the
-            red[kFinWaves + wave] = wb_sum;          // barrier that closed the atomics
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double Ltot = 0.0, badtot = 0.0;
-        for (int w = 0; w < kFinWaves; ++w) {
-            Ltot += red[w];
-            badtot += red[kFinWaves + w];
-        }
-        if (badtot > 0.0) {
-            d.fitness[p] = -INFINITY;
-            if (status) {
-                atomicAdd(&status[PGA_ST_DOMAIN], (int)badtot);
-                atomicAdd(&status[PGA_ST_NONFINITE], 1);
-            }
-        } else {
-            d.fitness[p] = 0.5 * Ltot;
-        }
-    }
+    finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(max_n), red, status);
 }
 
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status,
@@ -502,6 +521,228 @@ hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_
     if (total_inds <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finish, dim3(total_inds), dim3(kFinThreads), finish_lds_bytes(max_n), s, t, max_n,
                        parity, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cluster-pair fitness (exact FP64 route). c_s of Eq. 6 only involves the pairs
+// inside cluster s, so an individual with few such pairs is evaluated from
+// them directly instead of by the O(N^2) pair-sum: one 256-thread workgroup
+// per individual
+//   1. labels into LDS (invalid labels: fitness -inf, as the finish does);
+//   2. n_s by LDS atomics; pairs = sum_s n_s (n_s - 1) / 2 and max n_s;
+//   3. pairs above the limit: route[p] = 1 (the pair-sum and finish kernels
+//      evaluate it) and stop;
+//   4. members grouped by cluster (counting sort on the exclusive prefix of
+//      n_s); position x of the grouped list gets its index a(x) within its
+//      cluster, and W, the exclusive prefix of a, numbers the pairs: pair q
+//      belongs to the position x with W[x] <= q < W[x+1] and joins it with
+//      the earlier member at position x - a(x) + (q - W[x]);
+//   5. c_s = sum_{j in s} C_jj + 2 sum_{pairs} C_ij (upper triangle, as the
+//      FP64 pair-sum reads it) accumulated in 64-bit fixed point: with
+//      |C| <= 1 every partial sum is bounded by max n_s^2, and the scale 2^sc
+//      keeps max n_s^2 2^sc <= 2^61, so the integer sums are exact and the
+//      result does not depend on the order of the atomics;
+//   6. an entry with |C| > 1 or not finite sends the individual to the dense
+//      route (step 3's flag), which treats it exactly as before; otherwise
+//      route[p] = 0 and the log terms follow as in the finish.
+constexpr int kSparseMaxN = 2048;                  // larger instances always take the dense route
+
+__host__ __device__ __forceinline__ size_t pad16(size_t b) { return (b + 15) / 16 * 16; }
+// LDS: csum int64[n] | cnt int32[n] | begin int32[n] | W int32[n + 1] | members uint16[n]
+//      | labels uint16[n] | finish lists | kFinWaves x 2 doubles | 16 int32
+__host__ __device__ __forceinline__ size_t sparse_lds_bytes(int n) {
+    return pad16(8 * (size_t)n) + 2 * pad16(4 * (size_t)n) + pad16(4 * ((size_t)n + 1)) +
+           2 * pad16(2 * (size_t)n) + finish_lst_bytes(n) + 2 * kFinWaves * sizeof(double) + 16 * sizeof(int);
+}
+
+// Exclusive prefix sum of a[0 .. n) into out (may alias a); thread t scans a
+// contiguous run of ceil(n / 256). Returns the total; ends with a barrier.
+__device__ __forceinline__ int block_exscan(const int *a, int *out, int n, int *wtot) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (n + kFinThreads - 1) / kFinThreads;
+    const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+    int own = 0;
+    for (int x = b0; x < b1; ++x) own += a[x];
+    int inc = own;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    int run = inc - own, total = 0;
+#pragma unroll
+    for (int w = 0; w < kFinWaves; ++w) {
+        if (w < wave) run += wtot[w];
+        total += wtot[w];
+    }
+    for (int x = b0; x < b1; ++x) {
+        const int v = a[x];
+        out[x] = run;
+        run += v;
+    }
+    __syncthreads();
+    return total;
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int parity, double frac,
+                                                        int32_t *status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
+    const int g = blockIdx.x;
+    const int k = find_inst(t.inds, t.n_inst, g);
+    const InstDesc &d = t.desc[k];
+    if (inst_stopped(d)) return;                     // uniform over the workgroup
+    const int N = d.N;
+    const int p = g - t.inds[k];
+    if (N > lds_n) {                                 // lds_n <= kSparseMaxN
+        if (tid == 0) gst(d.route + p, 1);
+        return;
+    }
+    const size_t n = (size_t)lds_n;
+    unsigned char *b = smem;
+    long long *csum = (long long *)b;   b += pad16(8 * n);
+    int *cnt = (int *)b;                b += pad16(4 * n);
+    int *begin = (int *)b;              b += pad16(4 * n);
+    int *W = (int *)b;                  b += pad16(4 * (n + 1));
+    uint16_t *members = (uint16_t *)b;  b += pad16(2 * n);
+    uint16_t *labs = (uint16_t *)b;     b += pad16(2 * n);
+    uint16_t *lst = (uint16_t *)b;      b += finish_lst_bytes(lds_n);
+    double *red = (double *)b;          b += 2 * kFinWaves * sizeof(double);
+    int *ired = (int *)b;               // [0, 4) flags, [4, 8) max n_s, [8, 12) scan totals
+
+    const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
+    const double *__restrict__ C = d.C;
+
+    int bad = 0;
+    for (int j = tid; j < N; j += kFinThreads) {
+        const int l = gld(lab + j);
+        if (l < 0 || l >= N) bad = 1;
+        else labs[j] = (uint16_t)l;
+        cnt[j] = 0;
+        csum[j] = 0;
+    }
+    const int wbad = __any(bad) ? 1 : 0;             // all lanes vote, lane 0 records
+    if (lane == 0) ired[wave] = wbad;
+    __syncthreads();
+    if (ired[0] | ired[1] | ired[2] | ired[3]) {     // as the finish: labels outside [0, N)
+        if (tid == 0) {
+            gst(d.route + p, 0);
+            d.fitness[p] = -INFINITY;
+            if (status) {
+                atomicAdd(&status[PGA_ST_LABEL], 1);
+                atomicAdd(&status[PGA_ST_NONFINITE], 1);
+            }
+        }
+        if (d.n_s_out)
+            for (int s = tid; s < N; s += kFinThreads) d.n_s_out[(size_t)p * N + s] = 0;
+        if (d.c_s_out)
+            for (int s = tid; s < N; s += kFinThreads) d.c_s_out[(size_t)p * N + s] = 0.0;
+        return;
+    }
+    for (int j = tid; j < N; j += kFinThreads) atomicAdd(&cnt[labs[j]], 1);
+    __syncthreads();
+
+    long long pr = 0;
+    int nm = 0;
+    for (int s = tid; s < N; s += kFinThreads) {
+        const int c = cnt[s];
+        pr += (long long)c * (c - 1) / 2;
+        nm = max(nm, c);
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        pr += __shfl_xor(pr, m, 64);
+        nm = max(nm, __shfl_xor(nm, m, 64));
+    }
+    if (lane == 0) {
+        red[wave] = (double)pr;                      // exact: pr <= N^2 / 2 < 2^53
+        ired[4 + wave] = nm;
+    }
+    __syncthreads();
+    double pairs = 0.0;
+    int nmax = 0;
+#pragma unroll
+    for (int w = 0; w < kFinWaves; ++w) {
+        pairs += red[w];
+        nmax = max(nmax, ired[4 + w]);
+    }
+    if (pairs > floor(frac * 0.5 * (double)N * (double)(N - 1))) {
+        if (tid == 0) gst(d.route + p, 1);
+        return;                                      // uniform
+    }
+
+    block_exscan(cnt, begin, N, ired + 8);           // begin[s]: first position of cluster s
+    for (int j = tid; j < N; j += kFinThreads) members[atomicAdd(&begin[labs[j]], 1)] = (uint16_t)j;
+    __syncthreads();                                 // begin[s] is now the end of cluster s
+    for (int x = tid; x < N; x += kFinThreads) {
+        const int l = labs[members[x]];
+        W[x] = x - (begin[l] - cnt[l]);              // a(x)
+    }
+    __syncthreads();
+    const int T = block_exscan(W, W, N, ired + 8);   // T == pairs
+    if (tid == 0) W[N] = T;
+    int e;
+    frexp((double)nmax * (double)nmax, &e);          // max n_s^2 < 2^e
+    const int sc = 61 - e;
+    __syncthreads();
+
+    int badc = 0;
+    for (int j = tid; j < N; j += kFinThreads) {
+        const double c = gld(C + (size_t)j * N + j);
+        if (!(fabs(c) <= 1.0)) badc = 1;
+        else atomicAdd((unsigned long long *)&csum[labs[j]], (unsigned long long)llrint(ldexp(c, sc)));
+    }
+    // Four pairs per thread and round, their loads issued before any is used.
+    constexpr int kQ = 4;
+    for (int q0 = tid; q0 < T; q0 += kQ * kFinThreads) {
+        double c[kQ];
+        int l[kQ];
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) {
+            const int q = q0 + u * kFinThreads;
+            l[u] = -1;
+            c[u] = 0.0;
+            if (q < T) {
+                int lo = 0, hi = N;                  // W[lo] <= q < W[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (W[mid] <= q) lo = mid;
+                    else hi = mid;
+                }
+                const int x = lo;
+                const int y = x - (W[x + 1] - W[x]) + (q - W[x]);
+                const int j = members[x], i = members[y];
+                c[u] = gld(C + (size_t)min(i, j) * N + max(i, j));
+                l[u] = labs[j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) {
+            if (l[u] < 0) continue;
+            if (!(fabs(c[u]) <= 1.0)) badc = 1;
+            else atomicAdd((unsigned long long *)&csum[l[u]], (unsigned long long)llrint(ldexp(2.0 * c[u], sc)));
+        }
+    }
+    const int wbadc = __any(badc) ? 1 : 0;
+    if (lane == 0) ired[wave] = wbadc;
+    __syncthreads();
+    if (ired[0] | ired[1] | ired[2] | ired[3]) {
+        if (tid == 0) gst(d.route + p, 1);
+        return;
+    }
+    if (tid == 0) gst(d.route + p, 0);
+    finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(lds_n), red, status);
+}
+
+hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int32_t *status,
+                         hipStream_t s) {
+    if (total_inds <= 0) return hipSuccess;
+    const int n = std::min(max_n, kSparseMaxN);
+    hipLaunchKernelGGL(k_sparse, dim3(total_inds), dim3(kFinThreads), sparse_lds_bytes(n), s, t, n, parity,
+                       frac, status);
     return hipGetLastError();
 }
 

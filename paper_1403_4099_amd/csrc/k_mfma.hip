@@ -326,6 +326,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(B == 16 ? 2
     const int n_pairs = (n_jb + 1) / 2;
     const TilePos tp = tile_pos(local, n_pairs, (d.P + B - 1) / B, order);
     const int jp = tp.jp, pb = tp.pb;
+    if (d.route) {                                            // uniform: skip batches the cluster-pair
+        int any = 0;                                          // kernel evaluated entirely
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (pb * B + b < d.P) any |= gld(d.route + pb * B + b);
+        if (!any) return;
+    }
     const MfmaLds s{(uint32_t *)lds, lds + sizeof(uint16_t) * kMfmaRowCodes,
                     lds + sizeof(uint16_t) * kMfmaRowCodes + (size_t)B * cstride, cstride};
     {

@@ -69,7 +69,7 @@ struct TimedLaunch {
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_tl;
-constexpr int kTimers = 10;
+constexpr int kTimers = 11;
 double g_tsum[kTimers] = {0};
 int64_t g_tcnt[kTimers] = {0};
 
@@ -100,6 +100,18 @@ hipError_t timed(int id, hipStream_t s, F &&launch) {
 bool timing_on() {
     std::lock_guard<std::mutex> lk(g_tmu);
     return g_timing;
+}
+
+// ---- route limit -----------------------------------------------------------------
+// An individual whose clusters hold at most frac * N (N - 1) / 2 pairs is
+// evaluated by the cluster-pair kernel; 0 turns that route off. Read at every
+// call (and part of a captured graph's key).
+std::mutex g_route_mu;
+double g_route_frac = PGA_ROUTE_FRAC_DEFAULT;
+
+double route_frac() {
+    std::lock_guard<std::mutex> lk(g_route_mu);
+    return g_route_frac;
 }
 
 // ---- tuning table ----------------------------------------------------------------
@@ -133,7 +145,7 @@ int pick_variant(int form, int max_n, int total_p) {
 // and, for SUS selection, [rank P int32][weight prefix P uint64].
 struct Layout {
     size_t desc_off, pre_off, inst_off;
-    std::vector<size_t> wsum_off, elite_off, hs_off, ls_off, rank_off, cum_off;
+    std::vector<size_t> wsum_off, elite_off, hs_off, ls_off, rank_off, cum_off, route_off;
     size_t total;
 };
 
@@ -159,6 +171,8 @@ Layout make_layout(const int32_t *Ns, const int32_t *Ps, int n, int form, const 
         off = align_up(off + (sus ? sizeof(int32_t) * (size_t)Ps[k] : 0), 256);
         L.cum_off.push_back(off);
         off = align_up(off + (sus ? sizeof(uint64_t) * (size_t)Ps[k] : 0), 256);
+        L.route_off.push_back(off);
+        off = align_up(off + sizeof(int32_t) * (size_t)Ps[k], 256);
     }
     L.total = off;
     return L;
@@ -180,11 +194,16 @@ struct Shape {
     Variant v;
     int max_p, sus;      // largest P; 1 if an instance selects by SUS
     int stop;            // 1 if an instance may stop early (termination test on)
+    double frac;         // cluster-pair route limit (0: off; then every route pointer is null)
 };
 
 hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, int32_t *status,
                        hipStream_t s) {
     hipError_t e;
+    if (sh.frac > 0.0 &&
+        (e = timed(10, s, [&] { return launch_sparse(t, sh.inds, sh.max_n, parity, sh.frac, status, s); })) !=
+            hipSuccess)
+        return e;
     if (form == PGA_FORM_FP64)
         e = timed(0, s, [&] { return launch_pairsum_fp64(t, sh.tiles, parity, sh.v, s); });
     else
@@ -220,10 +239,11 @@ struct GraphKey {
     void *ws;
     int32_t *status;
     int n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus, stop;
+    double frac;
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus, stop) <
+        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus, stop, frac) <
                std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles, o.inds, o.max_n, o.ipg, o.order,
-                        o.max_p, o.sus, o.stop);
+                        o.max_p, o.sus, o.stop, o.frac);
     }
 };
 
@@ -355,7 +375,7 @@ namespace {
 int prepare_single(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
                    const int32_t *labels, int32_t P, int32_t form, double *fitness, int32_t *n_s,
                    double *c_s, void *ws, size_t ws_bytes, hipStream_t s, Tables *t, Shape *sh,
-                   InstDesc *dd) {
+                   InstDesc *dd, double frac) {
     if (N < 1 || P < 0) return PGA_ERR_ARG;
     if (form != PGA_FORM_FP64 && form != PGA_FORM_BF16X2) return PGA_ERR_ARG;
     if (N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
@@ -384,6 +404,7 @@ int prepare_single(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, 
     }
     d.n_s_out = n_s;
     d.c_s_out = c_s;
+    if (frac > 0.0) d.route = (int32_t *)((char *)ws + L.route_off[0]);
     *t = tables_at(ws, L, 1);
     sh->n_inst = 1;
     sh->inds = P;
@@ -391,6 +412,7 @@ int prepare_single(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, 
     sh->max_p = P;
     sh->sus = 0;
     sh->stop = 0;
+    sh->frac = frac;
     *dd = d;
     if (form == PGA_FORM_BF16X2) {
         HIP_TRY(launch_write_desc(d, 0, (InstDesc *)t->desc, (int32_t *)t->tiles, s));
@@ -415,7 +437,7 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
     Shape sh;
     InstDesc d;
     const int rc = prepare_single(C, C_hi, C_lo, N, labels, P, form, fitness, n_s, c_s, ws, ws_bytes, s,
-                                  &t, &sh, &d);
+                                  &t, &sh, &d, route_frac());
     if (rc != PGA_OK || P == 0) return rc;
     HIP_TRY(use_variant(d, t, form, pick_variant(form, N, P), &sh, s));
     HIP_TRY(run_fitness(t, sh, form, 0, status, s));
@@ -470,7 +492,9 @@ int pga_tune(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_
     Tables t;
     Shape sh;
     InstDesc d;
-    int rc = prepare_single(C, C_hi, C_lo, N, labels, P, form, fit, nullptr, nullptr, ws, base, s, &t, &sh, &d);
+    // The variants differ only in the pair-sum kernel, so every individual takes that route here.
+    int rc = prepare_single(C, C_hi, C_lo, N, labels, P, form, fit, nullptr, nullptr, ws, base, s, &t, &sh, &d,
+                            0.0);
     if (rc != PGA_OK) return rc;
     // The GPU's clock rises under sustained load, so the variants are timed round-robin over
     // kTuneRounds rounds after a warm-up, back to back with no host synchronisation between
@@ -593,7 +617,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
     int32_t *pf = (int32_t *)(hb + L.pre_off);
     int32_t *pi = pf + (n_inst + 1);
     pf[0] = pi[0] = 0;
-    Shape sh{n_inst, 0, 0, 0, Variant{form, 0, 0}, 0, 0, 0};
+    Shape sh{n_inst, 0, 0, 0, Variant{form, 0, 0}, 0, 0, 0, route_frac()};
     int total_p = 0;
     for (int k = 0; k < n_inst; ++k) {
         sh.max_n = std::max(sh.max_n, (int)inst[k].N);
@@ -636,6 +660,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
             d.sus_rank = (int32_t *)((char *)ws + L.rank_off[k]);
             d.sus_cum = (uint64_t *)((char *)ws + L.cum_off[k]);
         }
+        if (sh.frac > 0.0) d.route = (int32_t *)((char *)ws + L.route_off[k]);
         d.ind0 = pi[k];
         hd[k] = d;
         pf[k + 1] = pf[k] + pair_tiles(I.N, I.P, sh.v);
@@ -657,7 +682,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         return PGA_OK;
     }
     GraphKey key{ws, status, n_inst, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.order,
-                 sh.max_p, sh.sus, sh.stop};
+                 sh.max_p, sh.sus, sh.stop, sh.frac};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         hipGraph_t g = nullptr;
@@ -708,6 +733,16 @@ int pga_best(const double *fitness, const int32_t *labels, int32_t P, int32_t N,
     if (out_index) *out_index = hl[N];
     return PGA_OK;
 }
+
+// ---- route limit ----------------------------------------------------------------------------
+int pga_route_set(double frac) {
+    if (!(frac >= 0.0 && frac <= 1.0)) return PGA_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_route_mu);
+    g_route_frac = frac;
+    return PGA_OK;
+}
+
+double pga_route_get(void) { return route_frac(); }
 
 // ---- timing ----------------------------------------------------------------------------------
 int pga_timing_enable(int on) {

@@ -35,6 +35,8 @@ struct InstDesc {
     int32_t pad_;
     int32_t *sus_rank;          // P: 1-based rank (SUS only; workspace)
     uint64_t *sus_cum;          // P: inclusive prefix of the SUS weights (workspace)
+    int32_t *route;             // P: 1 = evaluated by pair-sum + finish, 0 = by the cluster-pair
+                                // kernel (workspace); null: every individual takes the pair-sum
 };
 
 // Prefix tables: for n instances, arrays of n + 1 exclusive prefix sums.
@@ -190,6 +192,8 @@ hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Vari
                                hipStream_t s);
 hipError_t launch_scale_split(Tables t, int max_ld, hipStream_t s);
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status, hipStream_t s);
+hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int32_t *status,
+                         hipStream_t s);
 
 hipError_t launch_init(Tables t, int total_inds, hipStream_t s);
 hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s);

@@ -31,7 +31,7 @@ EVOLVE_INIT = 1
 EVOLVE_EAGER = 2
 P_CROSS_DEFAULT = int(0.9 * 2**32)
 KERNELS = {"pairsum_fp64": 0, "pairsum_mfma": 1, "finish": 2, "rank": 3, "breed": 4,
-           "correlate": 5, "split": 6, "init": 7, "sus": 8, "ewma": 9}
+           "correlate": 5, "split": 6, "init": 7, "sus": 8, "ewma": 9, "cluster_pairs": 10}
 EWMA_RESET, EWMA_MARKET = 1, 2
 
 SYMBOLS = [
@@ -40,7 +40,8 @@ SYMBOLS = [
     "pga_fitness_ws_bytes", "pga_fitness", "pga_evolve_ws_bytes", "pga_evolve",
     "pga_best_ws_bytes", "pga_best", "pga_timing_enable", "pga_timing_reset", "pga_timing_read",
     "pga_variant_count", "pga_variant_info", "pga_tune_ws_bytes", "pga_tune", "pga_tune_set",
-    "pga_tune_get", "pga_ewma_ws_bytes", "pga_ewma", "pga_peak_mfma_bf16",
+    "pga_tune_get", "pga_ewma_ws_bytes", "pga_ewma", "pga_peak_mfma_bf16", "pga_route_set",
+    "pga_route_get",
 ]
 
 
@@ -107,6 +108,8 @@ def load(path: str = LIB_PATH):
         "pga_ewma_ws_bytes": ([i32, i32], sz),
         "pga_ewma": ([vp, i32, i32, i32, ct.c_double, i32, vp, vp, vp, vp, vp, vp, sz, vp], ct.c_int),
         "pga_peak_mfma_bf16": ([vp, i32, i32, ct.POINTER(ct.c_double), vp], ct.c_int),
+        "pga_route_set": ([ct.c_double], ct.c_int),
+        "pga_route_get": ([], ct.c_double),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -267,6 +270,32 @@ def tune(C: torch.Tensor, labels: torch.Tensor, form: str = "fp64", hi=None, lo=
                     ws.numel(), ct.byref(v), ms, _stream())
     _check(rc, "pga_tune")
     return v.value, [float(x) for x in ms]
+
+
+def route_set(frac: float):
+    """Cluster-pair route limit: individuals with at most frac * N (N - 1) / 2
+    within-cluster pairs (and N <= 2048) skip the O(N^2) pair-sum; 0 = off."""
+    _check(load().pga_route_set(float(frac)), "pga_route_set")
+
+
+def route_get() -> float:
+    return float(load().pga_route_get())
+
+
+class route:
+    """Context manager: run a block with another route limit, then restore it."""
+
+    def __init__(self, frac: float):
+        self.frac = frac
+
+    def __enter__(self):
+        self.prev = route_get()
+        route_set(self.frac)
+        return self
+
+    def __exit__(self, *exc):
+        route_set(self.prev)
+        return False
 
 
 def tune_set(form: str, N: int, P: int, variant: int):

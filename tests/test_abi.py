@@ -137,3 +137,21 @@ def test_peak_mfma_rejects_bad_arguments():
     buf = ct.create_string_buffer(64)
     assert L.pga_peak_mfma_bf16(ct.cast(buf, ct.c_void_p), 0, 1, None, None) == -1  # PGA_ERR_ARG
     assert L.pga_peak_mfma_bf16(ct.cast(buf, ct.c_void_p), 1, 0, None, None) == -1  # PGA_ERR_ARG
+
+
+def test_route_limit_is_host_state_with_checked_range(lib):
+    """The cluster-pair route limit is a host-side setting: set, read back, range-checked."""
+    prev = pga.route_get()
+    assert prev == 1.0 / 64.0                        # PGA_ROUTE_FRAC_DEFAULT
+    try:
+        for bad in (-0.1, 1.5, float("nan")):
+            assert lib.pga_route_set(bad) == -1      # PGA_ERR_ARG
+            assert pga.route_get() == prev
+        for ok in (0.0, 0.25, 1.0):
+            assert lib.pga_route_set(ok) == 0
+            assert pga.route_get() == ok
+        with pga.route(0.5):
+            assert pga.route_get() == 0.5
+        assert pga.route_get() == 1.0
+    finally:
+        pga.route_set(prev)

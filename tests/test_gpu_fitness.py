@@ -12,6 +12,14 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
+@pytest.fixture(autouse=True)
+def _dense_route():
+    """These tests check the O(N^2) pair-sum kernels: every individual takes that route
+    (the cluster-pair route has its own tests)."""
+    with pga.route(0.0):
+        yield
+
+
 def _g(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 

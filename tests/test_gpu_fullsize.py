@@ -4,6 +4,8 @@ in the launch configuration bench.py times (variant 0, the tuner's choice at thi
 * pga_correlate of the full window against the oracle's correlation;
 * every individual's n_s, and sampled individuals' c_s and L_c, against the oracle, in both
   forms (the oracle computes the sampled individuals one by one);
+* the default route (cluster-pair route for the random half, pair-sum for the near-planted half):
+  each individual's result equals bit for bit that of the route its pair count selects;
 * one generation of the whole population in lockstep with the oracle: the oracle breeds from the
   GPU's population and fitness, and the GPU's next population must match bit for bit."""
 import numpy as np
@@ -47,6 +49,13 @@ def variant0():
         pga.tune_set(form, N, P, -1)
 
 
+@pytest.fixture()
+def dense():
+    """Every individual through the O(N^2) pair-sum kernel of its form."""
+    with pga.route(0.0):
+        yield
+
+
 def test_correlate_full_window(full):
     w, C, _, _ = full
     Cg = pga.correlate(_g(w.R)).cpu().numpy()
@@ -54,7 +63,7 @@ def test_correlate_full_window(full):
     assert np.array_equal(Cg, Cg.T) and np.all(np.diag(Cg) == 1.0)
 
 
-def test_fitness_fp64_full_population(full, variant0):
+def test_fitness_fp64_full_population(full, variant0, dense):
     _, C, pop, sample = full
     f_g, ns_g, cs_g = pga.fitness(_g(C), _g(pop), "fp64", want_ns=True, want_cs=True)
     f_g, ns_g, cs_g = f_g.cpu().numpy(), ns_g.cpu().numpy(), cs_g.cpu().numpy()
@@ -68,7 +77,7 @@ def test_fitness_fp64_full_population(full, variant0):
     say(f"  fp64: max |dL|/M = {np.max(np.abs(f_g[sample] - f_o) / np.maximum(mag, 1e-300)):.2e}")
 
 
-def test_fitness_bf16x2_full_population(full, variant0):
+def test_fitness_bf16x2_full_population(full, variant0, dense):
     _, C, pop, sample = full
     Cg = _g(C)
     hi, lo = pga.split(Cg)
@@ -106,3 +115,29 @@ def test_one_generation_lockstep_full_population(full, variant0, form):
     assert np.array_equal(I.pop.cpu().numpy(), nxt)
     # the final fitness of the call is that of the new population
     assert torch.equal(I.fitness, pga.fitness(Cg, I.pop, form, hi=hi, lo=lo))
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+def test_fitness_default_route_full_population(full, variant0, form):
+    _, C, pop, sample = full
+    Cg, popg = _g(C), _g(pop)
+    hi = lo = None
+    if form == "bf16x2":
+        hi, lo = pga.split(Cg)
+    frac = pga.route_get()
+    lim = int(np.floor(frac * 0.5 * N * (N - 1)))
+    ns = np.stack([np.bincount(row, minlength=N) for row in pop]).astype(np.int64)
+    on = (ns * (ns - 1) // 2).sum(axis=1) <= lim
+    say(f"  {form}: {int(on.sum())} of {P} individuals within the pair limit {lim}")
+    assert on[: P // 2].all()
+    f_mix = pga.fitness(Cg, popg, form, hi=hi, lo=lo).cpu().numpy()
+    with pga.route(1.0):
+        f_pairs = pga.fitness(Cg, popg, form, hi=hi, lo=lo).cpu().numpy()
+    with pga.route(0.0):
+        f_dense = pga.fitness(Cg, popg, form, hi=hi, lo=lo).cpu().numpy()
+    assert np.array_equal(f_mix[on], f_pairs[on])
+    assert np.array_equal(f_mix[~on], f_dense[~on])
+    f_o, mag = O.fitness(C, pop[sample], want_mag=True)
+    sp = on[sample]
+    assert np.all(np.abs(f_mix[sample][sp] - f_o[sp]) <= fitness_tol(mag[sp], 1e-10))
+    assert np.all(np.abs(f_pairs[sample] - f_o) <= fitness_tol(mag, 1e-10))

@@ -1,0 +1,212 @@
+"""GPU parity of the cluster-pair route of pga_fitness / pga_evolve.
+
+An individual whose clusters hold at most frac * N (N - 1) / 2 pairs (and N <= 2048) is
+evaluated from those pairs alone (exact FP64 in both forms); every other individual takes the
+O(N^2) pair-sum of its form. Checked here:
+* the pair route against the oracle (FP64 tolerance), with n_s, c_s and status;
+* the choice itself: in a mixed population every individual's result equals, bit for bit, the
+  all-pairs result when its pair count (counted on the host) is within the limit and the
+  all-dense result otherwise, at the limit and one pair past it included;
+* entries with |C_ij| > 1 or NaN inside a cluster, N above 2048 and invalid labels give exactly
+  the dense route's results and status;
+* evolution through the route (graph and eager) in lockstep with the oracle's breeding."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1403_4099_amd import pga, synth
+from gpu_cases import corr, fitness_tol, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _g(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def pair_counts(pop, N):
+    return np.array([int((lambda n: (n * (n - 1) // 2).sum())(np.bincount(r, minlength=N).astype(np.int64)))
+                     for r in pop])
+
+
+def limit(frac, N):
+    return math.floor(frac * 0.5 * N * (N - 1))
+
+
+def _fit(C, pop, form, frac, **kw):
+    Cg = _g(C)
+    hi = lo = None
+    if form == "bf16x2":
+        hi, lo = pga.split(Cg)
+    with pga.route(frac):
+        return pga.fitness(Cg, _g(pop), form, hi=hi, lo=lo, **kw)
+
+
+PAIR_CASES = [
+    # N, P, K (labels in [0, K)), seed
+    (1, 3, 1, 0),
+    (2, 5, 1, 1),
+    (18, 100, 3, 2),
+    (63, 70, 63, 3),
+    (130, 64, 9, 4),
+    (257, 65, 30, 5),
+    (1000, 40, 1000, 6),
+    (1024, 33, 16, 7),
+    (2048, 6, 2048, 8),
+    (2048, 3, 3, 9),
+]
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+@pytest.mark.parametrize("N,P,K,seed", PAIR_CASES, ids=[f"N{c[0]}-P{c[1]}-K{c[2]}" for c in PAIR_CASES])
+def test_pair_route_matches_oracle(N, P, K, seed, form):
+    say(f"pair route {form} N={N} P={P} K={K}")
+    C, planted = corr(N, T=128, seed=seed)
+    pop = synth.random_labelings(P, N, seed=seed, K=K)
+    if P > 4:
+        pop[-2:] = synth.perturbed_labelings(planted, 2, 0.05, seed)
+    f_o, ns_o, cs_o, mag = O.fitness(C, pop, want_ns=True, want_cs=True, want_mag=True)
+    st = pga.new_status()
+    f_g, ns_g, cs_g = _fit(C, pop, form, 1.0, want_ns=True, want_cs=True, status=st)
+    torch.cuda.synchronize()
+    assert np.array_equal(ns_g.cpu().numpy(), ns_o)
+    assert np.all(np.abs(cs_g.cpu().numpy() - cs_o) <= 1e-12 * np.maximum(1.0, ns_o.astype(float) ** 2))
+    d = np.abs(f_g.cpu().numpy() - f_o)
+    assert np.all(d <= fitness_tol(mag, 1e-10)), float(np.max(d / np.maximum(mag, 1e-300)))
+    assert st.cpu().numpy().sum() == 0
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+def test_each_individual_takes_the_route_its_pair_count_selects(form):
+    N, frac = 300, 1.0 / 64
+    lim = limit(frac, N)
+    say(f"route choice {form} N={N} limit={lim}")
+    C, _ = corr(N, T=128, seed=21)
+    parts = [synth.random_labelings(40, N, seed=22, K=K) for K in (N, N // 2, N // 8, 12, 3)]
+    pop = np.concatenate(parts)
+    # one individual exactly at the limit and one a pair past it (singletons elsewhere)
+    for extra in (0, 1):
+        row = np.arange(N, dtype=np.int32)
+        need, pos = lim + extra, 0
+        while need > 0:
+            n = 2
+            while (n + 1) * n // 2 <= need:
+                n += 1
+            row[pos:pos + n] = row[pos]
+            need -= n * (n - 1) // 2
+            pos += n
+        pop = np.concatenate([pop, row[None, :]])
+    pc = pair_counts(pop, N)
+    assert pc[-2] == lim and pc[-1] == lim + 1
+    on = pc <= lim
+    assert on.any() and (~on).any()
+    f_mix = _fit(C, pop, form, frac).cpu().numpy()
+    f_pairs = _fit(C, pop, form, 1.0).cpu().numpy()
+    f_dense = _fit(C, pop, form, 0.0).cpu().numpy()
+    assert np.array_equal(f_mix[on], f_pairs[on])
+    assert np.array_equal(f_mix[~on], f_dense[~on])
+    # the pair route is the same arithmetic in both forms
+    other = "bf16x2" if form == "fp64" else "fp64"
+    assert np.array_equal(f_pairs, _fit(C, pop, other, 1.0).cpu().numpy())
+    f_o, mag = O.fitness(C, pop, want_mag=True)
+    assert np.all(np.abs(f_pairs - f_o) <= fitness_tol(mag, 1e-10))
+
+
+def test_entries_outside_the_unit_interval_take_the_dense_route():
+    N = 40
+    C, _ = corr(N, T=64, seed=31)
+    C = C.copy()
+    C[3, 5] = C[5, 3] = 1.5
+    C[10, 11] = C[11, 10] = np.nan
+    pop = synth.random_labelings(30, N, seed=32, K=N)
+    pop[0, [3, 5]] = 7                        # pair (3, 5) in one cluster
+    pop[1, [10, 11]] = 2                      # pair (10, 11) in one cluster
+    for r in range(2, len(pop)):              # elsewhere the two pairs are never in one cluster
+        for a, b in ((3, 5), (10, 11)):
+            if pop[r, a] == pop[r, b]:
+                pop[r, b] = (pop[r, b] + 1) % N
+    for form in ("fp64", "bf16x2"):
+        st_a, st_b = pga.new_status(), pga.new_status()
+        a, nsa, csa = _fit(C, pop, form, 1.0, want_ns=True, want_cs=True, status=st_a)
+        b, nsb, csb = _fit(C, pop, form, 0.0, want_ns=True, want_cs=True, status=st_b)
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.isinf(a[1]) and np.isinf(b[1])
+        assert np.array_equal(a[:2], b[:2]), form
+        assert np.array_equal(nsa.cpu().numpy()[:2], nsb.cpu().numpy()[:2])
+        assert np.array_equal(csa.cpu().numpy()[:2], csb.cpu().numpy()[:2])
+        if form == "fp64":   # the MFMA form's NaN reaches every individual of the dense route
+            assert np.array_equal(st_a.cpu().numpy(), st_b.cpu().numpy())
+    # the other individuals never meet a bad entry: the pair route agrees with the oracle
+    f = _fit(C, pop, "fp64", 1.0).cpu().numpy()
+    Cc = np.where(np.isfinite(C), np.clip(C, -1, 1), 0.0)
+    f_o, mag = O.fitness(Cc, pop[2:], want_mag=True)
+    assert np.all(np.abs(f[2:] - f_o) <= fitness_tol(mag, 1e-10))
+
+
+def test_invalid_labels_and_domain_status_as_dense_route():
+    C = np.array([[1.0, 1.0, 0.1, 0.0], [1.0, 1.0, 0.1, 0.0], [0.1, 0.1, 1.0, -1.0], [0.0, 0.0, -1.0, 1.0]])
+    pop = np.array([[0, 0, 1, 2], [0, 1, 2, 2], [0, 1, 4, 3], [-1, 0, 0, 0], [0, 1, 2, 3], [1, 1, 1, 1]],
+                   dtype=np.int32)
+    st_o = O.status_zero()
+    f_o, ns_o, cs_o = O.fitness(C, pop, want_ns=True, want_cs=True, status=st_o)
+    for form in ("fp64", "bf16x2"):
+        st = pga.new_status()
+        f_g, ns_g, cs_g = _fit(C, pop, form, 1.0, want_ns=True, want_cs=True, status=st)
+        f_g = f_g.cpu().numpy()
+        assert np.array_equal(np.isinf(f_g), np.isinf(f_o))
+        assert np.allclose(f_g[np.isfinite(f_o)], f_o[np.isfinite(f_o)], rtol=1e-12, atol=1e-13)
+        assert np.array_equal(st.cpu().numpy(), st_o), form
+        assert np.array_equal(ns_g.cpu().numpy(), ns_o)
+        assert np.allclose(cs_g.cpu().numpy(), cs_o, rtol=1e-12, atol=1e-13)
+
+
+def test_above_2048_stocks_every_individual_takes_the_dense_route():
+    N = 2049
+    C, _ = corr(N, T=64, seed=41)
+    pop = synth.random_labelings(5, N, seed=42)
+    for form in ("fp64", "bf16x2"):
+        assert torch.equal(_fit(C, pop, form, 1.0), _fit(C, pop, form, 0.0))
+
+
+def test_pair_route_is_deterministic():
+    C, _ = corr(500, T=64, seed=51)
+    pop = synth.random_labelings(300, 500, seed=52, K=60)
+    a = _fit(C, pop, "fp64", 1.0, want_cs=True)
+    b = _fit(C, pop, "fp64", 1.0, want_cs=True)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("frac", [0.0, 1.0 / 64, 1.0], ids=["dense", "default", "pairs"])
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+def test_evolve_through_the_route_in_lockstep_with_oracle(form, frac):
+    N, P, E, G = 130, 64, 2, 3
+    say(f"evolve route={frac} {form}")
+    C, _ = corr(N, seed=61)
+    Cg = _g(C)
+    hi = lo = None
+    if form == "bf16x2":
+        hi, lo = pga.split(Cg)
+    with pga.route(frac):
+        I = pga.make_instance(Cg, P, hi=hi, lo=lo, stats_rows=G + 1, elites=E, seed=5, instance_id=1)
+        ctx = pga.Context()
+        ctx.evolve([I], 0, form=form, init=True)
+        pop = I.pop.cpu().numpy()
+        for g in range(G):
+            f = I.fitness.cpu().numpy()
+            I.gen0 = g
+            ctx.evolve([I], 1, form=form)
+            nxt = O.breed(pop, f, E=E, seed=5, inst=1, gen=g, selection=0)
+            assert np.array_equal(I.pop.cpu().numpy(), nxt), g
+            pop = nxt
+        # graph replay equals eager launches
+        J = pga.make_instance(Cg, P, hi=hi, lo=lo, pop=_g(pop), stats_rows=3, elites=E, seed=5, instance_id=1)
+        K = pga.make_instance(Cg, P, hi=hi, lo=lo, pop=_g(pop), stats_rows=3, elites=E, seed=5, instance_id=1)
+        ctx.evolve([J], 2, form=form)
+        ctx.evolve([K], 2, form=form, eager=True)
+        assert torch.equal(J.pop, K.pop) and torch.equal(J.fitness, K.fitness)
+    f_o, mag = O.fitness(C, I.pop.cpu().numpy(), want_mag=True)
+    tol = fitness_tol(mag, 1e-10) if (form == "fp64" or frac == 1.0) else 1e-4 * mag + 1e-9
+    assert np.all(np.abs(I.fitness.cpu().numpy() - f_o) <= tol)

@@ -15,6 +15,14 @@ DEV = "cuda"
 SHAPES = [(100, 70), (1024, 96), (300, 1), (4096, 9)]
 
 
+@pytest.fixture(autouse=True)
+def _dense_route():
+    """These tests check the O(N^2) pair-sum kernels: every individual takes that route
+    (the cluster-pair route has its own tests)."""
+    with pga.route(0.0):
+        yield
+
+
 def _g(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
