@@ -529,7 +529,8 @@ hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_
 // inside cluster s, so an individual with few such pairs is evaluated from
 // them directly instead of by the O(N^2) pair-sum: one 256-thread workgroup
 // per individual
-//   1. labels into LDS (invalid labels: fitness -inf, as the finish does);
+//   1. labels and the diagonal of C (a contiguous copy) into registers, the
+//      labels also into LDS (invalid labels: fitness -inf, as the finish does);
 //   2. n_s by LDS atomics; pairs = sum_s n_s (n_s - 1) / 2 and max n_s;
 //   3. pairs above the limit: route[p] = 1 (the pair-sum and finish kernels
 //      evaluate it) and stop;
@@ -547,13 +548,19 @@ hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_
 //      route (step 3's flag), which treats it exactly as before; otherwise
 //      route[p] = 0 and the log terms follow as in the finish.
 constexpr int kSparseMaxN = 2048;                  // larger instances always take the dense route
+constexpr int kSparseCache = kSparseMaxN / kFinThreads;   // stocks per thread, all in registers
 
 __host__ __device__ __forceinline__ size_t pad16(size_t b) { return (b + 15) / 16 * 16; }
-// LDS: csum int64[n] | cnt int32[n] | begin int32[n] | W int32[n + 1] | members uint16[n]
-//      | labels uint16[n] | finish lists | kFinWaves x 2 doubles | 16 int32
+__host__ __device__ __forceinline__ size_t sparse_members_bytes(int n) {
+    const size_t m = pad16(2 * (size_t)n), l = finish_lst_bytes(n);
+    return m > l ? m : l;
+}
+// LDS: csum int64[n] | cnt int32[n] | begin, then W, int32[n + 1] | members, then the
+// finish lists | labels uint16[n] | kFinWaves x 2 doubles | 16 int32.
+// 20.6 KB at N = 1024 (seven workgroups per CU).
 __host__ __device__ __forceinline__ size_t sparse_lds_bytes(int n) {
-    return pad16(8 * (size_t)n) + 2 * pad16(4 * (size_t)n) + pad16(4 * ((size_t)n + 1)) +
-           2 * pad16(2 * (size_t)n) + finish_lst_bytes(n) + 2 * kFinWaves * sizeof(double) + 16 * sizeof(int);
+    return pad16(8 * (size_t)n) + pad16(4 * (size_t)n) + pad16(4 * ((size_t)n + 1)) + sparse_members_bytes(n) +
+           pad16(2 * (size_t)n) + 2 * kFinWaves * sizeof(double) + 16 * sizeof(int);
 }
 
 // Exclusive prefix sum of a[0 .. n) into out (may alias a); thread t scans a
@@ -587,6 +594,10 @@ __device__ __forceinline__ int block_exscan(const int *a, int *out, int n, int *
     return total;
 }
 
+__device__ __forceinline__ unsigned long long fixed_pt(double c, int sc) {
+    return (unsigned long long)llrint(ldexp(c, sc));
+}
+
 __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int parity, double frac,
                                                         int32_t *status) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -605,24 +616,39 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     unsigned char *b = smem;
     long long *csum = (long long *)b;   b += pad16(8 * n);
     int *cnt = (int *)b;                b += pad16(4 * n);
-    int *begin = (int *)b;              b += pad16(4 * n);
-    int *W = (int *)b;                  b += pad16(4 * (n + 1));
-    uint16_t *members = (uint16_t *)b;  b += pad16(2 * n);
+    int *begin = (int *)b;              b += pad16(4 * (n + 1));
+    int *W = begin;                     // W replaces begin once a(x) is in registers
+    uint16_t *members = (uint16_t *)b;  b += sparse_members_bytes(lds_n);
+    uint16_t *lst = members;            // the finish lists replace members after the pairs
     uint16_t *labs = (uint16_t *)b;     b += pad16(2 * n);
-    uint16_t *lst = (uint16_t *)b;      b += finish_lst_bytes(lds_n);
     double *red = (double *)b;          b += 2 * kFinWaves * sizeof(double);
     int *ired = (int *)b;               // [0, 4) flags, [4, 8) max n_s, [8, 12) scan totals
 
     const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
     const double *__restrict__ C = d.C;
 
+    // Stocks j = tid + 256 u, u < ucache (uniform), all of them (N <= 2048).
+    const int ucache = (N + kFinThreads - 1) / kFinThreads;
+    int lr[kSparseCache];
+    double dg[kSparseCache];
+#pragma unroll
+    for (int u = 0; u < kSparseCache; ++u) {
+        if (u >= ucache) break;
+        const int j = tid + kFinThreads * u;
+        lr[u] = j < N ? gld(lab + j) : 0;
+        dg[u] = j < N ? gld(d.diag + j) : 0.0;
+    }
     int bad = 0;
-    for (int j = tid; j < N; j += kFinThreads) {
-        const int l = gld(lab + j);
-        if (l < 0 || l >= N) bad = 1;
-        else labs[j] = (uint16_t)l;
-        cnt[j] = 0;
-        csum[j] = 0;
+#pragma unroll
+    for (int u = 0; u < kSparseCache; ++u) {
+        if (u >= ucache) break;
+        const int j = tid + kFinThreads * u;
+        if (j < N) {
+            if (lr[u] < 0 || lr[u] >= N) bad = 1;
+            else labs[j] = (uint16_t)lr[u];
+            cnt[j] = 0;
+            csum[j] = 0;
+        }
     }
     const int wbad = __any(bad) ? 1 : 0;             // all lanes vote, lane 0 records
     if (lane == 0) ired[wave] = wbad;
@@ -642,7 +668,11 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
             for (int s = tid; s < N; s += kFinThreads) d.c_s_out[(size_t)p * N + s] = 0.0;
         return;
     }
-    for (int j = tid; j < N; j += kFinThreads) atomicAdd(&cnt[labs[j]], 1);
+#pragma unroll
+    for (int u = 0; u < kSparseCache; ++u) {
+        if (u >= ucache) break;
+        if (tid + kFinThreads * u < N) atomicAdd(&cnt[lr[u]], 1);
+    }
     __syncthreads();
 
     long long pr = 0;
@@ -673,30 +703,47 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
         if (tid == 0) gst(d.route + p, 1);
         return;                                      // uniform
     }
+    int e;
+    frexp((double)nmax * (double)nmax, &e);          // max n_s^2 < 2^e
+    const int sc = 61 - e;
 
     block_exscan(cnt, begin, N, ired + 8);           // begin[s]: first position of cluster s
-    for (int j = tid; j < N; j += kFinThreads) members[atomicAdd(&begin[labs[j]], 1)] = (uint16_t)j;
+    int badc = 0;
+#pragma unroll
+    for (int u = 0; u < kSparseCache; ++u) {
+        if (u >= ucache) break;
+        const int j = tid + kFinThreads * u;
+        if (j < N) {
+            members[atomicAdd(&begin[lr[u]], 1)] = (uint16_t)j;
+            if (!(fabs(dg[u]) <= 1.0)) badc = 1;
+            else atomicAdd((unsigned long long *)&csum[lr[u]], fixed_pt(dg[u], sc));
+        }
+    }
     __syncthreads();                                 // begin[s] is now the end of cluster s
-    for (int x = tid; x < N; x += kFinThreads) {
-        const int l = labs[members[x]];
-        W[x] = x - (begin[l] - cnt[l]);              // a(x)
+    int ax[kSparseCache];
+#pragma unroll
+    for (int u = 0; u < kSparseCache; ++u) {
+        if (u >= ucache) break;
+        const int x = tid + kFinThreads * u;
+        if (x < N) {
+            const int l = labs[members[x]];
+            ax[u] = x - (begin[l] - cnt[l]);         // a(x)
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kSparseCache; ++u) {
+        if (u >= ucache) break;
+        const int x = tid + kFinThreads * u;
+        if (x < N) W[x] = ax[u];
     }
     __syncthreads();
     const int T = block_exscan(W, W, N, ired + 8);   // T == pairs
     if (tid == 0) W[N] = T;
-    int e;
-    frexp((double)nmax * (double)nmax, &e);          // max n_s^2 < 2^e
-    const int sc = 61 - e;
     __syncthreads();
 
-    int badc = 0;
-    for (int j = tid; j < N; j += kFinThreads) {
-        const double c = gld(C + (size_t)j * N + j);
-        if (!(fabs(c) <= 1.0)) badc = 1;
-        else atomicAdd((unsigned long long *)&csum[labs[j]], (unsigned long long)llrint(ldexp(c, sc)));
-    }
-    // Four pairs per thread and round, their loads issued before any is used.
-    constexpr int kQ = 4;
+    // Eight pairs per thread and round, their loads issued before any is used.
+    constexpr int kQ = 8;
     for (int q0 = tid; q0 < T; q0 += kQ * kFinThreads) {
         double c[kQ];
         int l[kQ];
@@ -712,9 +759,8 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
                     if (W[mid] <= q) lo = mid;
                     else hi = mid;
                 }
-                const int x = lo;
-                const int y = x - (W[x + 1] - W[x]) + (q - W[x]);
-                const int j = members[x], i = members[y];
+                const int y = lo - (W[lo + 1] - W[lo]) + (q - W[lo]);
+                const int j = members[lo], i = members[y];
                 c[u] = gld(C + (size_t)min(i, j) * N + max(i, j));
                 l[u] = labs[j];
             }
@@ -723,7 +769,7 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
         for (int u = 0; u < kQ; ++u) {
             if (l[u] < 0) continue;
             if (!(fabs(c[u]) <= 1.0)) badc = 1;
-            else atomicAdd((unsigned long long *)&csum[l[u]], (unsigned long long)llrint(ldexp(2.0 * c[u], sc)));
+            else atomicAdd((unsigned long long *)&csum[l[u]], fixed_pt(2.0 * c[u], sc));
         }
     }
     const int wbadc = __any(badc) ? 1 : 0;
@@ -743,6 +789,20 @@ hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double
     const int n = std::min(max_n, kSparseMaxN);
     hipLaunchKernelGGL(k_sparse, dim3(total_inds), dim3(kFinThreads), sparse_lds_bytes(n), s, t, n, parity,
                        frac, status);
+    return hipGetLastError();
+}
+
+// Contiguous copy of the diagonal of every instance's C (read by the
+// cluster-pair kernel; blockIdx.y = instance).
+__global__ __launch_bounds__(256) void k_diag(Tables t) {
+    const InstDesc &d = t.desc[blockIdx.y];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (d.diag && j < d.N) gst(d.diag + j, gld(d.C + (size_t)j * d.N + j));
+}
+
+hipError_t launch_diag(Tables t, int max_n, hipStream_t s) {
+    if (t.n_inst <= 0 || max_n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_diag, dim3((max_n + 255) / 256, t.n_inst), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

@@ -145,7 +145,7 @@ int pick_variant(int form, int max_n, int total_p) {
 // and, for SUS selection, [rank P int32][weight prefix P uint64].
 struct Layout {
     size_t desc_off, pre_off, inst_off;
-    std::vector<size_t> wsum_off, elite_off, hs_off, ls_off, rank_off, cum_off, route_off;
+    std::vector<size_t> wsum_off, elite_off, hs_off, ls_off, rank_off, cum_off, route_off, diag_off;
     size_t total;
 };
 
@@ -173,6 +173,8 @@ Layout make_layout(const int32_t *Ns, const int32_t *Ps, int n, int form, const 
         off = align_up(off + (sus ? sizeof(uint64_t) * (size_t)Ps[k] : 0), 256);
         L.route_off.push_back(off);
         off = align_up(off + sizeof(int32_t) * (size_t)Ps[k], 256);
+        L.diag_off.push_back(off);
+        off = align_up(off + sizeof(double) * (size_t)Ns[k], 256);
     }
     L.total = off;
     return L;
@@ -404,7 +406,10 @@ int prepare_single(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, 
     }
     d.n_s_out = n_s;
     d.c_s_out = c_s;
-    if (frac > 0.0) d.route = (int32_t *)((char *)ws + L.route_off[0]);
+    if (frac > 0.0) {
+        d.route = (int32_t *)((char *)ws + L.route_off[0]);
+        d.diag = (double *)((char *)ws + L.diag_off[0]);
+    }
     *t = tables_at(ws, L, 1);
     sh->n_inst = 1;
     sh->inds = P;
@@ -440,6 +445,7 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
                                   &t, &sh, &d, route_frac());
     if (rc != PGA_OK || P == 0) return rc;
     HIP_TRY(use_variant(d, t, form, pick_variant(form, N, P), &sh, s));
+    if (sh.frac > 0.0) HIP_TRY(launch_diag(t, N, s));
     HIP_TRY(run_fitness(t, sh, form, 0, status, s));
     return PGA_OK;
 }
@@ -660,7 +666,10 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
             d.sus_rank = (int32_t *)((char *)ws + L.rank_off[k]);
             d.sus_cum = (uint64_t *)((char *)ws + L.cum_off[k]);
         }
-        if (sh.frac > 0.0) d.route = (int32_t *)((char *)ws + L.route_off[k]);
+        if (sh.frac > 0.0) {
+            d.route = (int32_t *)((char *)ws + L.route_off[k]);
+            d.diag = (double *)((char *)ws + L.diag_off[k]);
+        }
         d.ind0 = pi[k];
         hd[k] = d;
         pf[k + 1] = pf[k] + pair_tiles(I.N, I.P, sh.v);
@@ -674,6 +683,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
 
     Tables t = tables_at(ws, L, n_inst);
     if (form == PGA_FORM_BF16X2) HIP_TRY(launch_scale_split(t, split_ld(sh.max_n), s));
+    if (sh.frac > 0.0) HIP_TRY(launch_diag(t, sh.max_n, s));
     if (flags & PGA_EVOLVE_INIT) HIP_TRY(timed(7, s, [&] { return launch_init(t, sh.inds, s); }));
 
     const bool eager = (flags & PGA_EVOLVE_EAGER) || timing_on();

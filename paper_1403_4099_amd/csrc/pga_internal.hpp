@@ -37,6 +37,7 @@ struct InstDesc {
     uint64_t *sus_cum;          // P: inclusive prefix of the SUS weights (workspace)
     int32_t *route;             // P: 1 = evaluated by pair-sum + finish, 0 = by the cluster-pair
                                 // kernel (workspace); null: every individual takes the pair-sum
+    double *diag;               // N: C_jj, contiguous (workspace; with route)
 };
 
 // Prefix tables: for n instances, arrays of n + 1 exclusive prefix sums.
@@ -192,6 +193,7 @@ hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Vari
                                hipStream_t s);
 hipError_t launch_scale_split(Tables t, int max_ld, hipStream_t s);
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status, hipStream_t s);
+hipError_t launch_diag(Tables t, int max_n, hipStream_t s);
 hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int32_t *status,
                          hipStream_t s);
 
