@@ -8,10 +8,14 @@ graph launch) -> pga_best. Inputs are synthetic (one-factor returns) and
 resident in HBM before the timed region.
 
 Prints one JSON line. `value` is fitness evaluations per second of the chosen
-form over whole steps ((G + 1) * P per step); the FP64 form is timed the same
-way for the speed-up. `roofline` is for the dominant kernel (the pair-sum of
-the chosen form), its average duration measured with HIP events on the
-launching stream. `cpu_baseline` is the CPU oracle on a bounded sample.
+form over whole steps ((G + 1) * P per step), every individual through the
+O(N^2) pair-sum of the form (cluster-pair route off); the FP64 form is timed
+the same way for the speed-up. `roofline` is for the dominant kernel (the
+pair-sum of the chosen form), its average duration measured with HIP events on
+the launching stream. `route` repeats the steps with the library's default
+cluster-pair route (individuals with few within-cluster pairs evaluated from
+those pairs alone, exact FP64) and gives that kernel's own roofline.
+`cpu_baseline` is the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -40,6 +44,8 @@ def parse():
     ap.add_argument("--generations", type=int, default=300)
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-route", action="store_true",
+                    help="skip the measurements with the cluster-pair route (only the pair-sum route)")
     ap.add_argument("--calib-copy-mib", type=int, default=256,
                     help="size of the plain device copy run once for counter calibration")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -148,6 +154,18 @@ def pair_visits(N: int, P: int) -> float:
     return float(N) * (N - 1) / 2 * P
 
 
+def within_pairs(pop) -> "np.ndarray":
+    """sum_s n_s (n_s - 1) / 2 of every row of a population (host)."""
+    import numpy as np
+    a = pop.cpu().numpy() if hasattr(pop, "cpu") else pop
+    N = a.shape[1]
+    out = np.empty(a.shape[0], dtype=np.int64)
+    for r in range(a.shape[0]):
+        n = np.bincount(a[r], minlength=N).astype(np.int64)
+        out[r] = int((n * (n - 1) // 2).sum())
+    return out
+
+
 def source_sha(path):
     """Hash of a kernel source together with the shared header that fixes its tile geometry."""
     h = hashlib.sha256()
@@ -212,6 +230,81 @@ def cpu_baseline(w, P, seed):
     }
 
 
+def route_section(args, forms, results, insts, timed, step, pop0, route_default, C, hi, lo, N, P, G):
+    """The cluster-pair route at the library's default limit: the same steps, its kernels, and
+    pga_fitness calls on the random and on the route run's final population."""
+    import numpy as np
+    import torch
+
+    from paper_1403_4099_amd import pga
+    pga.route_set(route_default)
+    lim = int(np.floor(route_default * 0.5 * N * (N - 1)))
+    route = {"limit_frac": route_default, "limit_pairs": lim,
+             "rule": "an individual with at most limit_pairs pairs inside its clusters (N <= 2048) is evaluated "
+                     "from those pairs (exact FP64); the others by the pair-sum of the form", "steps": {}}
+    for form in forms:
+        wall, ev, (lab, fbest, idx) = timed(form, args.steps, args.warmup)
+        route["steps"][form] = {"fitness_evals_per_s": (G + 1) * P * args.steps / wall,
+                                "gens_per_s": G * args.steps / wall, "ms_per_step": 1e3 * wall / args.steps,
+                                "speedup_vs_pairsum_only": results[form]["wall_s"] / wall, "best_Lc": fbest}
+        print(f"[bench] route {form}: {route['steps'][form]}", file=sys.stderr, flush=True)
+    pga.timing_enable(True)
+    rk = {}
+    for form in forms:
+        pga.timing_reset()
+        step(form)
+        torch.cuda.synchronize()
+        for kname in ("cluster_pairs", "pairsum_fp64", "pairsum_mfma", "finish", "rank", "breed"):
+            ms, n = pga.timing_read(kname)
+            if n:
+                rk.setdefault(form, {})[kname] = {"avg_us": 1e3 * ms / n, "launches": n}
+    pga.timing_enable(False)
+    route["kernels_us"] = rk
+    wp0 = within_pairs(pop0)
+    wpf = within_pairs(insts[args.form].pop)
+    route["population_pairs"] = {"random_mean": float(wp0.mean()), "final_mean": float(wpf.mean()),
+                                 "final_share_within_limit": float((wpf <= lim).mean())}
+    route["fitness_call"] = {}
+    t_route = None
+    for form in forms:
+        for tag, pop in (("random", pop0), ("final", insts[form].pop)):
+            for _ in range(3):
+                pga.fitness(C, pop, form, hi=hi, lo=lo)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                pga.fitness(C, pop, form, hi=hi, lo=lo)
+            e1.record()
+            torch.cuda.synchronize()
+            t_call = e0.elapsed_time(e1) * 1e-3 / 20
+            pga.timing_enable(True)
+            pga.timing_reset()
+            for _ in range(5):
+                pga.fitness(C, pop, form, hi=hi, lo=lo)
+            torch.cuda.synchronize()
+            ms, n = pga.timing_read("cluster_pairs")
+            pga.timing_enable(False)
+            t_k = 1e-3 * ms / n
+            route["fitness_call"].setdefault(form, {})[tag] = {
+                "fitness_call_us": 1e6 * t_call, "fitness_evals_per_s": P / t_call,
+                "cluster_pairs_us": 1e6 * t_k}
+            if form == args.form and tag == "random":
+                t_route = t_k
+    # algorithmic bytes of one launch on the random population: labels, the C entries of the
+    # within-cluster pairs, the fitness, and the diagonal once
+    byts = P * (4.0 * N + 8.0) + 8.0 * float(wp0.sum()) + 8.0 * N
+    ach = byts / t_route / 1e9
+    route["roofline"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM, "unit": "GB/s", "frac": ach / PEAK_HBM,
+                         "traffic": recorded_traffic(os.path.join(ROOT, "paper_1403_4099_amd", "csrc",
+                                                                  "k_fitness.hip"), N, P, -1),
+                         "kernel": "k_sparse", "avg_launch_us": 1e6 * t_route,
+                         "work_per_launch": "labels (4N B), within-cluster C entries (8 B each, "
+                                            f"{float(wp0.mean()):.0f} pairs per individual), fitness, diagonal "
+                                            "once, on the random generation-0 population"}
+    return route
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -226,6 +319,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    route_default = pga.route_get()
+    pga.route_set(0.0)          # headline: every individual through the pair-sum of its form
     w = synth.config3()
     N, T, P, G = w.N, w.T, w.P, args.generations
     R = torch.from_numpy(w.R).to(dev)
@@ -387,6 +482,12 @@ def main():
                    "note": "wall includes correlate, split, init and best once per step; kernel times are "
                            "eager launches with events, slightly above their graph-replay durations"}
 
+    # ---- the cluster-pair route at the library's default limit: the same steps, its kernels, and
+    # pga_fitness calls on the random and on the route run's final population
+    route = None
+    if not args.no_route:
+        route = route_section(args, forms, results, insts, timed, step, pop0, route_default, C, hi, lo, N, P, G)
+
     # ---- calibration copy for the HBM counters (plain device-to-device copy of known size), timed
     # as the measured HBM ceiling (read + write bytes over the best of 5 copies), and the measured
     # bf16 MFMA ceiling (the library's register-operand MFMA loop)
@@ -454,7 +555,8 @@ def main():
         "dtype": "bf16x2+f64" if form == "bf16x2" else "f64",
         "data": "synthetic",
         "config": {"workload": f"precision-form N={N} T={T} P={P} G={G}, 32 planted geometric clusters",
-                   "form": form, "N": N, "T": T, "P": P, "generations": G, "parallelism": "single GPU"},
+                   "form": form, "N": N, "T": T, "P": P, "generations": G, "parallelism": "single GPU",
+                   "route": "off: every individual through the pair-sum of the form (see route)"},
         "gens_per_s": G * args.steps / res["wall_s"],
         "pair_visits_per_s": pair_visits(N, P) * (G + 1) * args.steps / res["wall_s"],
         "speedup_vs_fp64": (results["fp64"]["wall_s"] / res["wall_s"]) if (form == "bf16x2" and "fp64" in results) else None,
@@ -467,14 +569,20 @@ def main():
         "autotune": tuned,
         "roofline": roof,
     }
+    line["route"] = route
+    pga.route_set(route_default)
+    # the batched and serving runs use the library's default route
     if args.batched_instances > 0:
         line["batched"] = batched_run(args.batched_instances, form)
+        line["batched"]["route_frac"] = route_default
         print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
     if args.serve_seconds > 0:
         line["serving"] = serving_run(args.serve_seconds, args.serve_rate, form)
+        line["serving"]["route_frac"] = route_default
         print(f"[bench] serving: {line['serving']}", file=sys.stderr, flush=True)
         line["serving_with_termination"] = serving_run(args.serve_seconds, args.serve_rate, form,
                                                        stall_gens=10, tol=1e-5)
+        line["serving_with_termination"]["route_frac"] = route_default
         print(f"[bench] serving with termination: {line['serving_with_termination']}", file=sys.stderr,
               flush=True)
     if not args.no_cpu_baseline:
