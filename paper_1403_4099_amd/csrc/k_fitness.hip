@@ -529,35 +529,38 @@ hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_
 // inside cluster s, so an individual with few such pairs is evaluated from
 // them directly instead of by the O(N^2) pair-sum: one 256-thread workgroup
 // per individual
-//   1. labels into registers (invalid labels: fitness -inf, as the finish does);
+//   1. labels and the diagonal of C (a contiguous copy) into registers, the
+//      labels also into LDS (invalid labels: fitness -inf, as the finish does);
 //   2. n_s by LDS atomics; pairs = sum_s n_s (n_s - 1) / 2 and max n_s;
 //   3. pairs above the limit: route[p] = 1 (the pair-sum and finish kernels
 //      evaluate it) and stop;
-//   4. members grouped by cluster (counting sort on the exclusive prefix of n_s);
-//   5. wave w lists the labels of its quarter of [0, N) with n_s > 1 in
-//      ascending order (as the finish); a lane takes a listed cluster of at
-//      most kSmallCluster members and sums it alone, the wave splits a larger
-//      one over its lanes:
-//        c_s = sum_{j in s} C_jj + 2 sum_{i<j in s} C_ij  (upper triangle, as
-//      the FP64 pair-sum reads it) in 64-bit fixed point: with |C| <= 1 every
-//      partial sum is bounded by max n_s^2, and the scale 2^sc keeps
-//      max n_s^2 2^sc <= 2^61, so the integer sums are exact and independent
-//      of the order of the terms; then the cluster's log terms of Eq. 8;
+//   4. members grouped by cluster (counting sort on the exclusive prefix of
+//      n_s); position x of the grouped list gets its index a(x) within its
+//      cluster, and W, the exclusive prefix of a, numbers the pairs: pair q
+//      belongs to the position x with W[x] <= q < W[x+1] and joins it with
+//      the earlier member at position x - a(x) + (q - W[x]);
+//   5. c_s = sum_{j in s} C_jj + 2 sum_{pairs} C_ij (upper triangle, as the
+//      FP64 pair-sum reads it) accumulated in 64-bit fixed point: with
+//      |C| <= 1 every partial sum is bounded by max n_s^2, and the scale 2^sc
+//      keeps max n_s^2 2^sc <= 2^61, so the integer sums are exact and the
+//      result does not depend on the order of the atomics;
 //   6. an entry with |C| > 1 or not finite sends the individual to the dense
-//      route (step 3's flag), which treats it exactly as before; otherwise the
-//      log terms are summed in a fixed order (per lane in list order, wave
-//      butterfly, waves in order) and route[p] = 0.
+//      route (step 3's flag), which treats it exactly as before; otherwise
+//      route[p] = 0 and the log terms follow as in the finish.
 constexpr int kSparseMaxN = 2048;                  // larger instances always take the dense route
 constexpr int kSparseCache = kSparseMaxN / kFinThreads;   // stocks per thread, all in registers
-constexpr int kSmallCluster = 16;                  // larger clusters are summed by a whole wave
-constexpr int kPairBatch = 8;                      // pairs whose loads are in flight together
 
 __host__ __device__ __forceinline__ size_t pad16(size_t b) { return (b + 15) / 16 * 16; }
-// LDS: n_s int32[n] | cluster ends int32[n + 1] | members uint16[n] | cluster lists
-//      | kFinWaves x 2 doubles | 16 int32.  12.4 KB at N = 1024.
+__host__ __device__ __forceinline__ size_t sparse_members_bytes(int n) {
+    const size_t m = pad16(2 * (size_t)n), l = finish_lst_bytes(n);
+    return m > l ? m : l;
+}
+// LDS: csum int64[n] | cnt int32[n] | begin, then W, int32[n + 1] | members, then the
+// finish lists | labels uint16[n] | kFinWaves x 2 doubles | 16 int32.
+// 20.6 KB at N = 1024 (seven workgroups per CU).
 __host__ __device__ __forceinline__ size_t sparse_lds_bytes(int n) {
-    return pad16(4 * (size_t)n) + pad16(4 * ((size_t)n + 1)) + pad16(2 * (size_t)n) + finish_lst_bytes(n) +
-           2 * kFinWaves * sizeof(double) + 16 * sizeof(int);
+    return pad16(8 * (size_t)n) + pad16(4 * (size_t)n) + pad16(4 * ((size_t)n + 1)) + sparse_members_bytes(n) +
+           pad16(2 * (size_t)n) + 2 * kFinWaves * sizeof(double) + 16 * sizeof(int);
 }
 
 // Exclusive prefix sum of a[0 .. n) into out (may alias a); thread t scans a
@@ -591,18 +594,12 @@ __device__ __forceinline__ int block_exscan(const int *a, int *out, int n, int *
     return total;
 }
 
-__device__ __forceinline__ long long fixed_pt(double c, int sc) { return llrint(ldexp(c, sc)); }
-
-// The log terms of Eq. 8 for one cluster, literal, with the domain test.
-__device__ __forceinline__ void cluster_term(int n, double c, double &L, int &nbad) {
-    const double nd = (double)n, n2 = nd * nd;
-    if (!(c > 0.0 && c < n2)) nbad += 1;
-    else L += log(nd / c) + (nd - 1.0) * log((n2 - nd) / (n2 - c));
+__device__ __forceinline__ unsigned long long fixed_pt(double c, int sc) {
+    return (unsigned long long)llrint(ldexp(c, sc));
 }
 
-// Held to 64 registers: eight waves per SIMD hide the latency of the dependent steps.
-__global__ __launch_bounds__(kFinThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sparse(
-    Tables t, int lds_n, int parity, double frac, int32_t *status) {
+__global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int parity, double frac,
+                                                        int32_t *status) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
     const int g = blockIdx.x;
@@ -617,27 +614,30 @@ __global__ __launch_bounds__(kFinThreads) __attribute__((amdgpu_waves_per_eu(8))
     }
     const size_t n = (size_t)lds_n;
     unsigned char *b = smem;
+    long long *csum = (long long *)b;   b += pad16(8 * n);
     int *cnt = (int *)b;                b += pad16(4 * n);
-    int *end = (int *)b;                b += pad16(4 * (n + 1));
-    uint16_t *members = (uint16_t *)b;  b += pad16(2 * n);
-    uint16_t *lst = (uint16_t *)b;      b += finish_lst_bytes(lds_n);
+    int *begin = (int *)b;              b += pad16(4 * (n + 1));
+    int *W = begin;                     // W replaces begin once a(x) is in registers
+    uint16_t *members = (uint16_t *)b;  b += sparse_members_bytes(lds_n);
+    uint16_t *lst = members;            // the finish lists replace members after the pairs
+    uint16_t *labs = (uint16_t *)b;     b += pad16(2 * n);
     double *red = (double *)b;          b += 2 * kFinWaves * sizeof(double);
     int *ired = (int *)b;               // [0, 4) flags, [4, 8) max n_s, [8, 12) scan totals
 
     const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
     const double *__restrict__ C = d.C;
-    const double *__restrict__ dg = d.diag;
 
     // Stocks j = tid + 256 u, u < ucache (uniform), all of them (N <= 2048).
     const int ucache = (N + kFinThreads - 1) / kFinThreads;
     int lr[kSparseCache];
+    double dg[kSparseCache];
 #pragma unroll
     for (int u = 0; u < kSparseCache; ++u) {
         if (u >= ucache) break;
         const int j = tid + kFinThreads * u;
         lr[u] = j < N ? gld(lab + j) : 0;
+        dg[u] = j < N ? gld(d.diag + j) : 0.0;
     }
-    const bool ones = gld(dg + N) == 1.0;            // every C_jj is 1 (uniform)
     int bad = 0;
 #pragma unroll
     for (int u = 0; u < kSparseCache; ++u) {
@@ -645,7 +645,9 @@ __global__ __launch_bounds__(kFinThreads) __attribute__((amdgpu_waves_per_eu(8))
         const int j = tid + kFinThreads * u;
         if (j < N) {
             if (lr[u] < 0 || lr[u] >= N) bad = 1;
+            else labs[j] = (uint16_t)lr[u];
             cnt[j] = 0;
+            csum[j] = 0;
         }
     }
     const int wbad = __any(bad) ? 1 : 0;             // all lanes vote, lane 0 records
@@ -705,162 +707,80 @@ __global__ __launch_bounds__(kFinThreads) __attribute__((amdgpu_waves_per_eu(8))
     frexp((double)nmax * (double)nmax, &e);          // max n_s^2 < 2^e
     const int sc = 61 - e;
 
-    block_exscan(cnt, end, N, ired + 8);             // first position of each cluster
+    block_exscan(cnt, begin, N, ired + 8);           // begin[s]: first position of cluster s
+    int badc = 0;
 #pragma unroll
     for (int u = 0; u < kSparseCache; ++u) {
         if (u >= ucache) break;
         const int j = tid + kFinThreads * u;
-        if (j < N) members[atomicAdd(&end[lr[u]], 1)] = (uint16_t)j;
-    }
-    __syncthreads();                                 // end[s]: one past the last position of cluster s
-
-    // Pass A (wave w, labels [w Q, (w + 1) Q)): per-label outputs of clusters with
-    // n_s <= 1, and the labels with n_s > 1 listed in ascending order.
-    const int QN = finish_quarter(N);
-    const int s_lo = wave * QN, s_hi = min(N, s_lo + QN);
-    uint16_t *wl = lst + (size_t)wave * finish_quarter(lds_n);
-    int nlist = 0;
-    for (int s0 = s_lo; s0 < s_hi; s0 += 64) {
-        const int s = s0 + lane;
-        const int ns = s < s_hi ? cnt[s] : 0;
-        if (s < s_hi) {
-            if (d.n_s_out) gst(d.n_s_out + (size_t)p * N + s, ns);
-            if (d.c_s_out && ns <= 1)
-                gst(d.c_s_out + (size_t)p * N + s, ns == 0 ? 0.0 : gld(dg + members[end[s] - 1]));
-        }
-        const uint64_t m = __ballot(ns > 1);
-        if (ns > 1) wl[nlist + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)s;
-        nlist += __popcll(m);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    // Pass B: c_s and the log terms of every listed cluster.
-    double L = 0.0, Lbig = 0.0;                      // Lbig: wave-uniform
-    int nbad = 0, nbad_big = 0, badc = 0;
-    auto add_pair = [&](long long &acc, double c) {
-        if (!(fabs(c) <= 1.0)) badc = 1;
-        else acc += fixed_pt(2.0 * c, sc);
-    };
-    for (int m0 = 0; m0 < nlist; m0 += 64) {         // wave-uniform
-        const int m = m0 + lane;
-        const int s = m < nlist ? wl[m] : 0;
-        const int ns = m < nlist ? cnt[s] : 0;
-        if (m < nlist && ns <= kSmallCluster) {
-            const int st = end[s] - ns;
-            long long acc = 0;
-            if (ones) {
-                acc = (long long)ns << sc;           // sum of ns diagonal ones, exact
-            } else {
-                for (int a = 0; a < ns; ++a) {
-                    const double c = gld(dg + members[st + a]);
-                    if (!(fabs(c) <= 1.0)) badc = 1;
-                    else acc += fixed_pt(c, sc);
-                }
-            }
-            // pairs (a, b), a < b, in batches whose loads are issued together
-            const int np = ns * (ns - 1) / 2;
-            int a = 0, bb = 1;
-            for (int q0 = 0; q0 < np; q0 += kPairBatch) {
-                double c[kPairBatch];
-#pragma unroll
-                for (int u = 0; u < kPairBatch; ++u) {
-                    c[u] = 0.0;
-                    if (q0 + u < np) {
-                        const int ja = members[st + a], jb = members[st + bb];
-                        c[u] = gld(C + (size_t)min(ja, jb) * N + max(ja, jb));
-                        if (++a == bb) {
-                            ++bb;
-                            a = 0;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kPairBatch; ++u)
-                    if (q0 + u < np) add_pair(acc, c[u]);
-            }
-            const double cs = ldexp((double)acc, -sc);
-            if (d.c_s_out) gst(d.c_s_out + (size_t)p * N + s, cs);
-            cluster_term(ns, cs, L, nbad);
-        }
-        // clusters above kSmallCluster members: the whole wave, in list order
-        uint64_t big = __ballot(m < nlist && ns > kSmallCluster);
-        while (big) {
-            const int bl = __ffsll((long long)big) - 1;
-            big &= big - 1;
-            const int sb = __shfl(s, bl, 64), nb = __shfl(ns, bl, 64);
-            const int st = end[sb] - nb;
-            long long acc = 0;
-            if (ones) {
-                if (lane == 0) acc = (long long)nb << sc;
-            } else {
-                for (int a = lane; a < nb; a += 64) {
-                    const double c = gld(dg + members[st + a]);
-                    if (!(fabs(c) <= 1.0)) badc = 1;
-                    else acc += fixed_pt(c, sc);
-                }
-            }
-            const int np = nb * (nb - 1) / 2;
-            for (int q0 = lane; q0 < np; q0 += 64 * kPairBatch) {
-                double c[kPairBatch];
-#pragma unroll
-                for (int u = 0; u < kPairBatch; ++u) {
-                    const int q = q0 + 64 * u;
-                    c[u] = 0.0;
-                    if (q < np) {
-                        // pair q = bq (bq - 1) / 2 + aq with aq < bq
-                        int bq = (int)((1.0 + sqrt(1.0 + 8.0 * (double)q)) * 0.5);
-                        while (bq * (bq - 1) / 2 > q) --bq;
-                        while ((bq + 1) * bq / 2 <= q) ++bq;
-                        const int aq = q - bq * (bq - 1) / 2;
-                        const int ja = members[st + aq], jb = members[st + bq];
-                        c[u] = gld(C + (size_t)min(ja, jb) * N + max(ja, jb));
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kPairBatch; ++u)
-                    if (q0 + 64 * u < np) add_pair(acc, c[u]);
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-            const double cs = ldexp((double)acc, -sc);
-            if (d.c_s_out && lane == bl) gst(d.c_s_out + (size_t)p * N + sb, cs);
-            cluster_term(nb, cs, Lbig, nbad_big);    // same value on every lane
+        if (j < N) {
+            members[atomicAdd(&begin[lr[u]], 1)] = (uint16_t)j;
+            if (!(fabs(dg[u]) <= 1.0)) badc = 1;
+            else atomicAdd((unsigned long long *)&csum[lr[u]], fixed_pt(dg[u], sc));
         }
     }
-    {
-        const double wL = wave_sum(L) + Lbig;
-        const double wB = wave_sum((double)nbad) + (double)nbad_big;
-        const int wbadc = __any(badc) ? 1 : 0;
-        if (lane == 0) {
-            red[wave] = wL;
-            red[kFinWaves + wave] = wB;
-            ired[wave] = wbadc;
+    __syncthreads();                                 // begin[s] is now the end of cluster s
+    int ax[kSparseCache];
+#pragma unroll
+    for (int u = 0; u < kSparseCache; ++u) {
+        if (u >= ucache) break;
+        const int x = tid + kFinThreads * u;
+        if (x < N) {
+            const int l = labs[members[x]];
+            ax[u] = x - (begin[l] - cnt[l]);         // a(x)
         }
     }
     __syncthreads();
-    if (ired[0] | ired[1] | ired[2] | ired[3]) {     // |C| > 1 or not finite inside a cluster
+#pragma unroll
+    for (int u = 0; u < kSparseCache; ++u) {
+        if (u >= ucache) break;
+        const int x = tid + kFinThreads * u;
+        if (x < N) W[x] = ax[u];
+    }
+    __syncthreads();
+    const int T = block_exscan(W, W, N, ired + 8);   // T == pairs
+    if (tid == 0) W[N] = T;
+    __syncthreads();
+
+    // Eight pairs per thread and round, their loads issued before any is used.
+    constexpr int kQ = 8;
+    for (int q0 = tid; q0 < T; q0 += kQ * kFinThreads) {
+        double c[kQ];
+        int l[kQ];
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) {
+            const int q = q0 + u * kFinThreads;
+            l[u] = -1;
+            c[u] = 0.0;
+            if (q < T) {
+                int lo = 0, hi = N;                  // W[lo] <= q < W[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (W[mid] <= q) lo = mid;
+                    else hi = mid;
+                }
+                const int y = lo - (W[lo + 1] - W[lo]) + (q - W[lo]);
+                const int j = members[lo], i = members[y];
+                c[u] = gld(C + (size_t)min(i, j) * N + max(i, j));
+                l[u] = labs[j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) {
+            if (l[u] < 0) continue;
+            if (!(fabs(c[u]) <= 1.0)) badc = 1;
+            else atomicAdd((unsigned long long *)&csum[l[u]], fixed_pt(2.0 * c[u], sc));
+        }
+    }
+    const int wbadc = __any(badc) ? 1 : 0;
+    if (lane == 0) ired[wave] = wbadc;
+    __syncthreads();
+    if (ired[0] | ired[1] | ired[2] | ired[3]) {
         if (tid == 0) gst(d.route + p, 1);
         return;
     }
-    if (tid == 0) {
-        double Ltot = 0.0, badtot = 0.0;
-        for (int w = 0; w < kFinWaves; ++w) {
-            Ltot += red[w];
-            badtot += red[kFinWaves + w];
-        }
-        gst(d.route + p, 0);
-        if (badtot > 0.0) {
-            d.fitness[p] = -INFINITY;
-            if (status) {
-                atomicAdd(&status[PGA_ST_DOMAIN], (int)badtot);
-                atomicAdd(&status[PGA_ST_NONFINITE], 1);
-            }
-        } else {
-            d.fitness[p] = 0.5 * Ltot;
-        }
-    }
+    if (tid == 0) gst(d.route + p, 0);
+    finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(lds_n), red, status);
 }
 
 hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int32_t *status,
@@ -872,24 +792,17 @@ hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double
     return hipGetLastError();
 }
 
-// Contiguous copy of the diagonal of every instance's C (one workgroup per
-// instance, blockIdx.y), and diag[N] = 1 if every C_jj is 1, else 0.
+// Contiguous copy of the diagonal of every instance's C (read by the
+// cluster-pair kernel; blockIdx.y = instance).
 __global__ __launch_bounds__(256) void k_diag(Tables t) {
     const InstDesc &d = t.desc[blockIdx.y];
-    if (!d.diag) return;                             // uniform
-    int ones = 1;
-    for (int j = threadIdx.x; j < d.N; j += 256) {
-        const double c = gld(d.C + (size_t)j * d.N + j);
-        gst(d.diag + j, c);
-        ones &= c == 1.0 ? 1 : 0;
-    }
-    const int all = __syncthreads_and(ones);
-    if (threadIdx.x == 0) gst(d.diag + d.N, all ? 1.0 : 0.0);
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (d.diag && j < d.N) gst(d.diag + j, gld(d.C + (size_t)j * d.N + j));
 }
 
 hipError_t launch_diag(Tables t, int max_n, hipStream_t s) {
     if (t.n_inst <= 0 || max_n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_diag, dim3(1, t.n_inst), dim3(256), 0, s, t);
+    hipLaunchKernelGGL(k_diag, dim3((max_n + 255) / 256, t.n_inst), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 
