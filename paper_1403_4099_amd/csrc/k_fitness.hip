@@ -529,8 +529,9 @@ hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_
 // inside cluster s, so an individual with few such pairs is evaluated from
 // them directly instead of by the O(N^2) pair-sum: one 256-thread workgroup
 // per individual
-//   1. labels and the diagonal of C (a contiguous copy) into registers, the
-//      labels also into LDS (invalid labels: fitness -inf, as the finish does);
+//   1. labels and the diagonal of C (a contiguous copy; not read when every
+//      C_jj is 1) into registers, the labels also into LDS (invalid labels:
+//      fitness -inf, as the finish does);
 //   2. n_s by LDS atomics; pairs = sum_s n_s (n_s - 1) / 2 and max n_s;
 //   3. pairs above the limit: route[p] = 1 (the pair-sum and finish kernels
 //      evaluate it) and stop;
@@ -629,6 +630,7 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
 
     // Stocks j = tid + 256 u, u < ucache (uniform), all of them (N <= 2048).
     const int ucache = (N + kFinThreads - 1) / kFinThreads;
+    const bool ones = gld(d.diag + N) == 1.0;        // every C_jj is 1 (uniform)
     int lr[kSparseCache];
     double dg[kSparseCache];
 #pragma unroll
@@ -636,7 +638,7 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
         if (u >= ucache) break;
         const int j = tid + kFinThreads * u;
         lr[u] = j < N ? gld(lab + j) : 0;
-        dg[u] = j < N ? gld(d.diag + j) : 0.0;
+        dg[u] = (!ones && j < N) ? gld(d.diag + j) : 1.0;
     }
     int bad = 0;
 #pragma unroll
@@ -715,10 +717,14 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
         const int j = tid + kFinThreads * u;
         if (j < N) {
             members[atomicAdd(&begin[lr[u]], 1)] = (uint16_t)j;
-            if (!(fabs(dg[u]) <= 1.0)) badc = 1;
-            else atomicAdd((unsigned long long *)&csum[lr[u]], fixed_pt(dg[u], sc));
+            if (!ones) {
+                if (!(fabs(dg[u]) <= 1.0)) badc = 1;
+                else atomicAdd((unsigned long long *)&csum[lr[u]], fixed_pt(dg[u], sc));
+            }
         }
     }
+    if (ones)                                        // sum of n_s diagonal ones, exact
+        for (int s = tid; s < N; s += kFinThreads) csum[s] = (long long)cnt[s] << sc;
     __syncthreads();                                 // begin[s] is now the end of cluster s
     int ax[kSparseCache];
 #pragma unroll
@@ -742,35 +748,52 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     if (tid == 0) W[N] = T;
     __syncthreads();
 
-    // Eight pairs per thread and round, their loads issued before any is used.
+    // Each thread takes kq consecutive pairs per round (one search, then a forward
+    // walk) with their loads issued together; kq = ceil(T / 256), at most kQ, so
+    // every thread has work. Consecutive pairs mostly share a cluster, so the
+    // terms are summed in a register while the label stays the same and added to
+    // csum once per run (fewer atomics on one LDS address).
     constexpr int kQ = 8;
-    for (int q0 = tid; q0 < T; q0 += kQ * kFinThreads) {
+    const int kq = min(kQ, max(1, (T + kFinThreads - 1) / kFinThreads));   // uniform
+    for (int q0 = tid * kq; q0 < T; q0 += kq * kFinThreads) {
+        int x = 0, hi = N;                           // W[x] <= q0 < W[hi]
+        while (hi - x > 1) {
+            const int mid = (x + hi) >> 1;
+            if (W[mid] <= q0) x = mid;
+            else hi = mid;
+        }
         double c[kQ];
         int l[kQ];
 #pragma unroll
         for (int u = 0; u < kQ; ++u) {
-            const int q = q0 + u * kFinThreads;
+            const int q = q0 + u;
             l[u] = -1;
             c[u] = 0.0;
-            if (q < T) {
-                int lo = 0, hi = N;                  // W[lo] <= q < W[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (W[mid] <= q) lo = mid;
-                    else hi = mid;
-                }
-                const int y = lo - (W[lo + 1] - W[lo]) + (q - W[lo]);
-                const int j = members[lo], i = members[y];
+            if (u < kq && q < T) {
+                while (W[x + 1] <= q) ++x;           // W[N] = T > q
+                const int y = x - (W[x + 1] - W[x]) + (q - W[x]);
+                const int j = members[x], i = members[y];
                 c[u] = gld(C + (size_t)min(i, j) * N + max(i, j));
                 l[u] = labs[j];
             }
         }
+        long long run = 0;
+        int cur = -1;
 #pragma unroll
         for (int u = 0; u < kQ; ++u) {
             if (l[u] < 0) continue;
-            if (!(fabs(c[u]) <= 1.0)) badc = 1;
-            else atomicAdd((unsigned long long *)&csum[l[u]], fixed_pt(2.0 * c[u], sc));
+            if (!(fabs(c[u]) <= 1.0)) {
+                badc = 1;
+                continue;
+            }
+            if (l[u] != cur) {
+                if (cur >= 0) atomicAdd((unsigned long long *)&csum[cur], (unsigned long long)run);
+                cur = l[u];
+                run = 0;
+            }
+            run += fixed_pt(2.0 * c[u], sc);
         }
+        if (cur >= 0) atomicAdd((unsigned long long *)&csum[cur], (unsigned long long)run);
     }
     const int wbadc = __any(badc) ? 1 : 0;
     if (lane == 0) ired[wave] = wbadc;
@@ -792,17 +815,24 @@ hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double
     return hipGetLastError();
 }
 
-// Contiguous copy of the diagonal of every instance's C (read by the
-// cluster-pair kernel; blockIdx.y = instance).
+// Contiguous copy of the diagonal of every instance's C (one workgroup per
+// instance, blockIdx.y), and diag[N] = 1 if every C_jj is 1, else 0.
 __global__ __launch_bounds__(256) void k_diag(Tables t) {
     const InstDesc &d = t.desc[blockIdx.y];
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (d.diag && j < d.N) gst(d.diag + j, gld(d.C + (size_t)j * d.N + j));
+    if (!d.diag) return;                             // uniform
+    int ones = 1;
+    for (int j = threadIdx.x; j < d.N; j += 256) {
+        const double c = gld(d.C + (size_t)j * d.N + j);
+        gst(d.diag + j, c);
+        ones &= c == 1.0 ? 1 : 0;
+    }
+    const int all = __syncthreads_and(ones);
+    if (threadIdx.x == 0) gst(d.diag + d.N, all ? 1.0 : 0.0);
 }
 
 hipError_t launch_diag(Tables t, int max_n, hipStream_t s) {
     if (t.n_inst <= 0 || max_n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_diag, dim3((max_n + 255) / 256, t.n_inst), dim3(256), 0, s, t);
+    hipLaunchKernelGGL(k_diag, dim3(1, t.n_inst), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

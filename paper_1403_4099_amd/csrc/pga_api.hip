@@ -174,7 +174,7 @@ Layout make_layout(const int32_t *Ns, const int32_t *Ps, int n, int form, const 
         L.route_off.push_back(off);
         off = align_up(off + sizeof(int32_t) * (size_t)Ps[k], 256);
         L.diag_off.push_back(off);
-        off = align_up(off + sizeof(double) * (size_t)Ns[k], 256);
+        off = align_up(off + sizeof(double) * ((size_t)Ns[k] + 1), 256);
     }
     L.total = off;
     return L;

@@ -37,7 +37,7 @@ struct InstDesc {
     uint64_t *sus_cum;          // P: inclusive prefix of the SUS weights (workspace)
     int32_t *route;             // P: 1 = evaluated by pair-sum + finish, 0 = by the cluster-pair
                                 // kernel (workspace); null: every individual takes the pair-sum
-    double *diag;               // N: C_jj, contiguous (workspace; with route)
+    double *diag;               // N + 1: C_jj, contiguous, then 1 if every C_jj is 1 (workspace; with route)
 };
 
 // Prefix tables: for n instances, arrays of n + 1 exclusive prefix sums.

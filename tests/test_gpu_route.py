@@ -146,6 +146,26 @@ def test_entries_outside_the_unit_interval_take_the_dense_route():
     assert np.all(np.abs(f[2:] - f_o) <= fitness_tol(mag, 1e-10))
 
 
+def test_pair_route_with_a_diagonal_other_than_ones():
+    """C_jj below 1 is summed term by term (the all-ones shortcut does not apply); a C_jj above 1
+    sends every individual to the pair-sum route."""
+    N = 90
+    C, _ = corr(N, T=64, seed=71)
+    rng = np.random.default_rng(72)
+    C = C.copy()
+    np.fill_diagonal(C, rng.uniform(0.6, 1.0, N))
+    pop = synth.random_labelings(50, N, seed=73, K=12)
+    f_o, ns_o, cs_o, mag = O.fitness(C, pop, want_ns=True, want_cs=True, want_mag=True)
+    for form in ("fp64", "bf16x2"):
+        f_g, ns_g, cs_g = _fit(C, pop, form, 1.0, want_ns=True, want_cs=True)
+        assert np.array_equal(ns_g.cpu().numpy(), ns_o)
+        assert np.all(np.abs(cs_g.cpu().numpy() - cs_o) <= 1e-12 * np.maximum(1.0, ns_o.astype(float) ** 2))
+        assert np.all(np.abs(f_g.cpu().numpy() - f_o) <= fitness_tol(mag, 1e-10))
+    C[7, 7] = 1.25
+    for form in ("fp64", "bf16x2"):
+        assert torch.equal(_fit(C, pop, form, 1.0), _fit(C, pop, form, 0.0))
+
+
 def test_invalid_labels_and_domain_status_as_dense_route():
     C = np.array([[1.0, 1.0, 0.1, 0.0], [1.0, 1.0, 0.1, 0.0], [0.1, 0.1, 1.0, -1.0], [0.0, 0.0, -1.0, 1.0]])
     pop = np.array([[0, 0, 1, 2], [0, 1, 2, 2], [0, 1, 4, 3], [-1, 0, 0, 0], [0, 1, 2, 3], [1, 1, 1, 1]],
