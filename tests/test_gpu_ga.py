@@ -55,6 +55,8 @@ LOCK_CASES = [
     (300, 40, 5, 3, "fp64"),
     (18, 100, 2, 6, "bf16x2"),
     (257, 48, 2, 3, "bf16x2"),
+    (516, 40, 1, 3, "bf16x2"),     # several 128-gene crossover blocks per child
+    (1028, 24, 2, 2, "fp64"),      # more gene pairs than threads: a second round
 ]
 
 
