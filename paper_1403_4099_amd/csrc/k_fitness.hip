@@ -337,20 +337,21 @@ __host__ __device__ __forceinline__ size_t finish_lst_bytes(int max_n) {
 __host__ __device__ __forceinline__ size_t finish_lds_bytes(int max_n) {
     // 14.1 KB at N = 1024 (eight workgroups per CU), 57 KB at N = 4096
     return finish_csum_bytes(max_n) + finish_cnt_bytes(max_n) + finish_lst_bytes(max_n) +
-           2 * kFinWaves * sizeof(double);
+           2 * kFinWaves * sizeof(double) + kFinWaves * sizeof(int);
 }
 
 // Per-label outputs and the log terms of Eq. 8 from n_s (cnt) and c_s held in
 // 64-bit fixed point (csum, scale 2^sc); thread 0 writes fitness[p]. Called by
 // all threads of a kFinThreads workgroup after the barrier that closed the
-// writes to cnt and csum. lst holds kFinWaves lists of lst_stride labels.
+// writes to cnt and csum. lst holds kFinWaves lists of lst_stride labels;
+// nlw holds kFinWaves ints.
 __device__ __forceinline__ void finish_terms(const InstDesc &d, int p, int N, const int *cnt,
                                              const long long *csum, int sc, uint16_t *lst, int lst_stride,
-                                             double *red, int32_t *status) {
+                                             double *red, int *nlw, int32_t *status) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
     // Pass A (wave w, labels [w Q, (w + 1) Q)): per-label outputs, and the labels
-    // with n_s > 1 compacted in ascending order, so the log terms run with every
-    // lane busy.
+    // with n_s > 1 compacted in ascending order; the four lists, in wave order,
+    // list every such label of the individual in ascending order.
     const int QN = finish_quarter(N);                // this instance's quarter; storage is sized by max_n
     const int s_lo = wave * QN, s_hi = min(N, s_lo + QN);
     uint16_t *wl = lst + (size_t)wave * lst_stride;
@@ -366,15 +367,23 @@ __device__ __forceinline__ void finish_terms(const InstDesc &d, int p, int N, co
         if (n > 1) wl[nlist + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)s;
         nlist += __popcll(m);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) nlw[wave] = nlist;
+    __syncthreads();
 
-    // Pass B: the two FP64 log terms of Eq. 8 for each listed cluster.
+    // Pass B: the two FP64 log terms of Eq. 8 for each listed cluster; entry m of
+    // the concatenated lists goes to thread m mod 256, so the (FP64, costly) terms
+    // are spread over the whole workgroup rather than over one wave per quarter.
+    int pre[kFinWaves + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int w = 0; w < kFinWaves; ++w) pre[w + 1] = pre[w] + nlw[w];
     double L = 0.0;
     int nbad = 0;
-    for (int m = lane; m < nlist; m += 64) {
-        const int s = wl[m];
+    for (int m = tid; m < pre[kFinWaves]; m += kFinThreads) {
+        int w = 0;
+#pragma unroll
+        for (int v = 1; v < kFinWaves; ++v) w += m >= pre[v] ? 1 : 0;
+        const int s = lst[(size_t)w * lst_stride + (m - pre[w])];
         const double nd = (double)cnt[s];
         const double c = ldexp((double)csum[s], -sc);
         const double n2 = nd * nd;
@@ -513,7 +522,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int
     }
     __syncthreads();
 
-    finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(max_n), red, status);
+    finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(max_n), red, (int *)(red + 2 * kFinWaves), status);
 }
 
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status,
@@ -803,7 +812,7 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
         return;
     }
     if (tid == 0) gst(d.route + p, 0);
-    finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(lds_n), red, status);
+    finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(lds_n), red, ired + 12, status);
 }
 
 hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int32_t *status,
