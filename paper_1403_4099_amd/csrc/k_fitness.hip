@@ -299,10 +299,11 @@ hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, const Vari
 //      rounded to int64 (sc chosen per individual so N max|v| 2^sc < 2^62:
 //      the integer sums are exact and order-free, error <= n_s 2^-(sc+1));
 //   3. per label s with n_s > 1: c_s, domain check, the two FP64 log terms
-//      of Eq. 8 in literal form. Wave w owns the labels of the w-th quarter of
-//      [0, N): it lists its labels with n_s > 1 in ascending order (ballot +
-//      prefix), sums the terms per lane in list order and over the wave by a
-//      butterfly; the four wave sums are added in wave order (a fixed order).
+//      of Eq. 8 in literal form. Wave w lists the labels of the w-th quarter
+//      of [0, N) with n_s > 1 in ascending order (ballot + prefix); thread t
+//      takes entries t, t + 256, ... of the four lists in wave order and sums
+//      their terms in that order, each wave adds its lanes by a butterfly, and
+//      the four wave sums are added in wave order (a fixed order).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
