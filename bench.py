@@ -309,7 +309,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
-              f"design note, not part of this build", file=sys.stderr)
+              f"design note and is not run here", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

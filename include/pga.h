@@ -74,7 +74,7 @@ extern "C" {
 typedef struct pga_ctx pga_ctx;
 
 /* GA parameters of one instance (Table 3 of Section 5.2.1 lists the paper's
- * own; this build uses tournament selection of size 2, uniform crossover and
+ * own; the library uses tournament selection of size 2, uniform crossover and
  * per-gene random-replacement mutation). */
 typedef struct {
     int32_t elites;        /* E, 0 <= E < P, E <= PGA_E_MAX (elitism, Section 3.1) */

@@ -12,7 +12,7 @@
  *
  * Every function is the plain definition written out (correlation, n_s, c_s,
  * L_c, brute force) or the GA's steps in the paper's order (Algorithm 1),
- * with the operator choices fixed for this build (tournament of two, uniform
+ * with the operator choices fixed here (tournament of two, uniform
  * crossover, per-gene random-replacement mutation, elitism), driven by the
  * Philox4x32-10 counter-based generator written from its published
  * definition (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy
@@ -177,7 +177,7 @@ void oracle_fitness(const double *C, int N, const int32_t *pop, int P, double *f
  * Then C_ij = S_ij / sqrt(S_ii S_jj) clamped to [-1, 1], C_ii = 1, and a
  * stock with S_ii = 0 gets 0 off the diagonal (counted in status[2]). The
  * paper does not give its market-mode estimator or the EWMA's exact form;
- * these are this build's readings. */
+ * these are the readings taken here. */
 void oracle_ewma(const double *R, int N, int T, long ld, double lambda, int reset, int market,
                  double *S, double *C, int32_t *status)
 {
@@ -351,7 +351,7 @@ static int tournament2(const double *f, int a, int b)
  * selection: stochastic universal sampling (Baker, 1987), where individuals
  * occupy consecutive segments of a line in proportion to their (scaled)
  * fitness and the line is read at equally spaced points from one random
- * offset. The paper does not say which scaling; this build ranks
+ * offset. The paper does not say which scaling; the reading here ranks
  * (fitness desc, index asc) and gives rank r (1 = best) the weight
  * floor(2^24 / sqrt(r)) = floor(sqrt(floor(2^48 / r))), computed in exact
  * integer arithmetic, and an individual with fitness -inf weight 0 (if every
