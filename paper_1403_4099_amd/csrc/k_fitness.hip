@@ -546,10 +546,10 @@ hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_
 //   3. pairs above the limit: route[p] = 1 (the pair-sum and finish kernels
 //      evaluate it) and stop;
 //   4. members grouped by cluster (counting sort on the exclusive prefix of
-//      n_s); position x of the grouped list gets its index a(x) within its
-//      cluster, and W, the exclusive prefix of a, numbers the pairs: pair q
-//      belongs to the position x with W[x] <= q < W[x+1] and joins it with
-//      the earlier member at position x - a(x) + (q - W[x]);
+//      n_s); the same scan gives PP, the exclusive prefix of the pair counts
+//      n_s (n_s - 1) / 2, which numbers the pairs: pair q belongs to the
+//      cluster s with PP[s] <= q < PP[s+1], and r = q - PP[s] = b (b-1)/2 + a
+//      (a < b) joins its members a and b;
 //   5. c_s = sum_{j in s} C_jj + 2 sum_{pairs} C_ij (upper triangle, as the
 //      FP64 pair-sum reads it) accumulated in 64-bit fixed point: with
 //      |C| <= 1 every partial sum is bounded by max n_s^2, and the scale 2^sc
@@ -566,12 +566,58 @@ __host__ __device__ __forceinline__ size_t sparse_members_bytes(int n) {
     const size_t m = pad16(2 * (size_t)n), l = finish_lst_bytes(n);
     return m > l ? m : l;
 }
-// LDS: csum int64[n] | cnt int32[n] | begin, then W, int32[n + 1] | members, then the
-// finish lists | labels uint16[n] | kFinWaves x 2 doubles | 16 int32.
-// 20.6 KB at N = 1024 (seven workgroups per CU).
+// LDS: csum int64[n] | cnt int32[n] | begin int32[n + 1] | PP int32[n + 1] | members,
+// then the finish lists | kFinWaves x 2 doubles | 16 int32.
+// 22.7 KB at N = 1024 (seven workgroups per CU).
 __host__ __device__ __forceinline__ size_t sparse_lds_bytes(int n) {
-    return pad16(8 * (size_t)n) + pad16(4 * (size_t)n) + pad16(4 * ((size_t)n + 1)) + sparse_members_bytes(n) +
-           pad16(2 * (size_t)n) + 2 * kFinWaves * sizeof(double) + 16 * sizeof(int);
+    return pad16(8 * (size_t)n) + pad16(4 * (size_t)n) + 2 * pad16(4 * ((size_t)n + 1)) + sparse_members_bytes(n) +
+           2 * kFinWaves * sizeof(double) + 16 * sizeof(int);
+}
+
+// Exclusive prefixes of n_s (begin) and of n_s (n_s - 1) / 2 (pp) over
+// [0, n), as block_exscan; returns the number of pairs; wtot: 8 ints.
+__device__ __forceinline__ int block_exscan_cnt_pairs(const int *cnt, int *begin, int *pp, int n, int *wtot) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (n + kFinThreads - 1) / kFinThreads;
+    const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+    int own = 0, ownp = 0;
+    for (int x = b0; x < b1; ++x) {
+        const int c = cnt[x];
+        own += c;
+        ownp += c * (c - 1) / 2;
+    }
+    int inc = own, incp = ownp;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64), yp = __shfl_up(incp, o, 64);
+        if (lane >= o) {
+            inc += y;
+            incp += yp;
+        }
+    }
+    if (lane == 63) {
+        wtot[wave] = inc;
+        wtot[kFinWaves + wave] = incp;
+    }
+    __syncthreads();
+    int run = inc - own, runp = incp - ownp, totalp = 0;
+#pragma unroll
+    for (int w = 0; w < kFinWaves; ++w) {
+        if (w < wave) {
+            run += wtot[w];
+            runp += wtot[kFinWaves + w];
+        }
+        totalp += wtot[kFinWaves + w];
+    }
+    for (int x = b0; x < b1; ++x) {
+        const int c = cnt[x];
+        begin[x] = run;
+        pp[x] = runp;
+        run += c;
+        runp += c * (c - 1) / 2;
+    }
+    __syncthreads();
+    return totalp;
 }
 
 // Exclusive prefix sum of a[0 .. n) into out (may alias a); thread t scans a
@@ -628,12 +674,11 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     long long *csum = (long long *)b;   b += pad16(8 * n);
     int *cnt = (int *)b;                b += pad16(4 * n);
     int *begin = (int *)b;              b += pad16(4 * (n + 1));
-    int *W = begin;                     // W replaces begin once a(x) is in registers
+    int *PP = (int *)b;                 b += pad16(4 * (n + 1));
     uint16_t *members = (uint16_t *)b;  b += sparse_members_bytes(lds_n);
     uint16_t *lst = members;            // the finish lists replace members after the pairs
-    uint16_t *labs = (uint16_t *)b;     b += pad16(2 * n);
     double *red = (double *)b;          b += 2 * kFinWaves * sizeof(double);
-    int *ired = (int *)b;               // [0, 4) flags, [4, 8) max n_s, [8, 12) scan totals
+    int *ired = (int *)b;               // [0, 4) flags, [4, 8) max n_s, [8, 16) scan totals
 
     const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
     const double *__restrict__ C = d.C;
@@ -657,7 +702,6 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
         const int j = tid + kFinThreads * u;
         if (j < N) {
             if (lr[u] < 0 || lr[u] >= N) bad = 1;
-            else labs[j] = (uint16_t)lr[u];
             cnt[j] = 0;
             csum[j] = 0;
         }
@@ -719,7 +763,9 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     frexp((double)nmax * (double)nmax, &e);          // max n_s^2 < 2^e
     const int sc = 61 - e;
 
-    block_exscan(cnt, begin, N, ired + 8);           // begin[s]: first position of cluster s
+    // begin[s]: first position of cluster s; PP[s]: pairs of the clusters below s
+    const int T = block_exscan_cnt_pairs(cnt, begin, PP, N, ired + 8);   // T == pairs
+    if (tid == 0) PP[N] = T;
     int badc = 0;
 #pragma unroll
     for (int u = 0; u < kSparseCache; ++u) {
@@ -736,27 +782,6 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     if (ones)                                        // sum of n_s diagonal ones, exact
         for (int s = tid; s < N; s += kFinThreads) csum[s] = (long long)cnt[s] << sc;
     __syncthreads();                                 // begin[s] is now the end of cluster s
-    int ax[kSparseCache];
-#pragma unroll
-    for (int u = 0; u < kSparseCache; ++u) {
-        if (u >= ucache) break;
-        const int x = tid + kFinThreads * u;
-        if (x < N) {
-            const int l = labs[members[x]];
-            ax[u] = x - (begin[l] - cnt[l]);         // a(x)
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kSparseCache; ++u) {
-        if (u >= ucache) break;
-        const int x = tid + kFinThreads * u;
-        if (x < N) W[x] = ax[u];
-    }
-    __syncthreads();
-    const int T = block_exscan(W, W, N, ired + 8);   // T == pairs
-    if (tid == 0) W[N] = T;
-    __syncthreads();
 
     // Each thread takes kq consecutive pairs per round (one search, then a forward
     // walk) with their loads issued together; kq = ceil(T / 256), at most kQ, so
@@ -766,12 +791,19 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     constexpr int kQ = 8;
     const int kq = min(kQ, max(1, (T + kFinThreads - 1) / kFinThreads));   // uniform
     for (int q0 = tid * kq; q0 < T; q0 += kq * kFinThreads) {
-        int x = 0, hi = N;                           // W[x] <= q0 < W[hi]
-        while (hi - x > 1) {
-            const int mid = (x + hi) >> 1;
-            if (W[mid] <= q0) x = mid;
+        int cs = 0, hi = N;                          // PP[cs] <= q0 < PP[hi]
+        while (hi - cs > 1) {
+            const int mid = (cs + hi) >> 1;
+            if (PP[mid] <= q0) cs = mid;
             else hi = mid;
         }
+        const int r = q0 - PP[cs];                   // = bq (bq - 1) / 2 + aq, aq < bq
+        int bq = (int)((1.0 + sqrt(1.0 + 8.0 * (double)r)) * 0.5);
+        while (bq * (bq - 1) / 2 > r) --bq;
+        while ((bq + 1) * bq / 2 <= r) ++bq;
+        int aq = r - bq * (bq - 1) / 2;
+        int st = begin[cs] - cnt[cs];                // first position of cluster cs
+        int pend = PP[cs + 1];                       // first pair of the clusters above cs
         double c[kQ];
         int l[kQ];
 #pragma unroll
@@ -780,11 +812,20 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
             l[u] = -1;
             c[u] = 0.0;
             if (u < kq && q < T) {
-                while (W[x + 1] <= q) ++x;           // W[N] = T > q
-                const int y = x - (W[x + 1] - W[x]) + (q - W[x]);
-                const int j = members[x], i = members[y];
+                while (q >= pend) {                  // next cluster with pairs (PP[N] = T > q)
+                    ++cs;
+                    pend = PP[cs + 1];
+                    st = begin[cs] - cnt[cs];
+                    aq = 0;
+                    bq = 1;
+                }
+                const int j = members[st + bq], i = members[st + aq];
                 c[u] = gld(C + (size_t)min(i, j) * N + max(i, j));
-                l[u] = labs[j];
+                l[u] = cs;
+                if (++aq == bq) {
+                    ++bq;
+                    aq = 0;
+                }
             }
         }
         long long run = 0;
