@@ -575,16 +575,19 @@ __host__ __device__ __forceinline__ size_t sparse_lds_bytes(int n) {
 }
 
 // Exclusive prefixes of n_s (begin) and of n_s (n_s - 1) / 2 (pp) over
-// [0, n), as block_exscan; returns the number of pairs; wtot: 8 ints.
-__device__ __forceinline__ int block_exscan_cnt_pairs(const int *cnt, int *begin, int *pp, int n, int *wtot) {
+// [0, n), as block_exscan; returns the number of pairs and sets nmax to the
+// largest n_s; wtot: 12 ints.
+__device__ __forceinline__ int block_exscan_cnt_pairs(const int *cnt, int *begin, int *pp, int n, int *wtot,
+                                                      int &nmax) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per = (n + kFinThreads - 1) / kFinThreads;
     const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
-    int own = 0, ownp = 0;
+    int own = 0, ownp = 0, mx = 0;
     for (int x = b0; x < b1; ++x) {
         const int c = cnt[x];
         own += c;
         ownp += c * (c - 1) / 2;
+        mx = max(mx, c);
     }
     int inc = own, incp = ownp;
 #pragma unroll
@@ -594,13 +597,16 @@ __device__ __forceinline__ int block_exscan_cnt_pairs(const int *cnt, int *begin
             inc += y;
             incp += yp;
         }
+        mx = max(mx, __shfl_xor(mx, o, 64));
     }
     if (lane == 63) {
         wtot[wave] = inc;
         wtot[kFinWaves + wave] = incp;
+        wtot[2 * kFinWaves + wave] = mx;
     }
     __syncthreads();
     int run = inc - own, runp = incp - ownp, totalp = 0;
+    nmax = 0;
 #pragma unroll
     for (int w = 0; w < kFinWaves; ++w) {
         if (w < wave) {
@@ -608,6 +614,7 @@ __device__ __forceinline__ int block_exscan_cnt_pairs(const int *cnt, int *begin
             runp += wtot[kFinWaves + w];
         }
         totalp += wtot[kFinWaves + w];
+        nmax = max(nmax, wtot[2 * kFinWaves + w]);
     }
     for (int x = b0; x < b1; ++x) {
         const int c = cnt[x];
@@ -678,7 +685,7 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     uint16_t *members = (uint16_t *)b;  b += sparse_members_bytes(lds_n);
     uint16_t *lst = members;            // the finish lists replace members after the pairs
     double *red = (double *)b;          b += 2 * kFinWaves * sizeof(double);
-    int *ired = (int *)b;               // [0, 4) flags, [4, 8) max n_s, [8, 16) scan totals
+    int *ired = (int *)b;               // [0, 4) flags, [4, 16) scan totals, then [12, 16) list lengths
 
     const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
     const double *__restrict__ C = d.C;
@@ -731,40 +738,16 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     }
     __syncthreads();
 
-    long long pr = 0;
-    int nm = 0;
-    for (int s = tid; s < N; s += kFinThreads) {
-        const int c = cnt[s];
-        pr += (long long)c * (c - 1) / 2;
-        nm = max(nm, c);
-    }
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) {
-        pr += __shfl_xor(pr, m, 64);
-        nm = max(nm, __shfl_xor(nm, m, 64));
-    }
-    if (lane == 0) {
-        red[wave] = (double)pr;                      // exact: pr <= N^2 / 2 < 2^53
-        ired[4 + wave] = nm;
-    }
-    __syncthreads();
-    double pairs = 0.0;
-    int nmax = 0;
-#pragma unroll
-    for (int w = 0; w < kFinWaves; ++w) {
-        pairs += red[w];
-        nmax = max(nmax, ired[4 + w]);
-    }
-    if (pairs > floor(frac * 0.5 * (double)N * (double)(N - 1))) {
+    // begin[s]: first position of cluster s; PP[s]: pairs of the clusters below s
+    int nmax;
+    const int T = block_exscan_cnt_pairs(cnt, begin, PP, N, ired + 4, nmax);   // T == pairs
+    if ((double)T > floor(frac * 0.5 * (double)N * (double)(N - 1))) {
         if (tid == 0) gst(d.route + p, 1);
         return;                                      // uniform
     }
     int e;
     frexp((double)nmax * (double)nmax, &e);          // max n_s^2 < 2^e
     const int sc = 61 - e;
-
-    // begin[s]: first position of cluster s; PP[s]: pairs of the clusters below s
-    const int T = block_exscan_cnt_pairs(cnt, begin, PP, N, ired + 8);   // T == pairs
     if (tid == 0) PP[N] = T;
     int badc = 0;
 #pragma unroll
