@@ -230,3 +230,33 @@ def test_evolve_through_the_route_in_lockstep_with_oracle(form, frac):
     f_o, mag = O.fitness(C, I.pop.cpu().numpy(), want_mag=True)
     tol = fitness_tol(mag, 1e-10) if (form == "fp64" or frac == 1.0) else 1e-4 * mag + 1e-9
     assert np.all(np.abs(I.fitness.cpu().numpy() - f_o) <= tol)
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+def test_batch_mixing_an_instance_above_2048_equals_each_alone(form):
+    """One launch sequence holds an instance above 2048 stocks (always the pair-sum route) and
+    small ones (cluster-pair route, with LDS laid out for 2048): each result equals its own run."""
+    specs = [(2100, 6, 0, 31), (150, 40, 1, 32), (37, 24, 2, 33)]
+    G = 2
+    ctx = pga.Context()
+
+    def inst(N, P, iid, seed, pop=None):
+        C, _ = corr(N, T=64, seed=80 + iid)
+        Cg = _g(C)
+        hi = lo = None
+        if form == "bf16x2":
+            hi, lo = pga.split(Cg)
+        return pga.make_instance(Cg, P, hi=hi, lo=lo, pop=pop, stats_rows=G + 1, elites=1, seed=seed,
+                                 instance_id=iid)
+
+    with pga.route(1.0 / 64):
+        alone = []
+        for N, P, iid, seed in specs:
+            I = inst(N, P, iid, seed)
+            ctx.evolve([I], G, form=form, init=True)
+            alone.append(I)
+        batch = [inst(N, P, iid, seed) for N, P, iid, seed in specs]
+        ctx.evolve(batch, G, form=form, init=True)
+        torch.cuda.synchronize()
+    for a, b in zip(alone, batch):
+        assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness) and torch.equal(a.stats, b.stats)
