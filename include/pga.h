@@ -199,6 +199,27 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
                 int32_t *n_s, double *c_s, int32_t *status, void *ws, size_t ws_bytes,
                 void *stream);
 
+/* ---- fitness without allocation --------------------------------------------
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, hosts that forbid hipMalloc.
+ * Same computation, arguments and results as pga_fitness, without (ws,
+ * ws_bytes): the scratch memory comes from a static device array of
+ * PGA_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs
+ * on until the process ends (its address is looked up once per device, on
+ * the first call with that device current). The call makes no hipMalloc or
+ * hipFree and creates no events (kernel timing does not apply to it).
+ * Limit: pga_fitness_ws_bytes(N, P, form) <= PGA_NOALLOC_SCRATCH_BYTES, else
+ * PGA_ERR_UNSUPPORTED with nothing enqueued (N = 1024, P = 4096 fits in both
+ * forms). Every call on one GPU shares that GPU's array, and the array keeps
+ * the last call's contents (each call writes all it reads): calls that can
+ * overlap on one GPU (different streams, different host threads) race and
+ * must be serialised by the caller. Errors otherwise as pga_fitness. Async. */
+#define PGA_NOALLOC_SCRATCH_BYTES ((size_t)40 << 20)
+size_t pga_fitness_noalloc_max_bytes(void);
+int pga_fitness_noalloc(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
+                        const int32_t *labels, int32_t P, int32_t form, double *fitness,
+                        int32_t *n_s, double *c_s, int32_t *status, void *stream);
+
 /* Cluster-pair route limit (process-wide, read at each call; pga_evolve's
  * cached graphs are keyed by it): frac in [0, 1]; 0 sends every individual to
  * the pair-sum kernels; 1 sends every individual with N <= 2048 to the

@@ -73,8 +73,13 @@ constexpr int kTimers = 11;
 double g_tsum[kTimers] = {0};
 int64_t g_tcnt[kTimers] = {0};
 
+// Set while the allocation-free entry point runs: its launches are never
+// bracketed by events (event creation is an allocation).
+thread_local bool t_untimed = false;
+
 template <class F>
 hipError_t timed(int id, hipStream_t s, F &&launch) {
+    if (t_untimed) return launch();
     bool on;
     {
         std::lock_guard<std::mutex> lk(g_tmu);
@@ -306,6 +311,11 @@ const char *pga_strerror(int code) {
 }
 
 int pga_last_hip_error(void) { return g_last_hip; }
+}  // extern "C"
+
+void pga::note_hip_error(int e) { g_last_hip = e; }
+
+extern "C" {
 
 // ---- correlation and split ----------------------------------------------------------
 int32_t pga_split_ld(int32_t N) { return N < 1 ? 0 : split_ld(N); }
@@ -437,7 +447,20 @@ hipError_t use_variant(const InstDesc &d, const Tables &t, int form, int vi, Sha
 int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
                 const int32_t *labels, int32_t P, int32_t form, double *fitness, int32_t *n_s,
                 double *c_s, int32_t *status, void *ws, size_t ws_bytes, void *stream) {
-    hipStream_t s = (hipStream_t)stream;
+    return pga::fitness_call(C, C_hi, C_lo, N, labels, P, form, fitness, n_s, c_s, status, ws, ws_bytes,
+                             (hipStream_t)stream, true);
+}
+}  // extern "C"
+
+namespace pga {
+int fitness_call(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N, const int32_t *labels,
+                 int32_t P, int32_t form, double *fitness, int32_t *n_s, double *c_s, int32_t *status, void *ws,
+                 size_t ws_bytes, hipStream_t s, bool timing_allowed) {
+    struct Untimed {
+        bool prev;
+        explicit Untimed(bool on) : prev(t_untimed) { t_untimed = prev || on; }
+        ~Untimed() { t_untimed = prev; }
+    } guard(!timing_allowed);
     Tables t;
     Shape sh;
     InstDesc d;
@@ -449,6 +472,9 @@ int pga_fitness(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int
     HIP_TRY(run_fitness(t, sh, form, 0, status, s));
     return PGA_OK;
 }
+}  // namespace pga
+
+extern "C" {
 
 // ---- autotuning ---------------------------------------------------------------------------
 int pga_variant_count(int32_t form) {

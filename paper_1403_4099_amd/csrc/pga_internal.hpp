@@ -202,6 +202,15 @@ hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s);
 hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, hipStream_t s);
 hipError_t launch_sus(Tables t, int max_p, hipStream_t s);
 hipError_t launch_copy_back(Tables t, int total_inds, int G, hipStream_t s);
+// Records a hipError_t for pga_last_hip_error() on this thread.
+void note_hip_error(int e);
+
+// pga_fitness with a choice of whether launches may be event-timed (the
+// allocation-free entry point passes false).
+int fitness_call(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N, const int32_t *labels,
+                 int32_t P, int32_t form, double *fitness, int32_t *n_s, double *c_s, int32_t *status, void *ws,
+                 size_t ws_bytes, hipStream_t s, bool timing_allowed);
+
 hipError_t launch_best(const double *fitness, const int32_t *labels, int P, int N, int32_t *out,
                        double *out_f, hipStream_t s);
 

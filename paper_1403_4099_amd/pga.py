@@ -41,7 +41,7 @@ SYMBOLS = [
     "pga_best_ws_bytes", "pga_best", "pga_timing_enable", "pga_timing_reset", "pga_timing_read",
     "pga_variant_count", "pga_variant_info", "pga_tune_ws_bytes", "pga_tune", "pga_tune_set",
     "pga_tune_get", "pga_ewma_ws_bytes", "pga_ewma", "pga_peak_mfma_bf16", "pga_route_set",
-    "pga_route_get",
+    "pga_route_get", "pga_fitness_noalloc", "pga_fitness_noalloc_max_bytes",
 ]
 
 
@@ -110,6 +110,8 @@ def load(path: str = LIB_PATH):
         "pga_peak_mfma_bf16": ([vp, i32, i32, ct.POINTER(ct.c_double), vp], ct.c_int),
         "pga_route_set": ([ct.c_double], ct.c_int),
         "pga_route_get": ([], ct.c_double),
+        "pga_fitness_noalloc": ([vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp], ct.c_int),
+        "pga_fitness_noalloc_max_bytes": ([], sz),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -213,6 +215,33 @@ def fitness(C: torch.Tensor, labels: torch.Tensor, form: str = "fp64", hi=None, 
     if want_cs:
         res.append(cs)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def fitness_noalloc(C: torch.Tensor, labels: torch.Tensor, form: str = "fp64", hi=None, lo=None,
+                    want_ns: bool = False, want_cs: bool = False, status: torch.Tensor | None = None,
+                    out: torch.Tensor | None = None):
+    """As fitness(), through pga_fitness_noalloc (scratch in the library's static device array;
+    the library allocates nothing). Output tensors are allocated here unless passed in."""
+    L = load()
+    dev = _dev()
+    P, N = labels.shape
+    assert labels.dtype == torch.int32 and labels.is_contiguous()
+    f = out if out is not None else torch.empty(P, dtype=torch.float64, device=dev)
+    ns = torch.empty((P, N), dtype=torch.int32, device=dev) if want_ns else None
+    cs = torch.empty((P, N), dtype=torch.float64, device=dev) if want_cs else None
+    rc = L.pga_fitness_noalloc(_ptr(C), _ptr(hi), _ptr(lo), N, _ptr(labels), P, FORMS[form], _ptr(f),
+                               _ptr(ns), _ptr(cs), _ptr(status), _stream())
+    _check(rc, "pga_fitness_noalloc")
+    res = [f]
+    if want_ns:
+        res.append(ns)
+    if want_cs:
+        res.append(cs)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def noalloc_max_bytes() -> int:
+    return int(load().pga_fitness_noalloc_max_bytes())
 
 
 def fitness_ws_bytes(N: int, P: int, form: str = "fp64") -> int:

@@ -88,6 +88,15 @@ def test_host_side_argument_errors(lib):
     assert sus_bytes >= lib.pga_evolve_ws_bytes(arr, 1, 0) + 4 * (4 + 8)
     arr[0].prm.tol = float("nan")
     assert lib.pga_evolve_ws_bytes(arr, 1, 0) == 0
+    # allocation-free fitness: same argument checks; a workspace need above the static scratch is refused
+    assert lib.pga_fitness_noalloc(fake, None, None, 0, fake, 4, 0, fake, None, None, None, None) == -1
+    assert lib.pga_fitness_noalloc(fake, None, None, 8, fake, 4, 7, fake, None, None, None, None) == -1
+    assert lib.pga_fitness_noalloc(fake, None, None, pga.N_MAX + 1, fake, 4, 0, fake, None, None, None,
+                                   None) == -4
+    assert lib.pga_fitness_noalloc(None, None, None, 8, None, 0, 0, None, None, None, None, None) == 0
+    assert lib.pga_fitness_ws_bytes(2048, 4096, 0) > lib.pga_fitness_noalloc_max_bytes()
+    assert lib.pga_fitness_noalloc(fake, None, None, 2048, fake, 4096, 0, fake, None, None, None, None) == -4
+    assert lib.pga_fitness_ws_bytes(1024, 4096, 1) <= lib.pga_fitness_noalloc_max_bytes() == 40 << 20
     # best: P < 1
     assert lib.pga_best(fake, fake, 0, 4, None, None, None, wsp, 1 << 16, None) == -1
 
