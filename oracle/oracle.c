@@ -540,11 +540,23 @@ static void term_update(double state[4], double b, int stall_gens, double tol)
     if (stall_gens > 0 && state[1] >= (double)stall_gens) state[2] = 1.0;
 }
 
+/* The termination test alone, for lockstep checks: one evaluated generation
+ * with best fitness b applied to state = {ref, stall, stopped, gens}. */
+void oracle_term_test(double state[4], double b, int stall_gens, double tol)
+{
+    term_update(state, b, stall_gens, tol);
+}
+
 /* Up to G generations of Algorithm 1 from generation gen0, then a final
  * fitness. If init != 0 the population is first filled by oracle_init_pop at
  * gen0 and state is reset to {-inf, 0, 0, 0}. Each generation: evaluate,
  * record statistics row g, apply the termination test, and, unless the run
  * has stopped, breed generation g + 1 (state[3] counts the generations bred).
+ * Algorithm 1 tests each generation once: a call that continues a state that
+ * has already tested a generation (ref finite or stall > 0) starts from the
+ * population the previous call tested last, so its first evaluation records
+ * statistics but does not enter the test again; splitting a run into several
+ * calls therefore gives the same run as one call.
  * A stopped run keeps its last population: nothing further is evaluated,
  * recorded or bred, in this call or a later one with the same state. pop
  * (P x N) is updated in place; fit (P) holds the fitness of the final
@@ -571,12 +583,13 @@ int oracle_evolve_term(const double *C, int N, int P, int E, int selection, uint
         free(next);
         return 0;
     }
+    const int tested = isfinite(state[0]) || state[1] != 0.0;
     double row[4];
     for (int g = 0; g <= G; ++g) {
         oracle_fitness(C, N, pop, P, fit, NULL, NULL, NULL, status);
         oracle_stats(fit, P, row);
         if (stats) memcpy(stats + 4 * (size_t)g, row, sizeof(row));
-        term_update(state, row[0], stall_gens, tol);
+        if (g > 0 || !tested) term_update(state, row[0], stall_gens, tol);
         if (g == G || state[2] != 0.0) break;
         oracle_breed_sel(pop, fit, N, P, E, selection, p_cross_thr, p_mut_thr, seed, inst,
                          gen0 + (uint32_t)g, next);

@@ -72,6 +72,8 @@ def lib():
         L.oracle_ewma.argtypes = [vp, ct.c_int, ct.c_int, ct.c_long, d, ct.c_int, ct.c_int, vp, vp, vp]
         L.oracle_ewma.restype = None
         L.oracle_evolve_term.restype = ct.c_int
+        L.oracle_term_test.argtypes = [vp, d, ct.c_int, d]
+        L.oracle_term_test.restype = None
         L.oracle_canonical.argtypes = [vp, ct.c_int, vp]
         L.oracle_canonical.restype = None
         L.oracle_best.argtypes = [vp, vp, ct.c_int, ct.c_int, vp, vp, vp]
@@ -252,6 +254,14 @@ def evolve_term(C, P, G, stall_gens, tol, E=2, p_cross_thr=P_CROSS_DEFAULT, p_mu
     if rc != 0:
         raise ValueError(f"oracle_evolve_term rc={rc}")
     return pop, fit, st, st8
+
+
+def term_test(state, b, stall_gens, tol):
+    """The termination test of one evaluated generation with best fitness b; returns the new
+    state [ref, stall, stopped, gens] (the input is not modified)."""
+    st = _c64(state).copy()
+    lib().oracle_term_test(_p(st), float(b), int(stall_gens), float(tol))
+    return st
 
 
 def ewma(R, lam=0.98, S=None, market=True, status=None):

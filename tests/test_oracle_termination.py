@@ -66,6 +66,22 @@ def test_continuation_matches_one_call(c1):
     assert np.array_equal(sa[12], st[12])
 
 
+@pytest.mark.parametrize("chunk", [1, 3, 7, 12])
+def test_any_split_into_calls_equals_one_call(c1, chunk):
+    # Algorithm 1 tests each generation once: a continuing call re-evaluates the population the
+    # previous call tested last and must not test it again, so a run cut into calls of `chunk`
+    # generations stops at the same generation with the same state and population as one call.
+    pop, fit, _, state = O.evolve_term(c1, 60, 300, 15, 1e-5, seed=5)
+    assert state[2] == 1
+    p, s, g0 = None, None, 0
+    for _ in range(400):
+        p, f, _, s = O.evolve_term(c1, 60, chunk, 15, 1e-5, seed=5, pop=p, state=s, gen0=g0)
+        g0 = int(s[3])
+        if s[2] == 1:
+            break
+    assert np.array_equal(s, state) and np.array_equal(p, pop) and np.array_equal(f, fit)
+
+
 def test_call_after_stop_changes_nothing(c1):
     pop, fit, _, state = O.evolve_term(c1, 50, 200, 5, 1e9, seed=4)
     assert state[2] == 1
