@@ -97,7 +97,11 @@ typedef struct {
  * generation with best fitness b: b improves on ref when ref is not finite
  * and b is, or when b > ref + tol * max(1, |ref|); an improvement sets
  * ref = b and stall = 0, anything else adds 1 to stall; the instance stops
- * when stall reaches stall_gens. A stopped instance keeps its population:
+ * when stall reaches stall_gens. Each generation is tested once: the first
+ * evaluation of a call that continues a state which has already tested a
+ * generation (ref finite or stall > 0) re-evaluates the population the
+ * previous call tested last and leaves the state unchanged, so a run split
+ * into several calls equals one call. A stopped instance keeps its population:
  * no later generation of this or any later call evaluates, records
  * statistics rows or breeds it. */
 typedef struct {
@@ -127,6 +131,9 @@ typedef struct {
 /* ---- context and errors ------------------------------------------------ */
 int pga_ctx_create(pga_ctx **out);
 int pga_ctx_destroy(pga_ctx *ctx);
+/* Number of captured graphs the context holds (at most 32; the least recently
+ * launched is dropped to make room). PGA_ERR_ARG for a null context. */
+int pga_ctx_graphs(pga_ctx *ctx);
 const char *pga_strerror(int code);
 int pga_last_hip_error(void);     /* hipError_t of the last PGA_ERR_HIP on this thread */
 
@@ -138,7 +145,11 @@ int pga_last_hip_error(void);     /* hipError_t of the last PGA_ERR_HIP on this 
  * s_i = 0 gets 0 off the diagonal and is counted in status[PGA_ST_ZEROVAR].
  * C_hi / C_lo (nullable, both or neither): also write the BF16 split of C
  * (as pga_split). Requires 1 <= N <= PGA_N_MAX, T >= 2. */
-size_t pga_correlate_ws_bytes(int32_t N);   /* 2N doubles: row means and sums of squares */
+/* Workspace: 2N doubles (row means, sums of squares) and the partial Gram
+ * tiles of the FP64 MFMA Gram (the t range of each 64 x 64 tile of the upper
+ * triangle is split into up to 8 slices, added in slice order). 0 for N < 1
+ * or N > PGA_N_MAX. */
+size_t pga_correlate_ws_bytes(int32_t N);
 int pga_correlate(const double *R, int32_t N, int32_t T, int64_t ld_r, double *C,
                   uint16_t *C_hi, uint16_t *C_lo, int32_t *status, void *ws, size_t ws_bytes,
                   void *stream);
@@ -167,8 +178,9 @@ int pga_split(const double *C, int32_t N, uint16_t *C_hi, uint16_t *C_lo, void *
  * BF16 split of C as pga_split. Computed as S <- lambda^T S + X X^T with
  * x_it scaled by sqrt((1 - lambda) lambda^(T-1-t)) (FP64 throughout).
  * Errors: PGA_ERR_ARG (null pointer, N < 1, T < 1, ld_r < T, lambda outside
- * [0, 1), unknown flag, one of hi/lo), PGA_ERR_UNSUPPORTED (split with
- * N > PGA_N_MAX), PGA_ERR_WORKSPACE (pga_ewma_ws_bytes(N, T)). Async. */
+ * [0, 1), unknown flag, one of hi/lo), PGA_ERR_UNSUPPORTED (N > PGA_N_MAX),
+ * PGA_ERR_WORKSPACE (pga_ewma_ws_bytes(N, T): the weighted returns, N x T
+ * doubles, and the partial Gram tiles as pga_correlate). Async. */
 size_t pga_ewma_ws_bytes(int32_t N, int32_t T);
 int pga_ewma(const double *R, int32_t N, int32_t T, int32_t ld_r, double lambda, int32_t flags,
              double *S, double *C, uint16_t *C_hi, uint16_t *C_lo, int32_t *status, void *ws,
@@ -265,6 +277,14 @@ int pga_tune(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_
              size_t ws_bytes, int32_t *out_variant, float *out_ms, void *stream);
 int pga_tune_set(int32_t form, int32_t N, int32_t P, int32_t variant);
 int pga_tune_get(int32_t form, int32_t N, int32_t P);
+/* Persisted tuning table (host files, SYNC). pga_tune_save writes every entry
+ * as a text line "form ceil(N/64) ceil(log2 P) variant" and returns the number
+ * of entries; pga_tune_load adds the entries of such a file to the table (an
+ * entry replaces the one with the same key) and returns their number. A file
+ * that cannot be opened, or a load file with any malformed or out-of-range
+ * line (it is then not applied at all): PGA_ERR_ARG. */
+int pga_tune_save(const char *path);
+int pga_tune_load(const char *path);
 
 /* ---- evolution (Algorithm 1) ------------------------------------------- */
 /* Runs `generations` (G >= 0) generations on each of the n_inst instances
@@ -285,6 +305,12 @@ int pga_tune_get(int32_t form, int32_t N, int32_t P);
  * uniform crossover with probability p_cross and per-gene mutation to a
  * uniform label. After G generations
  * the final population is evaluated into `fitness` and stats row G.
+ * Launch sizes are rounded up to one of four values per octave and the
+ * instance list padded with empty slots, so a captured graph is replayed for
+ * every later call whose instance count, totals of tiles and individuals,
+ * largest N and largest P round to the same values (and with the same
+ * workspace, status buffer, form, G, kernel variant and route limit); the
+ * instances' descriptors are uploaded at each call.
  * Random draws come from Philox4x32-10 with counter
  *   (block, individual or child, generation, tag | instance_id << 4),
  * tags INIT=0, SELECT=1, CROSSOVER=2, MUTATION=3, SUS=4, SHUFFLE=5, so a run is a pure
@@ -318,7 +344,8 @@ int pga_best(const double *fitness, const int32_t *labels, int32_t P, int32_t N,
  * elapsed milliseconds and launch count for kernel id
  *   0 pair-sum FP64, 1 pair-sum BF16x2 MFMA, 2 finish (n_s, c_s, L_c),
  *   3 rank/stats, 4 breed, 5 correlate, 6 split, 7 init, 8 SUS ranks and
- *   weights, 9 EWMA correlation, 10 cluster-pair fitness. */
+ *   weights, 9 EWMA correlation, 10 cluster-pair fitness, 11 the labels with
+ *   n_s >= 2 (BF16x2 form, before its pair-sum). */
 int pga_timing_enable(int on);
 int pga_timing_reset(void);
 int pga_timing_read(int kernel_id, double *total_ms, int64_t *count);
@@ -332,6 +359,15 @@ int pga_timing_read(int kernel_id, double *total_ms, int64_t *count);
  * times the launch with events on `stream`. PGA_ERR_ARG for out == NULL,
  * n_workgroups < 1 or iters < 1. Async. */
 int pga_peak_mfma_bf16(float *out, int32_t n_workgroups, int32_t iters, double *flops, void *stream);
+
+/* Measurement aid (not part of the method): sustained FP64 vector FMA
+ * throughput. Launches n_workgroups x 256 threads; every lane runs iters
+ * rounds of 8 independent v_fma_f64 chains on register operands and each wave
+ * writes one double to out (device, caller-owned, 4 * n_workgroups doubles).
+ * *flops (host, may be NULL) receives n_workgroups * 256 * iters * 8 * 2; the
+ * caller times the launch. PGA_ERR_ARG for out == NULL, n_workgroups < 1 or
+ * iters < 1. Async. */
+int pga_peak_fp64(double *out, int32_t n_workgroups, int32_t iters, double *flops, void *stream);
 
 #ifdef __cplusplus
 }

@@ -1,10 +1,11 @@
 // Correlation (Eq. 7 of Section 2.2.3) and the BF16 hi + lo split of C.
 //
 //   row stats : mean_i and s_i = sum_t (R_it - mean_i)^2 (two passes, FP64)
-//   corr      : C_ij = sum_t x_it x_jt / sqrt(s_i s_j) on 64 x 64 output tiles
-//               of the upper triangle, x = R - mean staged through LDS,
-//               FP64 FMA in ascending t; mirrored store, C_ii = 1, clamp to
-//               [-1, 1], zero-variance stocks get 0 off the diagonal
+//   corr      : C_ij = sum_t x_it x_jt / sqrt(s_i s_j): FP64 MFMA Gram on 64 x 64
+//               output tiles of the upper triangle (t split into slices), x =
+//               R - mean staged through LDS; the slices added in order, C_ii =
+//               1, clamp to [-1, 1], zero-variance stocks get 0 off the
+//               diagonal, mirrored store
 //   split     : hi = bf16(C), lo = bf16(C - hi), round to nearest even from
 //               FP64, zero padding up to the 32-aligned leading dimension
 //   ewma      : online exponentially weighted correlation with the market
@@ -54,84 +55,227 @@ hipError_t launch_row_stats(const double *R, int N, int T, int64_t ld, double *m
     return hipGetLastError();
 }
 
-// 64 x 64 output tile per workgroup; thread (tx, ty) owns rows i0 + 4ty..+3
-// and columns j0 + 4tx..+3. K loop over t in chunks of 16 through LDS;
-// x(g, t) gives the (already centred or weighted) value of row g at time t.
-constexpr int kCT = 64, kCK = 16;
+// ---- Gram matrix on FP64 MFMA ----------------------------------------------------
+// G_ij = sum_t x_it x_jt over the upper triangle of 64 x 64 output tiles, each
+// tile's t range split into S slices (S from gram_split: enough workgroups to
+// fill the GPU), one workgroup per (tile, slice):
+//   * the workgroup stages x of its 64 + 64 rows, 16 samples at a time, in LDS
+//     (two buffers: the next chunk's global loads are in flight while the
+//     current one is multiplied); x = R - mean for the correlation, the
+//     weighted returns as they are for the EWMA covariance;
+//   * wave w owns the 32 x 32 quadrant (w / 2, w % 2) of the tile: four 16 x 16
+//     blocks, each accumulated by v_mfma_f64_16x16x4_f64 (lane l supplies
+//     A[l % 16][l / 16] and B[l / 16][l % 16]: row l % 16 of A and column
+//     l % 16 of B at the four samples t0 + 4 (l / 16) .. + 3, one per MFMA, so
+//     both operands see the same t);
+//   * the slice's 64 x 64 partial Gram goes to the workspace; a finish kernel
+//     adds the S slices of a tile in slice order (a fixed order: the result
+//     does not depend on timing), applies the normalisation and writes the
+//     tile and its mirror image through LDS, both coalesced.
+typedef double gram_d4 __attribute__((ext_vector_type(4)));
 
-template <class X>
-__device__ __forceinline__ void gram_tile(X x, int N, int T, int i0, int j0, double (&acc)[4][4]) {
-    __shared__ double As[kCK][kCT + 1];
-    __shared__ double Bs[kCK][kCT + 1];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+constexpr int kGT = 64;                 // output tile edge
+constexpr int kGK = 16;                 // samples per staged chunk
+constexpr int kGPad = kGK + 2;          // LDS row stride (doubles): 16-byte aligned rows, spread banks
+constexpr int kGMaxSplit = 8;
 
-    for (int t0 = 0; t0 < T; t0 += kCK) {
+int gram_tiles(int N) {
+    const int nt = (N + kGT - 1) / kGT;
+    return nt * (nt + 1) / 2;
+}
+
+// Slices per tile for a given N (upper bound) and, with T known, the slices used:
+// about 512 workgroups in all, at most kGMaxSplit, and at least 64 samples per slice.
+int gram_split_max(int N) {
+    const int t = gram_tiles(N);
+    int S = (512 + t - 1) / t;
+    return S < 1 ? 1 : (S > kGMaxSplit ? kGMaxSplit : S);
+}
+
+int gram_split(int N, int T) {
+    int S = gram_split_max(N);
+    const int by_t = T / 64 > 1 ? T / 64 : 1;
+    return S < by_t ? S : by_t;
+}
+
+size_t gram_ws_doubles(int N) { return (size_t)gram_tiles(N) * gram_split_max(N) * kGT * kGT; }
+
+// Tile u of the upper triangle, row-major: (ti, tj) with ti <= tj.
+__device__ __forceinline__ void gram_tile_ij(int u, int nt, int &ti, int &tj) {
+    ti = 0;
+    while (u >= nt - ti) {
+        u -= nt - ti;
+        ++ti;
+    }
+    tj = ti + u;
+}
+
+template <bool CENTER>
+__global__ __launch_bounds__(256) void k_gram_mfma(const double *X, int N, int T, int64_t ld, const double *mu,
+                                                   int nt, int tiles, int S, double *part) {
+    __shared__ __align__(16) double sA[2][kGT * kGPad];
+    __shared__ __align__(16) double sB[2][kGT * kGPad];
+    const int total = tiles * S;
+    const int unit = xcd_tile(blockIdx.x, total);           // each XCD: a contiguous range of units
+    const int slice = unit / tiles, tile = unit - slice * tiles;
+    int ti, tj;
+    gram_tile_ij(tile, nt, ti, tj);
+    const int i0 = ti * kGT, j0 = tj * kGT;
+    const int per = ((T + S - 1) / S + kGK - 1) / kGK * kGK;  // samples per slice, whole chunks
+    const int ts = slice * per;
+    const int te = min(T, ts + per);
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    // staging: element x = e * 256 + tid of a 64 x 16 chunk is row x / 16, sample x % 16, so each load
+    // instruction of a wave reads four full 128-byte row segments
+    const int srow = tid >> 4, scol = tid & 15;
+    // Loads take clamped (always valid) addresses and the value is multiplied by a 0/1 weight
+    // afterwards, so every load is issued unconditionally and together with the others: rows past
+    // N and samples past the slice give 0 (a clamped address repeats an element of the same row
+    // or of row N - 1, whose entries are discarded).
+    double muA[4], muB[4], wA[4], wB[4];
+    const double *rowA[4], *rowB[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int ra = i0 + 16 * e + srow, rb = j0 + 16 * e + srow;
+        muA[e] = CENTER ? mu[min(ra, N - 1)] : 0.0;
+        muB[e] = CENTER ? mu[min(rb, N - 1)] : 0.0;
+        wA[e] = ra < N ? 1.0 : 0.0;
+        wB[e] = rb < N ? 1.0 : 0.0;
+        rowA[e] = X + (size_t)min(ra, N - 1) * ld;
+        rowB[e] = X + (size_t)min(rb, N - 1) * ld;
+    }
+    // The raw values are loaded first and only used when they are stored into LDS, after the
+    // current chunk's MFMAs have been issued, so the loads' latency is hidden behind them.
+    double va[4], vb[4], wt = 0.0;
+    auto load = [&](int t0) {
+        const int t = t0 + scol;
+        wt = t < te ? 1.0 : 0.0;
+        const int tc = min(t, te - 1);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int idx = threadIdx.x + 256 * e;   // 0..1023
-            const int r = idx >> 4, kk = idx & 15;
-            const int t = t0 + kk;
-            const int gi = i0 + r, gj = j0 + r;
-            As[kk][r] = (gi < N && t < T) ? x(gi, t) : 0.0;
-            Bs[kk][r] = (gj < N && t < T) ? x(gj, t) : 0.0;
+            va[e] = rowA[e][tc];
+            vb[e] = rowB[e][tc];
         }
-        __syncthreads();
+    };
+    auto store = [&](int buf) {
 #pragma unroll
-        for (int kk = 0; kk < kCK; ++kk) {
-            double a[4], b[4];
+        for (int e = 0; e < 4; ++e) {
+            sA[buf][(16 * e + srow) * kGPad + scol] = (va[e] - muA[e]) * (wA[e] * wt);
+            sB[buf][(16 * e + srow) * kGPad + scol] = (vb[e] - muB[e]) * (wB[e] * wt);
+        }
+    };
+
+    const int qr = wave >> 1, qc = wave & 1;
+    const int m = lane & 15, kq = lane >> 4;
+    gram_d4 acc[2][2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[kk][4 * ty + q];
-                b[q] = Bs[kk][4 * tx + q];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
+
+    int buf = 0;
+    if (ts < te) {
+        load(ts);
+        store(0);
+    }
+    __syncthreads();
+    for (int t0 = ts; t0 < te; t0 += kGK) {
+        const bool more = t0 + kGK < te;
+        if (more) load(t0 + kGK);
+        const double *A = sA[buf];
+        const double *B = sB[buf];
+        double xa[2][4], xb[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const double *pa = A + (32 * qr + 16 * a + m) * kGPad + 4 * kq;
+            const double *pb = B + (32 * qc + 16 * a + m) * kGPad + 4 * kq;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                xa[a][e] = pa[e];
+                xb[a][e] = pb[e];
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
         }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a][e], xb[b][e], acc[a][b], 0, 0, 0);
+        if (more) store(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
+    }
+    // Where each accumulator register sits in its 16 x 16 block is read off the hardware: one
+    // MFMA with A[i][0] = i, B[0][j] = 1 (zero for k > 0) gives every register its row i, one with
+    // A[i][0] = 1, B[0][j] = j its column j (small integers, exact in FP64).
+    const double idx = kq == 0 ? (double)m : 0.0, one = kq == 0 ? 1.0 : 0.0;
+    const gram_d4 zero = {0.0, 0.0, 0.0, 0.0};
+    const gram_d4 rowv = __builtin_amdgcn_mfma_f64_16x16x4f64(idx, one, zero, 0, 0, 0);
+    const gram_d4 colv = __builtin_amdgcn_mfma_f64_16x16x4f64(one, idx, zero, 0, 0, 0);
+    double *out = part + ((size_t)slice * tiles + tile) * (kGT * kGT);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ri = (int)rowv[r], ci = (int)colv[r];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) out[(32 * qr + 16 * a + ri) * kGT + 32 * qc + 16 * b + ci] = acc[a][b][r];
     }
 }
 
-__global__ __launch_bounds__(256) void k_corr(const double *R, int N, int T, int64_t ld,
-                                              const double *mu, const double *ss, double *C) {
-    const int ti = blockIdx.y, tj = blockIdx.x;
-    if (ti > tj) return;
-    const int i0 = ti * kCT, j0 = tj * kCT;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double acc[4][4];
-    gram_tile([&](int g, int t) { return R[(size_t)g * ld + t] - mu[g]; }, N, T, i0, j0, acc);
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        const int i = i0 + 4 * ty + x;
-        if (i >= N) continue;
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            const int j = j0 + 4 * tx + y;
-            if (j >= N || j < i) continue;
-            double v;
-            if (i == j) {
-                v = 1.0;
-            } else if (ss[i] == 0.0 || ss[j] == 0.0) {
-                v = 0.0;
-            } else {
-                v = acc[x][y] / sqrt(ss[i] * ss[j]);
-                v = fmin(1.0, fmax(-1.0, v));
-            }
-            C[(size_t)i * N + j] = v;
-            C[(size_t)j * N + i] = v;
+// Sum of the S slices of element e of tile `tile` (slice order).
+__device__ __forceinline__ double gram_sum(const double *part, int tiles, int S, int tile, int e) {
+    double v = 0.0;
+    for (int s = 0; s < S; ++s) v += part[((size_t)s * tiles + tile) * (kGT * kGT) + e];
+    return v;
+}
+
+// Writes value f(i, j, g) of every element of the tile at (i, j) and, off the
+// diagonal, at (j, i), both row-wise through an LDS transpose.
+template <class F>
+__device__ __forceinline__ void gram_emit(const double *part, int N, int nt, int tiles, int S, double *dst, F f) {
+    __shared__ double tr[kGT][kGT + 1];
+    const int tile = blockIdx.x;
+    int ti, tj;
+    gram_tile_ij(tile, nt, ti, tj);
+    const int i0 = ti * kGT, j0 = tj * kGT;
+    for (int e = threadIdx.x; e < kGT * kGT; e += 256) {
+        const int r = e / kGT, c = e % kGT;
+        const int i = i0 + r, j = j0 + c;
+        double v = 0.0;
+        if (i < N && j < N && (ti != tj || i <= j)) {
+            v = f(i, j, gram_sum(part, tiles, S, tile, e));
+            dst[(size_t)i * N + j] = v;
         }
+        tr[c][r] = v;
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kGT * kGT; e += 256) {
+        const int r = e / kGT, c = e % kGT;             // destination row j0 + r, column i0 + c
+        const int j = j0 + r, i = i0 + c;
+        if (i < N && j < N && (ti != tj ? true : i < j)) dst[(size_t)j * N + i] = tr[r][c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_corr_finish(const double *part, int N, int nt, int tiles, int S,
+                                                     const double *ss, double *C) {
+    gram_emit(part, N, nt, tiles, S, C, [&](int i, int j, double g) {
+        if (i == j) return 1.0;
+        const double a = ss[i], b = ss[j];
+        if (a == 0.0 || b == 0.0) return 0.0;
+        return fmin(1.0, fmax(-1.0, g / sqrt(a * b)));
+    });
 }
 
 hipError_t launch_corr(const double *R, int N, int T, int64_t ld, const double *mu, const double *ss,
-                       double *C, hipStream_t s) {
-    const int nt = (N + kCT - 1) / kCT;
-    hipLaunchKernelGGL(k_corr, dim3(nt, nt), dim3(256), 0, s, R, N, T, ld, mu, ss, C);
+                       double *C, double *part, hipStream_t s) {
+    const int nt = (N + kGT - 1) / kGT, tiles = gram_tiles(N), S = gram_split(N, T);
+    hipLaunchKernelGGL(k_gram_mfma<true>, dim3(tiles * S), dim3(256), 0, s, R, N, T, ld, mu, nt, tiles, S, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_corr_finish, dim3(tiles), dim3(256), 0, s, part, N, nt, tiles, S, ss, C);
     return hipGetLastError();
 }
 
@@ -185,7 +329,7 @@ hipError_t launch_split(const double *C, int N, uint16_t *hi, uint16_t *lo, hipS
 //   prep : x_it = sqrt(w_t) (R_it - m_t), m_t the equal-weight market return
 //          (sum over i in ascending order, / N) or 0; one thread per t;
 //   gram : S_ij <- lambda^T S_ij + sum_t x_it x_jt on the 64 x 64 tiles of
-//          the upper triangle (same FP64 tile as the correlation), mirrored;
+//          the upper triangle (the MFMA Gram of the correlation), mirrored;
 //   norm : C_ij = S_ij / sqrt(S_ii S_jj), clamp, C_ii = 1, zero variance -> 0.
 __global__ __launch_bounds__(256) void k_ewma_prep(const double *R, int N, int T, int64_t ld, double lam,
                                                    int market, double *X) {
@@ -200,27 +344,11 @@ __global__ __launch_bounds__(256) void k_ewma_prep(const double *R, int N, int T
     for (int i = 0; i < N; ++i) X[(size_t)i * T + t] = sw * (R[(size_t)i * ld + t] - m);
 }
 
-__global__ __launch_bounds__(256) void k_ewma_gram(const double *X, int N, int T, double decay, int reset,
-                                                   double *S) {
-    const int ti = blockIdx.y, tj = blockIdx.x;
-    if (ti > tj) return;
-    const int i0 = ti * kCT, j0 = tj * kCT;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double acc[4][4];
-    gram_tile([&](int g, int t) { return X[(size_t)g * T + t]; }, N, T, i0, j0, acc);
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        const int i = i0 + 4 * ty + x;
-        if (i >= N) continue;
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            const int j = j0 + 4 * tx + y;
-            if (j >= N || j < i) continue;
-            const double v = reset ? acc[x][y] : fma(decay, S[(size_t)i * N + j], acc[x][y]);
-            S[(size_t)i * N + j] = v;
-            S[(size_t)j * N + i] = v;
-        }
-    }
+__global__ __launch_bounds__(256) void k_ewma_finish(const double *part, int N, int nt, int tiles, int S,
+                                                     double decay, int reset, double *Sm) {
+    gram_emit(part, N, nt, tiles, S, Sm, [&](int i, int j, double g) {
+        return reset ? g : fma(decay, Sm[(size_t)i * N + j], g);
+    });
 }
 
 __global__ __launch_bounds__(256) void k_ewma_norm(const double *S, int N, double *C, int32_t *status) {
@@ -241,12 +369,16 @@ __global__ __launch_bounds__(256) void k_ewma_norm(const double *S, int N, doubl
 }
 
 hipError_t launch_ewma(const double *R, int N, int T, int64_t ld, double lam, int reset, int market, double *S,
-                       double *C, double *X, int32_t *status, hipStream_t s) {
+                       double *C, double *X, double *part, int32_t *status, hipStream_t s) {
     hipLaunchKernelGGL(k_ewma_prep, dim3((T + 255) / 256), dim3(256), 0, s, R, N, T, ld, lam, market, X);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nt = (N + kCT - 1) / kCT;
-    hipLaunchKernelGGL(k_ewma_gram, dim3(nt, nt), dim3(256), 0, s, X, N, T, pow(lam, (double)T), reset, S);
+    const int nt = (N + kGT - 1) / kGT, tiles = gram_tiles(N), Sp = gram_split(N, T);
+    hipLaunchKernelGGL(k_gram_mfma<false>, dim3(tiles * Sp), dim3(256), 0, s, X, N, T, (int64_t)T, nullptr, nt,
+                       tiles, Sp, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ewma_finish, dim3(tiles), dim3(256), 0, s, part, N, nt, tiles, Sp, pow(lam, (double)T),
+                       reset, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t nn = (int64_t)N * N;
     hipLaunchKernelGGL(k_ewma_norm, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, S, N, C, status);

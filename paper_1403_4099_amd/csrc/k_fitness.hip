@@ -162,7 +162,9 @@ template <int B>
 __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int order) {
     __shared__ int4 lab_s[kFp64Waves][2][64][B / 4];
 
-    const int tile = order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int total = t.tiles[t.n_inst];                  // the grid may exceed it (capacity-sized graph)
+    if ((int)blockIdx.x >= total) return;
+    const int tile = order ? xcd_tile(blockIdx.x, total) : blockIdx.x;
     const int k = find_inst(t.tiles, t.n_inst, tile);
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;
@@ -323,23 +325,33 @@ constexpr int kFinCache = 8;                       // stocks per thread kept in 
 // LDS of the finish workgroup: csum (int64) [N], cnt (int32) [N], the label
 // lists (uint16, a quarter of N per wave), then per-wave reduction slots.
 // Arrays are padded to 16 bytes (64-bit LDS atomics need aligned addresses).
-__host__ __device__ __forceinline__ size_t finish_csum_bytes(int max_n) {
+__host__ __device__ constexpr size_t finish_csum_bytes(int max_n) {
     return ((size_t)max_n * sizeof(long long) + 15) / 16 * 16;
 }
-__host__ __device__ __forceinline__ size_t finish_cnt_bytes(int max_n) {
+__host__ __device__ constexpr size_t finish_cnt_bytes(int max_n) {
     return ((size_t)max_n * sizeof(int) + 15) / 16 * 16;
 }
-__host__ __device__ __forceinline__ int finish_quarter(int max_n) {
+__host__ __device__ constexpr int finish_quarter(int max_n) {
     return (max_n + kFinWaves - 1) / kFinWaves;
 }
-__host__ __device__ __forceinline__ size_t finish_lst_bytes(int max_n) {
+__host__ __device__ constexpr size_t finish_lst_bytes(int max_n) {
     return ((size_t)kFinWaves * finish_quarter(max_n) * sizeof(uint16_t) + 15) / 16 * 16;
 }
-__host__ __device__ __forceinline__ size_t finish_lds_bytes(int max_n) {
+__host__ __device__ constexpr size_t finish_lds_bytes(int max_n) {
     // 14.1 KB at N = 1024 (eight workgroups per CU), 57 KB at N = 4096
     return finish_csum_bytes(max_n) + finish_cnt_bytes(max_n) + finish_lst_bytes(max_n) +
            2 * kFinWaves * sizeof(double) + kFinWaves * sizeof(int);
 }
+// Every region of the layout starts 16-byte aligned for every N the library takes (a 64-bit LDS
+// atomic at a misaligned address through a generic pointer faults), and the whole fits in LDS.
+constexpr bool finish_layout_ok() {
+    for (int n = 1; n <= PGA_N_MAX; ++n) {
+        if (finish_csum_bytes(n) % 16 || finish_cnt_bytes(n) % 16 || finish_lst_bytes(n) % 16) return false;
+        if (finish_lds_bytes(n) > (size_t)kMaxLdsBytes) return false;
+    }
+    return true;
+}
+static_assert(finish_layout_ok(), "finish LDS layout: aligned regions within the LDS limit");
 
 // Per-label outputs and the log terms of Eq. 8 from n_s (cnt) and c_s held in
 // 64-bit fixed point (csum, scale 2^sc); thread 0 writes fitness[p]. Called by
@@ -425,6 +437,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
     const int g = blockIdx.x;
+    if (g >= t.inds[t.n_inst]) return;               // the grid may exceed the total (capacity-sized graph)
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;                     // uniform over the workgroup
@@ -561,18 +574,26 @@ hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_
 constexpr int kSparseMaxN = 2048;                  // larger instances always take the dense route
 constexpr int kSparseCache = kSparseMaxN / kFinThreads;   // stocks per thread, all in registers
 
-__host__ __device__ __forceinline__ size_t pad16(size_t b) { return (b + 15) / 16 * 16; }
-__host__ __device__ __forceinline__ size_t sparse_members_bytes(int n) {
+__host__ __device__ constexpr size_t pad16(size_t b) { return (b + 15) / 16 * 16; }
+__host__ __device__ constexpr size_t sparse_members_bytes(int n) {
     const size_t m = pad16(2 * (size_t)n), l = finish_lst_bytes(n);
     return m > l ? m : l;
 }
 // LDS: csum int64[n] | cnt int32[n] | begin int32[n + 1] | PP int32[n + 1] | members,
 // then the finish lists | kFinWaves x 2 doubles | 16 int32.
 // 22.7 KB at N = 1024 (seven workgroups per CU).
-__host__ __device__ __forceinline__ size_t sparse_lds_bytes(int n) {
+__host__ __device__ constexpr size_t sparse_lds_bytes(int n) {
     return pad16(8 * (size_t)n) + pad16(4 * (size_t)n) + 2 * pad16(4 * ((size_t)n + 1)) + sparse_members_bytes(n) +
            2 * kFinWaves * sizeof(double) + 16 * sizeof(int);
 }
+constexpr bool sparse_layout_ok() {
+    for (int n = 1; n <= kSparseMaxN; ++n) {
+        if (sparse_members_bytes(n) % 16) return false;
+        if (sparse_lds_bytes(n) > (size_t)kMaxLdsBytes) return false;
+    }
+    return true;
+}
+static_assert(sparse_layout_ok(), "cluster-pair LDS layout: aligned regions within the LDS limit");
 
 // Exclusive prefixes of n_s (begin) and of n_s (n_s - 1) / 2 (pp) over
 // [0, n), as block_exscan; returns the number of pairs and sets nmax to the
@@ -667,6 +688,7 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
     const int g = blockIdx.x;
+    if (g >= t.inds[t.n_inst]) return;               // the grid may exceed the total (capacity-sized graph)
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;                     // uniform over the workgroup
@@ -853,7 +875,7 @@ hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double
 // instance, blockIdx.y), and diag[N] = 1 if every C_jj is 1, else 0.
 __global__ __launch_bounds__(256) void k_diag(Tables t) {
     const InstDesc &d = t.desc[blockIdx.y];
-    if (!d.diag) return;                             // uniform
+    if (!d.diag || d.P == 0) return;                 // uniform
     int ones = 1;
     for (int j = threadIdx.x; j < d.N; j += 256) {
         const double c = gld(d.C + (size_t)j * d.N + j);

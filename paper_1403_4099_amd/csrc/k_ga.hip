@@ -19,6 +19,7 @@ namespace pga {
 // (i/4, p, gen0, INIT), N). One workgroup per individual.
 __global__ __launch_bounds__(256) void k_init(Tables t) {
     const int g = blockIdx.x;
+    if (g >= t.inds[t.n_inst]) return;                     // the grid may exceed the total (capacity-sized graph)
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
     const int N = d.N;
@@ -211,15 +212,23 @@ struct RankBlock {
 // Termination state after this generation's best b (thread 0 of the ranking
 // workgroup): improvement, stall count, stop flag; the generation about to be
 // bred is counted unless this is the final evaluation or the run stopped.
-__device__ void term_update(const InstDesc &d, pga_term_state st, double b, int final) {
-    const bool improved = isfinite(st.ref) ? (b > st.ref + d.tol * fmax(1.0, fabs(st.ref))) : isfinite(b);
-    if (improved) {
-        st.ref = b;
-        st.stall = 0;
-    } else {
-        st.stall += 1;
+// Algorithm 1 tests each generation once: the first evaluation of a call
+// (first != 0) re-evaluates the population a previous call tested last when
+// the state has already tested a generation (ref finite or stall > 0), and
+// then does not enter the test again, so a run split into several calls is
+// the same run as one call.
+__device__ void term_update(const InstDesc &d, pga_term_state st, double b, int final, int first) {
+    const bool retest = first && (isfinite(st.ref) || st.stall != 0);
+    if (!retest) {
+        const bool improved = isfinite(st.ref) ? (b > st.ref + d.tol * fmax(1.0, fabs(st.ref))) : isfinite(b);
+        if (improved) {
+            st.ref = b;
+            st.stall = 0;
+        } else {
+            st.stall += 1;
+        }
+        if (d.stall_gens > 0 && st.stall >= d.stall_gens) st.stopped = 1;
     }
-    if (d.stall_gens > 0 && st.stall >= d.stall_gens) st.stopped = 1;
     if (!final && !st.stopped) {
         st.gens += 1;
         st.call_gens += 1;
@@ -230,6 +239,7 @@ __device__ void term_update(const InstDesc &d, pga_term_state st, double b, int 
 __global__ __launch_bounds__(kRankThreads) void k_rank(Tables t, int gen_off, int final) {
     __shared__ RankLds sh;
     const InstDesc &d = t.desc[blockIdx.x];
+    if (d.P == 0) return;                                  // a padding slot of a capacity-sized launch
     const int P = d.P, E = d.E;
     // The fitness values, the stop flag and (thread 0) the termination state are
     // all requested before any of them is used.
@@ -253,7 +263,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank(Tables t, int gen_off, in
         if (r == 0) best = b;
         if (r < E && threadIdx.x == 0) d.elite[r] = b.i;
     });
-    if (d.term && threadIdx.x == 0) term_update(d, st, best.f, final);
+    if (d.term && threadIdx.x == 0) term_update(d, st, best.f, final, gen_off == 0);
     if (d.stats) rb.write_stats(d, gen_off, best);
 }
 
@@ -292,7 +302,7 @@ __device__ __forceinline__ int tournament2(const double *f, int a, int b) {
 __global__ __launch_bounds__(256) void k_sus_rank(Tables t) {
     __shared__ double fq[256];
     const InstDesc &d = t.desc[blockIdx.z];
-    if (d.selection != PGA_SELECT_SUS || inst_stopped(d)) return;
+    if (d.P == 0 || d.selection != PGA_SELECT_SUS || inst_stopped(d)) return;
     const int P = d.P;
     const int p0 = blockIdx.x * 256, q0 = blockIdx.y * 256;
     if (p0 >= P || q0 >= P) return;                          // uniform over the workgroup
@@ -318,7 +328,7 @@ __global__ __launch_bounds__(1024) void k_sus_prefix(Tables t) {
     __shared__ uint64_t wsum[16];
     __shared__ uint64_t carry_s;
     const InstDesc &d = t.desc[blockIdx.x];
-    if (d.selection != PGA_SELECT_SUS || inst_stopped(d)) return;
+    if (d.P == 0 || d.selection != PGA_SELECT_SUS || inst_stopped(d)) return;
     const int P = d.P;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int pass = 0; pass < 2; ++pass) {                   // pass 1 only if every weight was 0
@@ -398,6 +408,7 @@ __device__ int sus_pick(const InstDesc &d, uint32_t k, uint32_t n, uint64_t u, u
 // kernel before breed.
 __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off, int fold) {
     const int g = blockIdx.x;
+    if (g >= t.inds[t.n_inst]) return;                     // the grid may exceed the total (capacity-sized graph)
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;                           // set by this generation's rank
@@ -424,7 +435,7 @@ __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off
         if (c == 0) {
             if (d.term && threadIdx.x == 0) {
                 if (gen_off == 0) st.call_gens = 0;
-                term_update(d, st, best.f, 0);
+                term_update(d, st, best.f, 0, gen_off == 0);
             }
             if (d.stats) rb.write_stats(d, gen_off, best);
         }
@@ -497,6 +508,7 @@ hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int f
 // pop. Without a termination test every call breeds G generations.
 __global__ __launch_bounds__(256) void k_copy_back(Tables t, int G) {
     const int g = blockIdx.x;
+    if (g >= t.inds[t.n_inst]) return;                     // the grid may exceed the total (capacity-sized graph)
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
     const int bred = d.term ? gld(&d.term->call_gens) : G;

@@ -1,40 +1,48 @@
 // BF16x2 pair-sum on MFMA: v_pj = C_jj + 2 sum_{i<j} [s_pi = s_pj] (hi_ji + lo_ji),
-// the sum over i being the diagonal of a one-hot contraction (c_s is the
+// the sum over i read off the compacted one-hot contraction Z = C Y (c_s is the
 // diagonal of Y^T C Y, Eq. 6).
 //
-// One wave owns 16 stocks j = jt0 .. jt0+15 and walks the rows i < j in
-// chunks of 32 with v_mfma_f32_16x16x32_bf16:
-//   A[m][k] = 2^125 C[jt0 + m][i0 + k]       (hi, then lo: two MFMAs)
-//   B[k][n] = 2^-125 [s_{i0+k} = s_{jt0+n}] [i0 + k < jt0 + n]
-//   D[m][n] += sum_k A[m][k] B[k][n];  D[n][n] = partial sum for stock jt0+n
-// Lane l supplies row m = l%16 of A and column n = l%16 of B over the same
-// eight k = 8(l/16)..+7, so its A row and B column are both stock jt0 + l%16.
+// One wave owns 16 stocks j = jt0 .. jt0+15 and walks the rows i < j in chunks
+// of 32 with v_mfma_f32_16x16x32_bf16:
+//   A[m][k] = 2^125 C[jt0 + m][i0 + k]        (hi, then lo: two MFMAs)
+//   B[k][c] = 2^-125 [s^(b_c)_{i0 + k} = l_c]  (column c: individual b_c, label l_c)
+//   D[m][c] += sum_k A[m][k] B[k][c]
+// Compaction: the columns are not one per stock but one per distinct label
+// that the wave's 16 stocks carry in an individual and that at least one
+// other stock of that individual shares (n_s >= 2; a singleton's sum is 0),
+// packed over the workgroup's individuals into as few groups of 16 columns as
+// they need: a chunk issues ceil(sum_b K_b / 16) MFMA pairs instead of one per
+// individual (K_b: such labels of individual b in the wave's tile). Stock m of
+// individual b then reads its sum from D[m][column of (b, its label)]. The
+// label sets come from a bit mask per individual of the labels with n_s >= 2
+// (k_nsmask); individuals past P or evaluated by the cluster-pair kernel get
+// no columns.
+//
+// The triangle i < j is applied to A in the one chunk that reaches the
+// diagonal: A's row m is stock jt0 + m, and its element k is zeroed when row
+// i0 + k is not below that stock, once for all columns of the chunk.
 //
 // Label codes. A workgroup serves one block of 64 stocks, which carry at most
-// 64 distinct labels. Each such label gets a code (the block position of one
-// stock that has it, 0..63); a row whose label is not among them gets the
-// code kCodeNone. Codes are stored shifted into bits 8..15 of a 16-bit word,
-// so for a row word r and a column word c the saturating difference
-// 0x0100 - (r ^ c) is 0x0100 (the bf16 number 2^-125) when the labels are
-// equal and 0 otherwise: two packed 16-bit ALU ops build two B elements. The
-// 2^-125 is undone by keeping A as the split parts times 2^125 (a workspace
-// copy made once per call); every product is then exactly the split part, as
-// with a one-hot of 1.0.
+// 64 distinct labels per individual. Each such label gets a code (the block
+// position of one stock that has it, 0..63); a row whose label is not among
+// them gets the code kCodeNone. Codes are stored shifted into bits 8..15 of a
+// 16-bit word, so for a row word r and a column word c the saturating
+// difference 0x0100 - (r ^ c) is 0x0100 (the bf16 number 2^-125) when the
+// labels are equal and 0 otherwise: two packed 16-bit ALU ops build two B
+// elements. A column left unused in the last group gets the code kCodeFree,
+// which matches no row. The 2^-125 is undone by keeping A as the split parts
+// times 2^125 (a workspace copy made once per call); every product is then
+// exactly the split part, as with a one-hot of 1.0.
 //
-// The i < j mask is applied only in the chunk that reaches the diagonal. A is
-// loaded once per (wave, chunk), one chunk ahead, by direct global-to-LDS
-// loads into a two-slot ring per wave (no registers hold it in flight, so
-// nothing is copied from chunk to chunk), and reused by the B (4, 8 or 16)
-// individuals of the workgroup, whose row codes are staged in LDS 8192 / B
-// rows at a time. In a chunk the 16 lanes of a row group need the same 8 row
-// codes per individual; instead of 16 identical LDS reads, each lane reads
-// B/4 different dwords (two row codes each) and the xor takes its row operand
-// from the lane that holds it (DPP row broadcast), so a chunk costs one
-// B*64-byte LDS read per wave. FP32 accumulation is flushed into FP64 at
-// every 512-row boundary, so no FP32 partial sum spans more than 512 rows.
-// The 4- and 8-individual kernels are held to 128 registers (four waves per
-// SIMD): MFMA and VALU work of a SIMD serialise on this GPU, and the fourth
-// wave hides the latency between them.
+// A is loaded once per (wave, chunk), one chunk ahead, by direct
+// global-to-LDS loads into a two-slot ring per wave (no registers hold it in
+// flight), and reused by every column group. Row codes are staged in LDS per
+// individual, RC rows at a time; lane (n, g) of a column group reads the 8
+// codes of rows i0 + 8g .. +7 of its column's individual in one 16-byte read.
+// FP32 accumulation is flushed into FP64 at every 512-row boundary (no FP32
+// partial sum spans more than 512 rows): each group's 16 x 16 accumulator goes
+// through a wave-private LDS buffer, from which every lane takes the sums of
+// its stock for the individuals it keeps (b = g, g + 4, ...).
 #include "pga_internal.hpp"
 
 #include <type_traits>
@@ -49,6 +57,7 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 constexpr int kCodeShift = 8;
 constexpr uint16_t kOneHot = 0x0100;        // bf16 2^-125
 constexpr uint8_t kCodeNone = 0xFF;         // row label not present in the column block
+constexpr uint32_t kCodeFree = 0xFE;        // column of a group left unused: matches no row
 
 __device__ __forceinline__ uint32_t onehot2(uint32_t rows2, uint32_t col2) {
     const u16x2 x = __builtin_bit_cast(u16x2, rows2 ^ col2);
@@ -56,43 +65,78 @@ __device__ __forceinline__ uint32_t onehot2(uint32_t rows2, uint32_t col2) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(one, x));
 }
 
-// Row codes in the xor of lane t of a row group come from lane T of that
-// group (DPP row broadcast; T a compile-time constant).
-template <int T>
-__device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + T, 0xF, 0xF, false);
-}
-
 template <int... I, typename F>
 __device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &&f) {
     (f(std::integral_constant<int, I>{}), ...);
 }
 
-// Position of individual b's dword within a staged row pair: lane t of a row
-// group reads positions (B/4)(t/4) .. +B/4-1, i.e. individuals t/4, t/4 + 4, ...
-template <int B>
-__host__ __device__ constexpr int mfma_pos(int b) {
-    return (B / 4) * (b & 3) + (b >> 2);
+// ---- labels with n_s >= 2 ------------------------------------------------------
+// Bit l of word l / 32 of row p of d.ns2 is set when label l is held by at
+// least two stocks of individual p (one workgroup per individual: an LDS
+// histogram, then one ballot per 64 labels). Individuals evaluated by the
+// cluster-pair kernel are skipped (their rows are not read). Labels outside
+// [0, N) are not counted; such an individual gets -inf in the finish.
+__global__ __launch_bounds__(256) void k_nsmask(Tables t, int parity) {
+    extern __shared__ int ns_cnt[];
+    const int gi = blockIdx.x;
+    if (gi >= t.inds[t.n_inst]) return;
+    const int k = find_inst(t.inds, t.n_inst, gi);
+    const InstDesc &d = t.desc[k];
+    if (!d.ns2 || inst_stopped(d)) return;                    // uniform
+    const int p = gi - t.inds[k];
+    if (d.route && gld(d.route + p) == 0) return;
+    const int N = d.N;
+    const int32_t *lab = d.pop[parity] + (size_t)p * N;
+    for (int s = threadIdx.x; s < N; s += 256) ns_cnt[s] = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += 256) {
+        const int l = gld(lab + j);
+        if ((unsigned)l < (unsigned)N) atomicAdd(&ns_cnt[l], 1);
+    }
+    __syncthreads();
+    const int ldm = (N + 31) >> 5;
+    uint32_t *out = d.ns2 + (size_t)p * ldm;
+    for (int l0 = 64 * (threadIdx.x >> 6); l0 < N; l0 += 256) {
+        const int l = l0 + (threadIdx.x & 63);
+        const unsigned long long m = __ballot(l < N && ns_cnt[l] >= 2);
+        if ((threadIdx.x & 63) == 0) {
+            gst(out + (l0 >> 5), (uint32_t)m);
+            if ((l0 >> 5) + 1 < ldm) gst(out + (l0 >> 5) + 1, (uint32_t)(m >> 32));
+        }
+    }
 }
 
-// LDS of one workgroup (dynamic): row codes, kMfmaRowCodes 16-bit words (the
-// code shifted into bits 8..15), as dwords [row pair][mfma_pos(b)] holding the
-// rows 2q (low half) and 2q + 1 of individual b; then the label -> code
-// tables [B][cstride] (bytes, cstride >= N); then each wave's ring of
-// kMfmaASlots A slots, 2 KB each (the 16 x 32 hi tile, then the lo tile, in
-// lane order), filled by direct global-to-LDS loads one chunk ahead.
+hipError_t launch_nsmask(Tables t, int total_inds, int max_n, int parity, hipStream_t s) {
+    if (total_inds <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nsmask, dim3(total_inds), dim3(256), sizeof(int) * (size_t)max_n, s, t, parity);
+    return hipGetLastError();
+}
+
+// LDS of one workgroup (dynamic): row codes [B][RS] (16-bit words, the code
+// shifted into bits 8..15; RS = RC + 8), the label -> code tables [B][cstride]
+// (bytes, cstride >= N), each wave's ring of kMfmaASlots A slots (2 KB each:
+// the 16 x 32 hi tile, then the lo tile, in lane order) filled by direct
+// global-to-LDS loads one chunk ahead, and 1 KB per wave for the column table
+// and the flushes.
 struct MfmaLds {
-    uint32_t *rows;
+    uint16_t *rows;
     uint8_t *code;
     unsigned char *aring;
+    uint32_t *scratch;
     int cstride;
 };
+
+__device__ __forceinline__ uint32_t shfl_xor32(uint32_t v, int m) {
+    return (uint32_t)__shfl_xor((int)v, m, 64);
+}
 
 // One column block jb (64 stocks, 16 per wave) for the B individuals of batch pb.
 // On entry every code table entry below N holds kCodeNone; it is restored on exit.
 template <int B>
 __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, int parity, const MfmaLds &s) {
-    constexpr int RC = kMfmaRowCodes / B;                     // rows staged per pass
+    constexpr int RC = mfma_rows(B);                          // rows staged per pass
+    constexpr int RS = mfma_row_stride(B);
+    constexpr int BU = B / 4;                                 // individuals a lane keeps: g, g + 4, ...
     const int N = d.N, P = d.P, ld = d.ld_h;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, kept scalar
     const int lane = threadIdx.x & 63;
@@ -106,46 +150,113 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
     const uint16_t *__restrict__ ls = d.ls;
     auto code = [&](int b, int l) -> uint8_t & { return s.code[(size_t)b * s.cstride + l]; };
 
+    // Individuals of the batch evaluated here (uniform): inside P and not taken
+    // by the cluster-pair kernel.
+    bool live[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int p = pbase + b;
+        live[b] = p < P && !(d.route && gld(d.route + p) == 0);
+    }
     // Column labels; lanes with g == 0 register them in the code table. Stock,
     // individual and label are clamped into range as in the staging below: a
-    // column past N or an individual past P is not stored, and a clamped
-    // duplicate only writes a consistent code (the position of some stock with
-    // that label) into its own individual's table.
+    // column past N or an individual that is not live gets no column, and a
+    // clamped duplicate only writes a consistent code (the position of some
+    // stock with that label) into its own individual's table.
     const uint32_t lmax = (uint32_t)(N - 1);
     const int jc = min(j, N - 1);
     uint32_t lj[B];
 #pragma unroll
     for (int b = 0; b < B; ++b)
         lj[b] = min((uint32_t)gld(labels + (size_t)min(pbase + b, P - 1) * N + jc), lmax);
+    const int ldm = (N + 31) >> 5;
+    uint32_t nsw[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) nsw[b] = gld(d.ns2 + (size_t)min(pbase + b, P - 1) * ldm + (lj[b] >> 5));
     if (g == 0) {
 #pragma unroll
         for (int b = 0; b < B; ++b) code(b, (int)lj[b]) = (uint8_t)q;
     }
     __syncthreads();
-    uint32_t col2[B];
+
+    // Columns of this wave: per individual, the set of codes of the labels that
+    // its 16 stocks here carry with n_s >= 2 (a 64-bit set, OR over the 16
+    // lanes of a row group; the four row groups hold the same stocks), numbered
+    // individual by individual in ascending code order. slot: this lane's
+    // column per individual (-1 for none); nq column groups of 16 in all.
+    uint32_t cc[B];
+    int slot[B];
+    int S = 0;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const uint32_t c = code(b, (int)lj[b]);
-        col2[b] = (c << kCodeShift) | (c << (16 + kCodeShift));
+        cc[b] = code(b, (int)lj[b]);
+        const bool ns = live[b] && j < N && ((nsw[b] >> (lj[b] & 31)) & 1u);
+        uint32_t lo = (ns && cc[b] < 32) ? (1u << cc[b]) : 0u;
+        uint32_t hi = (ns && cc[b] >= 32) ? (1u << (cc[b] - 32)) : 0u;
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1) {
+            lo |= shfl_xor32(lo, m);
+            hi |= shfl_xor32(hi, m);
+        }
+        const uint64_t M = ((uint64_t)hi << 32) | lo;
+        slot[b] = ns ? S + __popcll(M & ((1ull << cc[b]) - 1ull)) : -1;
+        S += __popcll(M);
     }
+    const int nq = __builtin_amdgcn_readfirstlane((S + 15) >> 4);
+    const int nq2 = (nq + 1) & ~1;                            // groups run in pairs
+    // Column table in this wave's scratch: entry c = (individual << 8) | code,
+    // kCodeFree where unused; lane n of group t takes entry 16 t + n.
+    uint32_t *tbl = s.scratch + 256 * wave;
+    for (int e = lane; e < 16 * B; e += 64) tbl[e] = kCodeFree;
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+        if (slot[b] >= 0) tbl[slot[b]] = ((uint32_t)b << 8) | cc[b];
+    __syncthreads();
+    uint32_t col2[B], rofs[B];
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        const uint32_t e = tbl[16 * t + n];
+        const uint32_t c = e & 0xFFu;
+        col2[t] = (c << kCodeShift) | (c << (16 + kCodeShift));
+        rofs[t] = (e >> 8) * (uint32_t)RS + 8u * (uint32_t)g;   // this lane's 8 rows of that individual
+    }
+    // the slots of the individuals this lane keeps (b = g + 4 u)
+    int myslot[BU];
+    bool mylive[BU];
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+        const int b0 = 4 * u;
+        myslot[u] = g == 0 ? slot[b0] : g == 1 ? slot[b0 + 1] : g == 2 ? slot[b0 + 2] : slot[b0 + 3];
+        mylive[u] = g == 0 ? live[b0] : g == 1 ? live[b0 + 1] : g == 2 ? live[b0 + 2] : live[b0 + 3];
+    }
+    __syncthreads();                                          // the table is read before any flush reuses it
 
     floatx4 acc[B];
-    double acc64[B];
+    double acc64[BU];
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
-        acc64[b] = 0.0;
-    }
-    const int dreg = n & 3;                                   // lane holds D[n][n] in register n & 3 ...
-    const bool diag_lane = (n >> 2) == g;                     // ... when its 4-row group contains row n
+    for (int t = 0; t < B; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < BU; ++u) acc64[u] = 0.0;
 
+    // Flush: each group's D (this lane: rows 4g .. 4g + 3 of column n) goes to the
+    // wave's scratch column-major, and each lane adds D[n][its column] of every
+    // individual it keeps whose column lies in that group. LDS operations of one
+    // wave complete in order, so a group's reads precede the next group's writes.
+    float *fb = (float *)(s.scratch + 256 * wave);
     auto flush = [&]() {
+        static_for(std::make_integer_sequence<int, B>{}, [&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            if (t < nq2) {
+                *(floatx4 *)(fb + 16 * n + 4 * g) = acc[t];
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const float v = dreg == 0 ? acc[b][0] : dreg == 1 ? acc[b][1] : dreg == 2 ? acc[b][2] : acc[b][3];
-            acc64[b] += (double)v;
-            acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
+                for (int u = 0; u < BU; ++u) {
+                    const int c = myslot[u] - 16 * t;
+                    if (c >= 0 && c < 16) acc64[u] += (double)fb[16 * c + n];
+                }
+                acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+        });
     };
     // Only waves with jt0 < N load A, and then j < ld for every lane (ld is a
     // multiple of 32 and jt0 a multiple of 16), so the loads need no guard. The
@@ -169,75 +280,61 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         ah = *(const uint4 *)(sl + 16 * lane);
         al = *(const uint4 *)(sl + 1024 + 16 * lane);
     };
-    // Lane t of row group g reads, into R[k], rows i0 + 8g + 2(t%4), +1 of individual 4k + t/4.
-    auto read_r = [&](int i0, int c0, uint32_t (&R)[B / 4]) {
-        const uint32_t *rp = s.rows + (size_t)(((i0 - c0) >> 1) + 4 * g + (n & 3)) * B + (B / 4) * (n >> 2);
-        if constexpr (B == 4) {
-            R[0] = *rp;
-        } else if constexpr (B == 8) {
-            const uint2 q2 = *(const uint2 *)rp;
-            R[0] = q2.x;
-            R[1] = q2.y;
-        } else {
-            const uint4 q4 = *(const uint4 *)rp;
-            R[0] = q4.x;
-            R[1] = q4.y;
-            R[2] = q4.z;
-            R[3] = q4.w;
-        }
+    // B column of group t: the 8 row codes of this lane's rows of the column's
+    // individual against the column's code.
+    auto bcol = [&](const uint16_t *rb, int t) -> bf16x8 {
+        const uint4 r = *(const uint4 *)(rb + rofs[t]);
+        uint4 v;
+        v.x = onehot2(r.x, col2[t]);
+        v.y = onehot2(r.y, col2[t]);
+        v.z = onehot2(r.z, col2[t]);
+        v.w = onehot2(r.w, col2[t]);
+        return __builtin_bit_cast(bf16x8, v);
     };
-    auto chunk = [&](auto masked_tag, int i0, int c0, uint4 ah, uint4 al, const uint32_t (&R)[B / 4]) {
+    auto chunk = [&](auto masked_tag, int i0, int c0, uint4 ah, uint4 al) {
         constexpr bool masked = decltype(masked_tag)::value;
-        const int ik = i0 + 8 * g;                            // first of this lane's 8 rows
-        uint32_t m[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-        if constexpr (masked) {
+        if constexpr (masked) {                               // A row n is stock j: keep rows i < j
+            const int ik = i0 + 8 * g;                        // first of this lane's 8 rows
+            uint32_t m[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 m[r] = ((ik + 2 * r < j) ? 0xFFFFu : 0u) | ((ik + 2 * r + 1 < j) ? 0xFFFF0000u : 0u);
+            ah.x &= m[0]; ah.y &= m[1]; ah.z &= m[2]; ah.w &= m[3];
+            al.x &= m[0]; al.y &= m[1]; al.z &= m[2]; al.w &= m[3];
         }
         const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah);
         const bf16x8 Al = __builtin_bit_cast(bf16x8, al);
-        // B column of individual b: its dword e (rows ik + 2e, +1) is in R[b/4] of lane 4(b%4) + e.
-        auto bcol = [&](auto bc) -> bf16x8 {
-            constexpr int b = decltype(bc)::value;
-            constexpr int t = 4 * (b & 3);
-            uint4 v;
-            v.x = onehot2(row_bcast<t + 0>(R[b >> 2]), col2[b]);
-            v.y = onehot2(row_bcast<t + 1>(R[b >> 2]), col2[b]);
-            v.z = onehot2(row_bcast<t + 2>(R[b >> 2]), col2[b]);
-            v.w = onehot2(row_bcast<t + 3>(R[b >> 2]), col2[b]);
-            if constexpr (masked) {
-                v.x &= m[0]; v.y &= m[1]; v.z &= m[2]; v.w &= m[3];
+        const uint16_t *rb = s.rows + (i0 - c0);
+        // groups in pairs (the hi and lo MFMAs of one group depend on each other;
+        // the other group's fill the gap); an odd last group is paired with
+        // free columns, whose sums are 0
+        static_for(std::make_integer_sequence<int, B / 2>{}, [&](auto hc) {
+            constexpr int t = 2 * decltype(hc)::value;
+            if (t < nq) {                                     // uniform
+                const bf16x8 B0 = bcol(rb, t);
+                const bf16x8 B1 = bcol(rb, t + 1);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B0, acc[t], 0, 0, 0);
+                acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B1, acc[t + 1], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B0, acc[t], 0, 0, 0);
+                acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B1, acc[t + 1], 0, 0, 0);
             }
-            return __builtin_bit_cast(bf16x8, v);
-        };
-        static_for(std::make_integer_sequence<int, B / 2>{}, [&](auto hb) {
-            constexpr int b = 2 * decltype(hb)::value;
-            const bf16x8 B0 = bcol(std::integral_constant<int, b>{});
-            const bf16x8 B1 = bcol(std::integral_constant<int, b + 1>{});
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B0, acc[b], 0, 0, 0);
-            acc[b + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B1, acc[b + 1], 0, 0, 0);
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B0, acc[b], 0, 0, 0);
-            acc[b + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B1, acc[b + 1], 0, 0, 0);
         });
         if (((i0 + 32) % kMfmaFlushRows) == 0) flush();
     };
-    // Chunks [i0, end) of one kind. A chunk first reads its A and row codes from
-    // LDS (its A was loaded during the previous chunk), then starts the load of
-    // the next chunk's A into the other slot, then computes.
+    // Chunks [i0, end) of one kind. A chunk first reads its A from LDS (loaded
+    // during the previous chunk), then starts the load of the next chunk's A
+    // into the other slot, then computes.
     auto run = [&](auto masked_tag, int &i0, int end, int cend, int c0) {
         for (; i0 < end; i0 += 32) {
             uint4 ah, al;
             read_a(i0, c0, ah, al);
-            uint32_t R[B / 4];
-            read_r(i0, c0, R);
             if (i0 + 32 < cend) load_a(i0 + 32, c0);
-            chunk(masked_tag, i0, c0, ah, al, R);
+            chunk(masked_tag, i0, c0, ah, al);
         }
     };
 
     const int wg_iend = min(jb * kMfmaCols + kMfmaCols, N);   // rows any wave of the group needs
-    const int my_iend = jt0 < N ? min(jt0 + 16, N) : 0;       // rows this wave needs (i < j <= jt0+15)
+    const int my_iend = (jt0 < N && nq > 0) ? min(jt0 + 16, N) : 0;   // rows this wave needs (i < j <= jt0+15)
     const int i_diag = (jt0 / 32) * 32;                       // first chunk that may hold i >= j
 
     for (int c0 = 0; c0 < wg_iend; c0 += RC) {
@@ -245,14 +342,14 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         const int rows32 = (rows + 31) & ~31;                 // chunks read whole 32-row groups
         // Thread t stages row pairs t + 256k of every individual: all 2 * PK * B
         // labels are loaded before the first table lookup, so the pass costs one
-        // memory latency; each row pair is written as B consecutive dwords.
+        // memory latency; each row pair of an individual is one dword.
         // Nothing here needs a validity test, only in-bounds addresses: rows past
         // the pass (only past N, in its last 32-row chunk) meet zero-padded A;
-        // individuals past P are not stored; a label outside [0, N) makes the
-        // finish kernel give its individual -inf whatever its sums. So row and
-        // individual indices are clamped into range, and labels to N - 1.
+        // individuals that are not live have no column; a label outside [0, N)
+        // makes the finish kernel give its individual -inf whatever its sums. So
+        // row and individual indices are clamped into range, and labels to N - 1.
         constexpr int PK = RC / 512;
-        const uint32_t rlast = (uint32_t)(rows - 1), lmax = (uint32_t)(N - 1);
+        const uint32_t rlast = (uint32_t)(rows - 1);
         uint32_t lab[PK][2][B];
 #pragma unroll
         for (int k = 0; k < PK; ++k) {
@@ -273,15 +370,12 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
                 for (int b = 0; b < B; ++b) lab[k][h][b] = code(b, (int)min(lab[k][h][b], lmax));
 #pragma unroll
         for (int k = 0; k < PK; ++k) {
-            const int q = threadIdx.x + 256 * k;
-            if (2 * q < rows32) {
-                uint32_t w[B];
+            const int qd = threadIdx.x + 256 * k;
+            if (2 * qd < rows32) {
 #pragma unroll
-                for (int b = 0; b < B; ++b)                       // code of row 2q in bits 8..15, of 2q+1 in 24..31
-                    w[mfma_pos<B>(b)] = __builtin_amdgcn_perm(lab[k][1][b], lab[k][0][b], 0x040C000Cu);
-#pragma unroll
-                for (int v = 0; v < B / 4; ++v)
-                    *(uint4 *)(s.rows + (size_t)q * B + 4 * v) = uint4{w[4 * v], w[4 * v + 1], w[4 * v + 2], w[4 * v + 3]};
+                for (int b = 0; b < B; ++b)                   // code of row 2qd in bits 8..15, of 2qd+1 in 24..31
+                    *(uint32_t *)(s.rows + (size_t)b * RS + 2 * qd) =
+                        (lab[k][0][b] << kCodeShift) | (lab[k][1][b] << (16 + kCodeShift));
             }
         }
         __syncthreads();
@@ -296,12 +390,12 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
         __syncthreads();
     }
     flush();
-    if (diag_lane && j < N) {
+    if (j < N) {
         const double cjj = gld(d.C + (size_t)j * N + j);
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int p = pbase + b;
-            if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[b], cjj));
+        for (int u = 0; u < BU; ++u) {
+            const int p = pbase + g + 4 * u;
+            if (mylive[u]) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[u], cjj));
         }
     }
     // Restore the table (every reader passed the barrier that closes the row loop).
@@ -317,7 +411,9 @@ template <int B>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(B == 16 ? 2 : 4))) void k_pairsum_mfma(Tables t, int parity,
                                                                                      int order, int cstride) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const int tile = order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int total = t.tiles[t.n_inst];                  // the grid may exceed it (capacity-sized graph)
+    if ((int)blockIdx.x >= total) return;
+    const int tile = order ? xcd_tile(blockIdx.x, total) : blockIdx.x;
     const int k = find_inst(t.tiles, t.n_inst, tile);
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;                              // uniform over the workgroup
@@ -333,8 +429,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(B == 16 ? 2
             if (pb * B + b < d.P) any |= gld(d.route + pb * B + b);
         if (!any) return;
     }
-    const MfmaLds s{(uint32_t *)lds, lds + sizeof(uint16_t) * kMfmaRowCodes,
-                    lds + sizeof(uint16_t) * kMfmaRowCodes + (size_t)B * cstride, cstride};
+    const MfmaLds s{(uint16_t *)lds, lds + mfma_lds_code_off(B), lds + mfma_lds_ring_off(B, cstride),
+                    (uint32_t *)(lds + mfma_lds_scratch_off(B, cstride)), cstride};
     {
         const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
 #pragma unroll
@@ -382,6 +478,7 @@ __device__ __forceinline__ uint32_t scale2(uint32_t w) {
 
 __global__ __launch_bounds__(256) void k_scale_split(Tables t) {
     const InstDesc &d = t.desc[blockIdx.y];
+    if (d.P == 0) return;                                     // a padding slot of a capacity-sized launch
     const size_t n8 = (size_t)d.ld_h * d.ld_h / 8;            // ld is a multiple of 32
     const size_t ld = (size_t)d.ld_h;
     for (size_t v = (size_t)blockIdx.x * 256 + threadIdx.x; v < n8; v += (size_t)gridDim.x * 256) {

@@ -9,6 +9,7 @@
 #include "pga_internal.hpp"
 
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -69,7 +70,7 @@ struct TimedLaunch {
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_tl;
-constexpr int kTimers = 11;
+constexpr int kTimers = 12;
 double g_tsum[kTimers] = {0};
 int64_t g_tcnt[kTimers] = {0};
 
@@ -147,10 +148,12 @@ int pick_variant(int form, int max_n, int total_p) {
 // [InstDesc x n][prefix tiles n+1][prefix inds n+1]
 // then per instance: [wsum P x N doubles][elite PGA_E_MAX int32]
 // and, for the BF16x2 form, [hi * 2^125 ld x ld][lo * 2^125 ld x ld] (bf16),
-// and, for SUS selection, [rank P int32][weight prefix P uint64].
+// and, for SUS selection, [rank P int32][weight prefix P uint64],
+// then [route P int32][diagonal N + 1 doubles],
+// and, for the BF16x2 form, [labels with n_s >= 2: P x ceil(N / 32) uint32].
 struct Layout {
     size_t desc_off, pre_off, inst_off;
-    std::vector<size_t> wsum_off, elite_off, hs_off, ls_off, rank_off, cum_off, route_off, diag_off;
+    std::vector<size_t> wsum_off, elite_off, hs_off, ls_off, rank_off, cum_off, route_off, diag_off, ns2_off;
     size_t total;
 };
 
@@ -180,6 +183,9 @@ Layout make_layout(const int32_t *Ns, const int32_t *Ps, int n, int form, const 
         off = align_up(off + sizeof(int32_t) * (size_t)Ps[k], 256);
         L.diag_off.push_back(off);
         off = align_up(off + sizeof(double) * ((size_t)Ns[k] + 1), 256);
+        L.ns2_off.push_back(off);
+        off = align_up(off + (form == PGA_FORM_BF16X2 ? sizeof(uint32_t) * (size_t)Ps[k] * (((size_t)Ns[k] + 31) / 32)
+                                                      : 0), 256);
     }
     L.total = off;
     return L;
@@ -193,6 +199,22 @@ Tables tables_at(void *ws, const Layout &L, int n) {
     t.inds = t.tiles + (n + 1);
     t.n_inst = n;
     return t;
+}
+
+// ---- launch sizes of pga_evolve ------------------------------------------------------
+// Counts and totals are rounded up to one of four values per octave (x -> the next
+// multiple of 2^(floor(log2 x) - 2)), and the instance list is padded with empty
+// descriptors (P = 0) to the rounded count: every kernel reads the real totals from
+// the device-side prefix tables and skips the workgroups past them, so a captured
+// graph serves every mix of instances whose sizes round to the same values (the
+// admissions and retirements of a serving loop), with at most a quarter of a launch
+// as padding.
+int bucket(int x) {
+    if (x <= 4) return x;
+    int e = 0;
+    while ((x >> (e + 1)) != 0) ++e;             // floor(log2 x)
+    const int u = 1 << (e - 2);
+    return (x + u - 1) / u * u;
 }
 
 // ---- the schedule ----------------------------------------------------------------
@@ -211,10 +233,13 @@ hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, i
         (e = timed(10, s, [&] { return launch_sparse(t, sh.inds, sh.max_n, parity, sh.frac, status, s); })) !=
             hipSuccess)
         return e;
-    if (form == PGA_FORM_FP64)
+    if (form == PGA_FORM_FP64) {
         e = timed(0, s, [&] { return launch_pairsum_fp64(t, sh.tiles, parity, sh.v, s); });
-    else
+    } else {
+        if ((e = timed(11, s, [&] { return launch_nsmask(t, sh.inds, sh.max_n, parity, s); })) != hipSuccess)
+            return e;
         e = timed(1, s, [&] { return launch_pairsum_mfma(t, sh.tiles, parity, sh.v, sh.max_n, s); });
+    }
     if (e != hipSuccess) return e;
     return timed(2, s, [&] { return launch_finish(t, sh.inds, sh.max_n, parity, status, s); });
 }
@@ -254,19 +279,29 @@ struct GraphKey {
     }
 };
 
+struct CachedGraph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+constexpr int kMaxGraphs = 32;                       // captured graphs kept per context (least recently used go)
+
 struct pga_ctx {
     hipStream_t cap = nullptr;
     void *staging = nullptr;
     size_t staging_bytes = 0;
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
-    std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    uint64_t launches = 0;
+    std::map<GraphKey, CachedGraph> graphs;
 };
 
 // Measured-ceiling kernel (k_peaks.hip), outside the method's kernels.
 namespace pga {
 hipError_t launch_peak_mfma(float *out, int n_workgroups, int iters, hipStream_t s);
 double peak_mfma_flops(int n_workgroups, int iters);
+hipError_t launch_peak_fp64(double *out, int n_workgroups, int iters, hipStream_t s);
+double peak_fp64_flops(int n_workgroups, int iters);
 }  // namespace pga
 
 extern "C" {
@@ -288,8 +323,8 @@ int pga_ctx_create(pga_ctx **out) {
 int pga_ctx_destroy(pga_ctx *c) {
     if (!c) return PGA_ERR_ARG;
     for (auto &kv : c->graphs) {
-        hipGraphExecDestroy(kv.second.second);
-        hipGraphDestroy(kv.second.first);
+        hipGraphExecDestroy(kv.second.exec);
+        hipGraphDestroy(kv.second.graph);
     }
     if (c->upload_pending) hipEventSynchronize(c->upload_done);
     if (c->staging) hipHostFree(c->staging);
@@ -297,6 +332,11 @@ int pga_ctx_destroy(pga_ctx *c) {
     if (c->cap) hipStreamDestroy(c->cap);
     delete c;
     return PGA_OK;
+}
+
+int pga_ctx_graphs(pga_ctx *c) {
+    if (!c) return PGA_ERR_ARG;
+    return (int)c->graphs.size();
 }
 
 const char *pga_strerror(int code) {
@@ -321,8 +361,8 @@ extern "C" {
 int32_t pga_split_ld(int32_t N) { return N < 1 ? 0 : split_ld(N); }
 
 size_t pga_correlate_ws_bytes(int32_t N) {
-    if (N < 1) return 0;
-    return align_up(sizeof(double) * 2 * (size_t)N, 256);
+    if (N < 1 || N > PGA_N_MAX) return 0;
+    return align_up(sizeof(double) * 2 * (size_t)N, 256) + sizeof(double) * gram_ws_doubles(N);
 }
 
 int pga_correlate(const double *R, int32_t N, int32_t T, int64_t ld_r, double *C, uint16_t *C_hi,
@@ -333,10 +373,11 @@ int pga_correlate(const double *R, int32_t N, int32_t T, int64_t ld_r, double *C
     if (!ws || ws_bytes < pga_correlate_ws_bytes(N)) return PGA_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     double *mu = (double *)ws, *ss = mu + N;
+    double *part = (double *)((char *)ws + align_up(sizeof(double) * 2 * (size_t)N, 256));
     HIP_TRY(timed(5, s, [&] {
         hipError_t e = launch_row_stats(R, N, T, ld_r, mu, ss, status, s);
         if (e != hipSuccess) return e;
-        return launch_corr(R, N, T, ld_r, mu, ss, C, s);
+        return launch_corr(R, N, T, ld_r, mu, ss, C, part, s);
     }));
     if (C_hi) HIP_TRY(timed(6, s, [&] { return launch_split(C, N, C_hi, C_lo, s); }));
     return PGA_OK;
@@ -352,8 +393,8 @@ int pga_split(const double *C, int32_t N, uint16_t *C_hi, uint16_t *C_lo, void *
 
 // ---- online EWMA correlation -------------------------------------------------------------
 size_t pga_ewma_ws_bytes(int32_t N, int32_t T) {
-    if (N < 1 || T < 1) return 0;
-    return align_up(sizeof(double) * (size_t)N * (size_t)T, 256);
+    if (N < 1 || T < 1 || N > PGA_N_MAX) return 0;
+    return align_up(sizeof(double) * (size_t)N * (size_t)T, 256) + sizeof(double) * gram_ws_doubles(N);
 }
 
 int pga_ewma(const double *R, int32_t N, int32_t T, int32_t ld_r, double lambda, int32_t flags, double *S,
@@ -363,12 +404,13 @@ int pga_ewma(const double *R, int32_t N, int32_t T, int32_t ld_r, double lambda,
     if (!(lambda >= 0.0 && lambda < 1.0)) return PGA_ERR_ARG;
     if ((C_hi == nullptr) != (C_lo == nullptr)) return PGA_ERR_ARG;
     if (flags & ~(PGA_EWMA_RESET | PGA_EWMA_MARKET)) return PGA_ERR_ARG;
-    if (C_hi && N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
+    if (N > PGA_N_MAX) return PGA_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < pga_ewma_ws_bytes(N, T)) return PGA_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
+    double *part = (double *)((char *)ws + align_up(sizeof(double) * (size_t)N * (size_t)T, 256));
     HIP_TRY(timed(9, s, [&] {
         return launch_ewma(R, N, T, ld_r, lambda, (flags & PGA_EWMA_RESET) ? 1 : 0,
-                           (flags & PGA_EWMA_MARKET) ? 1 : 0, S, C, (double *)ws, status, s);
+                           (flags & PGA_EWMA_MARKET) ? 1 : 0, S, C, (double *)ws, part, status, s);
     }));
     if (C_hi) HIP_TRY(timed(6, s, [&] { return launch_split(C, N, C_hi, C_lo, s); }));
     return PGA_OK;
@@ -413,6 +455,7 @@ int prepare_single(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, 
     if (form == PGA_FORM_BF16X2) {
         d.hs = (uint16_t *)((char *)ws + L.hs_off[0]);
         d.ls = (uint16_t *)((char *)ws + L.ls_off[0]);
+        d.ns2 = (uint32_t *)((char *)ws + L.ns2_off[0]);
     }
     d.n_s_out = n_s;
     d.c_s_out = c_s;
@@ -502,6 +545,49 @@ int pga_tune_set(int32_t form, int32_t N, int32_t P, int32_t variant) {
     if (variant < 0) g_tune.erase(tune_key(form, N, P));
     else g_tune[tune_key(form, N, P)] = variant;
     return PGA_OK;
+}
+
+// Tuning table file: one line per entry, "form n64 log2p variant" (n64 = ceil(N / 64),
+// log2p = ceil(log2 P), the table's own key), '#' starts a comment line.
+int pga_tune_save(const char *path) {
+    if (!path) return PGA_ERR_ARG;
+    std::map<std::tuple<int, int, int>, int> copy;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        copy = g_tune;
+    }
+    FILE *f = fopen(path, "w");
+    if (!f) return PGA_ERR_ARG;
+    fprintf(f, "# libpga pair-sum variants: form ceil(N/64) ceil(log2 P) variant\n");
+    for (const auto &kv : copy)
+        fprintf(f, "%d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
+    const int bad = ferror(f);
+    if (fclose(f) != 0 || bad) return PGA_ERR_ARG;
+    return (int)copy.size();
+}
+
+int pga_tune_load(const char *path) {
+    if (!path) return PGA_ERR_ARG;
+    FILE *f = fopen(path, "r");
+    if (!f) return PGA_ERR_ARG;
+    std::map<std::tuple<int, int, int>, int> read;
+    char line[256];
+    int rc = PGA_OK;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int form, nb, pb, v;
+        if (sscanf(line, "%d %d %d %d", &form, &nb, &pb, &v) != 4 || n_variants(form) == 0 || nb < 1 ||
+            nb > (PGA_N_MAX + 63) / 64 || pb < 0 || pb > 31 || v < 0 || v >= n_variants(form)) {
+            rc = PGA_ERR_ARG;                         // the whole file is rejected
+            break;
+        }
+        read[std::make_tuple(form, nb, pb)] = v;
+    }
+    fclose(f);
+    if (rc != PGA_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : read) g_tune[kv.first] = kv.second;
+    return (int)read.size();
 }
 
 size_t pga_tune_ws_bytes(int32_t N, int32_t P, int32_t form) {
@@ -606,13 +692,14 @@ static int check_instances(const pga_instance *inst, int32_t n, int32_t form) {
 
 size_t pga_evolve_ws_bytes(const pga_instance *inst, int32_t n_inst, int32_t form) {
     if (check_instances(inst, n_inst, form) != PGA_OK) return 0;
-    std::vector<int32_t> Ns(n_inst), Ps(n_inst), Ss(n_inst);
+    const int nb = bucket(n_inst);
+    std::vector<int32_t> Ns(nb, 0), Ps(nb, 0), Ss(nb, 0);
     for (int k = 0; k < n_inst; ++k) {
         Ns[k] = inst[k].N;
         Ps[k] = inst[k].P;
         Ss[k] = inst[k].prm.selection;
     }
-    return make_layout(Ns.data(), Ps.data(), n_inst, form, Ss.data()).total;
+    return make_layout(Ns.data(), Ps.data(), nb, form, Ss.data()).total;
 }
 
 int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t generations,
@@ -621,13 +708,14 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
     if (form != PGA_FORM_FP64 && form != PGA_FORM_BF16X2) return PGA_ERR_ARG;
     int rc = check_instances(inst, n_inst, form);
     if (rc != PGA_OK) return rc;
-    std::vector<int32_t> Ns(n_inst), Ps(n_inst), Ss(n_inst);
+    const int nb = bucket(n_inst);                   // descriptor slots: the instances, then padding
+    std::vector<int32_t> Ns(nb, 0), Ps(nb, 0), Ss(nb, 0);
     for (int k = 0; k < n_inst; ++k) {
         Ns[k] = inst[k].N;
         Ps[k] = inst[k].P;
         Ss[k] = inst[k].prm.selection;
     }
-    const Layout L = make_layout(Ns.data(), Ps.data(), n_inst, form, Ss.data());
+    const Layout L = make_layout(Ns.data(), Ps.data(), nb, form, Ss.data());
     if (!ws || ws_bytes < L.total) return PGA_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
 
@@ -647,9 +735,9 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
     char *hb = (char *)ctx->staging;
     InstDesc *hd = (InstDesc *)(hb + L.desc_off);
     int32_t *pf = (int32_t *)(hb + L.pre_off);
-    int32_t *pi = pf + (n_inst + 1);
+    int32_t *pi = pf + (nb + 1);
     pf[0] = pi[0] = 0;
-    Shape sh{n_inst, 0, 0, 0, Variant{form, 0, 0}, 0, 0, 0, route_frac()};
+    Shape sh{nb, 0, 0, 0, Variant{form, 0, 0}, 0, 0, 0, route_frac()};
     int total_p = 0;
     for (int k = 0; k < n_inst; ++k) {
         sh.max_n = std::max(sh.max_n, (int)inst[k].N);
@@ -658,6 +746,8 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         sh.stop |= inst[k].prm.stall_gens > 0 ? 1 : 0;
         total_p += inst[k].P;
     }
+    sh.max_n = bucket(sh.max_n);
+    sh.max_p = bucket(sh.max_p);
     sh.v = variant_at(form, pick_variant(form, sh.max_n, total_p));
     for (int k = 0; k < n_inst; ++k) {
         const pga_instance &I = inst[k];
@@ -678,6 +768,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         if (form == PGA_FORM_BF16X2) {
             d.hs = (uint16_t *)((char *)ws + L.hs_off[k]);
             d.ls = (uint16_t *)((char *)ws + L.ls_off[k]);
+            d.ns2 = (uint32_t *)((char *)ws + L.ns2_off[k]);
         }
         d.p_cross = I.prm.p_cross_thr;
         d.p_mut = I.prm.p_mut_thr;
@@ -701,13 +792,18 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         pf[k + 1] = pf[k] + pair_tiles(I.N, I.P, sh.v);
         pi[k + 1] = pi[k] + I.P;
     }
-    sh.tiles = pf[n_inst];
-    sh.inds = pi[n_inst];
+    for (int k = n_inst; k < nb; ++k) {              // padding slots: no individuals, no tiles
+        hd[k] = InstDesc{};
+        pf[k + 1] = pf[k];
+        pi[k + 1] = pi[k];
+    }
+    sh.tiles = bucket(pf[nb]);                       // launch sizes; the kernels stop at the real totals
+    sh.inds = bucket(pi[nb]);
     HIP_TRY(hipMemcpyAsync(ws, ctx->staging, head, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(ctx->upload_done, s));
     ctx->upload_pending = true;
 
-    Tables t = tables_at(ws, L, n_inst);
+    Tables t = tables_at(ws, L, nb);
     if (form == PGA_FORM_BF16X2) HIP_TRY(launch_scale_split(t, split_ld(sh.max_n), s));
     if (sh.frac > 0.0) HIP_TRY(launch_diag(t, sh.max_n, s));
     if (flags & PGA_EVOLVE_INIT) HIP_TRY(timed(7, s, [&] { return launch_init(t, sh.inds, s); }));
@@ -717,10 +813,19 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         HIP_TRY(run_generations(t, sh, form, generations, status, s));
         return PGA_OK;
     }
-    GraphKey key{ws, status, n_inst, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.order,
+    GraphKey key{ws, status, nb, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.order,
                  sh.max_p, sh.sus, sh.stop, sh.frac};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
+        // bounded cache: drop the least recently launched graph
+        if ((int)ctx->graphs.size() >= kMaxGraphs) {
+            auto old = ctx->graphs.begin();
+            for (auto g = ctx->graphs.begin(); g != ctx->graphs.end(); ++g)
+                if (g->second.last_use < old->second.last_use) old = g;
+            hipGraphExecDestroy(old->second.exec);
+            hipGraphDestroy(old->second.graph);
+            ctx->graphs.erase(old);
+        }
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
@@ -737,9 +842,10 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
             g_last_hip = (int)e;
             return PGA_ERR_HIP;
         }
-        it = ctx->graphs.emplace(key, std::make_pair(g, ge)).first;
+        it = ctx->graphs.emplace(key, CachedGraph{g, ge, 0}).first;
     }
-    HIP_TRY(hipGraphLaunch(it->second.second, s));
+    it->second.last_use = ++ctx->launches;
+    HIP_TRY(hipGraphLaunch(it->second.exec, s));
     return PGA_OK;
 }
 
@@ -824,6 +930,13 @@ int pga_peak_mfma_bf16(float *out, int32_t n_workgroups, int32_t iters, double *
     if (!out || n_workgroups < 1 || iters < 1) return PGA_ERR_ARG;
     if (flops) *flops = pga::peak_mfma_flops(n_workgroups, iters);
     HIP_TRY(pga::launch_peak_mfma(out, n_workgroups, iters, (hipStream_t)stream));
+    return PGA_OK;
+}
+
+int pga_peak_fp64(double *out, int32_t n_workgroups, int32_t iters, double *flops, void *stream) {
+    if (!out || n_workgroups < 1 || iters < 1) return PGA_ERR_ARG;
+    if (flops) *flops = pga::peak_fp64_flops(n_workgroups, iters);
+    HIP_TRY(pga::launch_peak_fp64(out, n_workgroups, iters, (hipStream_t)stream));
     return PGA_OK;
 }
 

@@ -38,6 +38,7 @@ struct InstDesc {
     int32_t *route;             // P: 1 = evaluated by pair-sum + finish, 0 = by the cluster-pair
                                 // kernel (workspace); null: every individual takes the pair-sum
     double *diag;               // N + 1: C_jj, contiguous, then 1 if every C_jj is 1 (workspace; with route)
+    uint32_t *ns2;              // P x ceil(N / 32): bit l set when label l has n_s >= 2 (workspace; BF16x2 form)
 };
 
 // Prefix tables: for n instances, arrays of n + 1 exclusive prefix sums.
@@ -53,7 +54,6 @@ constexpr int kFp64Waves = 4;                      // waves per workgroup, one c
 constexpr int kFp64Cols = 64;                      // columns per workgroup
 constexpr int kMfmaWaves = 4;                      // waves per workgroup, 16 columns each
 constexpr int kMfmaCols = 16 * kMfmaWaves;         // columns per workgroup
-constexpr int kMfmaRowCodes = 8192;                // row codes staged in LDS per workgroup (all individuals)
 constexpr int kMfmaFlushRows = 512;                // FP32 accumulators are flushed to FP64 every 512 rows
 constexpr int kMaxLdsBytes = 65536;                // LDS a workgroup may allocate
 
@@ -83,10 +83,26 @@ inline int32_t pair_tiles(int32_t N, int32_t P, const Variant &v) {
 }
 inline size_t mfma_code_stride(int max_n) { return ((size_t)max_n + 15) / 16 * 16; }
 constexpr int kMfmaASlots = 2;                     // A ring slots per wave (2 KB each) in the MFMA kernel
-inline size_t mfma_lds_bytes(int ipg, int max_n) {
-    return sizeof(uint16_t) * kMfmaRowCodes + (size_t)ipg * mfma_code_stride(max_n) +
-           (size_t)kMfmaWaves * kMfmaASlots * 2048;
+// Rows of row codes staged per pass and individual (a multiple of 512), and the
+// per-individual stride of the staged codes in 16-bit words (16 bytes of padding).
+__host__ __device__ constexpr int mfma_rows(int ipg) { return 4096 / ipg > 512 ? 4096 / ipg : 512; }
+__host__ __device__ constexpr int mfma_row_stride(int ipg) { return mfma_rows(ipg) + 8; }
+// LDS of the MFMA kernel: row codes, label -> code tables, A rings, 1 KB per wave of scratch.
+__host__ __device__ constexpr size_t mfma_align256(size_t x) { return (x + 255) / 256 * 256; }
+__host__ __device__ constexpr size_t mfma_lds_code_off(int ipg) {
+    return mfma_align256(sizeof(uint16_t) * (size_t)ipg * mfma_row_stride(ipg));
 }
+__host__ __device__ constexpr size_t mfma_lds_ring_off(int ipg, int cstride) {
+    return mfma_lds_code_off(ipg) + mfma_align256((size_t)ipg * cstride);
+}
+__host__ __device__ constexpr size_t mfma_lds_scratch_off(int ipg, int cstride) {
+    return mfma_lds_ring_off(ipg, cstride) + (size_t)kMfmaWaves * kMfmaASlots * 2048;
+}
+inline size_t mfma_lds_bytes(int ipg, int max_n) {
+    return mfma_lds_scratch_off(ipg, (int)mfma_code_stride(max_n)) + (size_t)kMfmaWaves * 1024;
+}
+static_assert(mfma_lds_code_off(4) % 256 == 0 && mfma_lds_code_off(8) % 256 == 0 && mfma_lds_code_off(16) % 256 == 0,
+              "MFMA LDS regions are 256-byte aligned");
 inline bool variant_ok(const Variant &v, int max_n) {
     return v.form != PGA_FORM_BF16X2 || mfma_lds_bytes(v.ipg, max_n) <= (size_t)kMaxLdsBytes;
 }
@@ -182,16 +198,18 @@ __device__ __forceinline__ bool ranks_before(double fa, int a, double fb, int b)
 hipError_t launch_row_stats(const double *R, int N, int T, int64_t ld, double *mu, double *ss,
                             int32_t *status, hipStream_t s);
 hipError_t launch_corr(const double *R, int N, int T, int64_t ld, const double *mu, const double *ss,
-                       double *C, hipStream_t s);
+                       double *C, double *part, hipStream_t s);
+size_t gram_ws_doubles(int N);      // partial Gram tiles of the FP64 MFMA Gram (correlation, EWMA)
 hipError_t launch_split(const double *C, int N, uint16_t *hi, uint16_t *lo, hipStream_t s);
 hipError_t launch_ewma(const double *R, int N, int T, int64_t ld, double lam, int reset, int market, double *S,
-                       double *C, double *X, int32_t *status, hipStream_t s);
+                       double *C, double *X, double *part, int32_t *status, hipStream_t s);
 
 hipError_t launch_write_desc(const InstDesc &d, int32_t tiles, InstDesc *dst, int32_t *prefix2, hipStream_t s);
 hipError_t launch_pairsum_fp64(Tables t, int total_tiles, int parity, const Variant &v, hipStream_t s);
 hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Variant &v, int max_n,
                                hipStream_t s);
 hipError_t launch_scale_split(Tables t, int max_ld, hipStream_t s);
+hipError_t launch_nsmask(Tables t, int total_inds, int max_n, int parity, hipStream_t s);
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status, hipStream_t s);
 hipError_t launch_diag(Tables t, int max_n, hipStream_t s);
 hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int32_t *status,

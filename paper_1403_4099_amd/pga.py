@@ -31,17 +31,17 @@ EVOLVE_INIT = 1
 EVOLVE_EAGER = 2
 P_CROSS_DEFAULT = int(0.9 * 2**32)
 KERNELS = {"pairsum_fp64": 0, "pairsum_mfma": 1, "finish": 2, "rank": 3, "breed": 4,
-           "correlate": 5, "split": 6, "init": 7, "sus": 8, "ewma": 9, "cluster_pairs": 10}
+           "correlate": 5, "split": 6, "init": 7, "sus": 8, "ewma": 9, "cluster_pairs": 10, "nsmask": 11}
 EWMA_RESET, EWMA_MARKET = 1, 2
 
 SYMBOLS = [
-    "pga_ctx_create", "pga_ctx_destroy", "pga_strerror", "pga_last_hip_error",
+    "pga_ctx_create", "pga_ctx_destroy", "pga_ctx_graphs", "pga_strerror", "pga_last_hip_error",
     "pga_correlate_ws_bytes", "pga_correlate", "pga_split_ld", "pga_split",
     "pga_fitness_ws_bytes", "pga_fitness", "pga_evolve_ws_bytes", "pga_evolve",
     "pga_best_ws_bytes", "pga_best", "pga_timing_enable", "pga_timing_reset", "pga_timing_read",
     "pga_variant_count", "pga_variant_info", "pga_tune_ws_bytes", "pga_tune", "pga_tune_set",
-    "pga_tune_get", "pga_ewma_ws_bytes", "pga_ewma", "pga_peak_mfma_bf16", "pga_route_set",
-    "pga_route_get", "pga_fitness_noalloc", "pga_fitness_noalloc_max_bytes",
+    "pga_tune_get", "pga_tune_save", "pga_tune_load", "pga_ewma_ws_bytes", "pga_ewma", "pga_peak_mfma_bf16", "pga_route_set",
+    "pga_route_get", "pga_fitness_noalloc", "pga_fitness_noalloc_max_bytes", "pga_peak_fp64",
 ]
 
 
@@ -83,6 +83,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "pga_ctx_create": ([ct.POINTER(vp)], ct.c_int),
         "pga_ctx_destroy": ([vp], ct.c_int),
+        "pga_ctx_graphs": ([vp], ct.c_int),
         "pga_strerror": ([ct.c_int], ct.c_char_p),
         "pga_last_hip_error": ([], ct.c_int),
         "pga_correlate_ws_bytes": ([i32], sz),
@@ -105,9 +106,12 @@ def load(path: str = LIB_PATH):
                      ct.c_int),
         "pga_tune_set": ([i32, i32, i32, i32], ct.c_int),
         "pga_tune_get": ([i32, i32, i32], ct.c_int),
+        "pga_tune_save": ([ct.c_char_p], ct.c_int),
+        "pga_tune_load": ([ct.c_char_p], ct.c_int),
         "pga_ewma_ws_bytes": ([i32, i32], sz),
         "pga_ewma": ([vp, i32, i32, i32, ct.c_double, i32, vp, vp, vp, vp, vp, vp, sz, vp], ct.c_int),
         "pga_peak_mfma_bf16": ([vp, i32, i32, ct.POINTER(ct.c_double), vp], ct.c_int),
+        "pga_peak_fp64": ([vp, i32, i32, ct.POINTER(ct.c_double), vp], ct.c_int),
         "pga_route_set": ([ct.c_double], ct.c_int),
         "pga_route_get": ([], ct.c_double),
         "pga_fitness_noalloc": ([vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp], ct.c_int),
@@ -331,6 +335,22 @@ def tune_set(form: str, N: int, P: int, variant: int):
     _check(load().pga_tune_set(FORMS[form], N, P, variant), "pga_tune_set")
 
 
+def tune_save(path: str) -> int:
+    """Write the tuning table to a text file; returns the number of entries."""
+    n = load().pga_tune_save(os.fsencode(path))
+    if n < 0:
+        _check(n, "pga_tune_save")
+    return n
+
+
+def tune_load(path: str) -> int:
+    """Add the entries of a tuning-table file; returns their number."""
+    n = load().pga_tune_load(os.fsencode(path))
+    if n < 0:
+        _check(n, "pga_tune_load")
+    return n
+
+
 def tune_get(form: str, N: int, P: int) -> int:
     v = load().pga_tune_get(FORMS[form], N, P)
     if v < 0:
@@ -410,6 +430,13 @@ class Context:
         self.h = h
         self.ws = None
 
+    def graphs(self) -> int:
+        """Captured graphs held by the context."""
+        n = load().pga_ctx_graphs(self.h)
+        if n < 0:
+            _check(n, "pga_ctx_graphs")
+        return n
+
     def close(self):
         if self.h:
             load().pga_ctx_destroy(self.h)
@@ -472,6 +499,26 @@ def peak_mfma_bf16(n_workgroups: int = 4096, iters: int = 1000, reps: int = 5) -
         best = min(best, e0.elapsed_time(e1) * 1e-3)
     if not bool(torch.isfinite(out).all()):
         raise PgaError("pga_peak_mfma_bf16: non-finite sink values")
+    return flops.value / best / 1e12
+
+
+def peak_fp64(n_workgroups: int = 4096, iters: int = 2000, reps: int = 5) -> float:
+    """Sustained FP64 vector FMA throughput in TFLOP/s (best of `reps` timed launches of the
+    library's register-operand FMA loop on the current stream)."""
+    out = torch.empty(4 * n_workgroups, dtype=torch.float64, device="cuda")
+    flops = ct.c_double()
+    L = load()
+    _check(L.pga_peak_fp64(_ptr(out), n_workgroups, iters, ct.byref(flops), _stream()), "pga_peak_fp64")
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _check(L.pga_peak_fp64(_ptr(out), n_workgroups, iters, None, _stream()), "pga_peak_fp64")
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    if not bool(torch.isfinite(out).all()):
+        raise PgaError("pga_peak_fp64: non-finite sink values")
     return flops.value / best / 1e12
 
 

@@ -9,7 +9,12 @@ re-clustering does not restart from random labelings.
 Scheduling (host side; every computation is a libpga kernel):
   * arrivals are admitted FIFO when the universe has no request in flight
     and the HBM footprint of the new request fits the budget (otherwise they
-    wait; a request whose footprint alone exceeds the budget is rejected);
+    wait; a request whose footprint alone exceeds the budget is rejected).
+    The budget counts the in-flight requests' transient buffers and every
+    resident population (P x N int32 per universe, kept between windows);
+    when an arrival does not fit, resident populations of idle universes are
+    evicted, least recently used first, and such a universe's next window
+    starts from a fresh initial population;
   * admitted requests get their correlation matrix (pga_correlate), then all
     requests in flight advance together by `chunk` generations in ONE
     pga_evolve call over the ragged set of instances (different N);
@@ -58,12 +63,18 @@ class Result:
         return self.done - self.arrival
 
 
+def resident_bytes(N: int, P: int) -> int:
+    """HBM bytes of a universe's resident population (P x N int32), kept between windows."""
+    return 4 * P * N
+
+
 def footprint_bytes(N: int, P: int, split_ld: int, form: str) -> int:
-    """HBM bytes one in-flight request holds: C, BF16 split, two populations, fitness,
-    stats, and its share of the evolve workspace (pair sums P x N FP64, elites, descriptor,
-    and for the BF16x2 form the scaled split copies)."""
+    """HBM bytes one in-flight request holds besides its universe's resident population: C,
+    BF16 split, the population's ping-pong partner, fitness, stats, and its share of the evolve
+    workspace (pair sums P x N FP64, elites, descriptor, and for the BF16x2 form the scaled
+    split copies)."""
     b = 8 * N * N + 8 * P + 8 * N * P + 4096
-    b += 2 * 4 * P * N                      # population + ping-pong partner
+    b += 4 * P * N                          # ping-pong partner of the population
     if form == "bf16x2":
         b += 2 * 2 * split_ld * split_ld    # hi, lo
         b += 2 * 2 * split_ld * split_ld    # their scaled workspace copies
@@ -90,6 +101,7 @@ class Scheduler:
        engine.finish(inst) -> (labels, fitness)
        engine.resident(universe) -> population tensor or None
        engine.keep(universe, inst) -> keeps the final population resident
+       engine.evict(universe) -> drops a resident population
     """
 
     def __init__(self, engine, P: int = 1024, generations: int = 100, chunk: int = 10,
@@ -106,7 +118,9 @@ class Scheduler:
         self.flights: list[_Flight] = []
         self.busy: set[int] = set()
         self.gen_of: dict[int, int] = collections.defaultdict(int)
-        self.used = 0
+        self.used = 0                       # in-flight transient bytes + resident populations
+        self.resident: collections.OrderedDict[int, int] = collections.OrderedDict()   # universe -> bytes (LRU)
+        self.evictions = 0
         self.results: list[Result] = []
         self.rejected: list[Request] = []
         self.t0 = None
@@ -116,22 +130,38 @@ class Scheduler:
     def now(self) -> float:
         return self.clock() - self.t0
 
+    def _make_room(self, need: int, keep: int) -> bool:
+        """Evict idle residents (least recently used first, never `keep`) until `need` more
+        bytes fit; True if they do."""
+        for u in list(self.resident):
+            if self.used + need <= self.budget:
+                break
+            if u == keep or u in self.busy:
+                continue
+            self.used -= self.resident.pop(u)
+            self.engine.evict(u)
+            self.evictions += 1
+        return self.used + need <= self.budget
+
     def _admit(self):
         kept = collections.deque()
         while self.pending:
             r = self.pending.popleft()
             need = footprint_bytes(r.N, self.P, self.split_ld(r.N), self.form)
-            if need > self.budget:
+            res = 0 if r.universe in self.resident else resident_bytes(r.N, self.P)
+            if need + resident_bytes(r.N, self.P) > self.budget:
                 self.rejected.append(r)
                 continue
-            if r.universe in self.busy or self.used + need > self.budget:
+            if r.universe in self.busy or not self._make_room(need + res, r.universe):
                 kept.append(r)
                 continue
             gen0 = self.gen_of[r.universe]
             inst, C, hi, lo = self.engine.start(r, gen0, self.engine.resident(r.universe))
             self.flights.append(_Flight(r, inst, C, hi, lo, self.G, self.now(), need))
             self.busy.add(r.universe)
-            self.used += need
+            self.used += need + res
+            self.resident[r.universe] = resident_bytes(r.N, self.P)
+            self.resident.move_to_end(r.universe)
         self.pending = kept
         self.max_inflight = max(self.max_inflight, len(self.flights))
 
@@ -191,6 +221,7 @@ class Scheduler:
             "requests_per_s": len(self.results) / span if span > 0 else 0.0,
             "max_in_flight": self.max_inflight,
             "chunks": self.chunks_run,
+            "evictions": self.evictions,
         }
 
 
@@ -198,7 +229,7 @@ class GpuEngine:
     """libpga-backed engine: correlation, warm-started ragged evolve, best."""
 
     def __init__(self, P: int = 1024, form: str = "fp64", elites: int = 2, seed: int = 0,
-                 eager: bool = True, stall_gens: int = 0, tol: float = 1e-5):
+                 eager: bool = False, stall_gens: int = 0, tol: float = 1e-5):
         import torch
 
         from . import pga
@@ -208,6 +239,9 @@ class GpuEngine:
         self.eager = eager
         self.stall_gens, self.tol = stall_gens, tol
         self.ctx = pga.Context()
+        # one workspace for every mix of requests (grown only if a mix needs more), so the
+        # graphs captured for the chunk launches stay valid from one mix to the next
+        self.ctx.ws = torch.empty(128 << 20, dtype=torch.uint8, device="cuda")
         self.pops: dict[int, object] = {}
         self.status = pga.new_status()
 
@@ -250,3 +284,6 @@ class GpuEngine:
 
     def keep(self, universe, inst):
         self.pops[universe] = inst.pop
+
+    def evict(self, universe):
+        self.pops.pop(universe, None)

@@ -80,3 +80,35 @@ def l_bound_from_cs(ns, cs, dcs):
     n2 = n * n
     fp = np.abs(-1.0 / c + (n - 1.0) / np.where(m, n2 - c, 1.0))
     return 0.5 * np.sum(np.where(m, fp * dcs, 0.0), axis=1) * 1.01 + 1e-13
+
+
+def pair_counts(pop, N):
+    """Within-cluster pairs sum_s n_s (n_s - 1) / 2 of every labeling (host-side count)."""
+    return np.array([int((lambda n: (n * (n - 1) // 2).sum())(np.bincount(r, minlength=N).astype(np.int64)))
+                     for r in pop])
+
+
+def route_limit(frac, N):
+    """Largest pair count the cluster-pair route takes at limit `frac` (N <= 2048)."""
+    return int(np.floor(frac * 0.5 * N * (N - 1)))
+
+
+def check_bf16x2_fitness(C, hi_bits, lo_bits, pop, f_gpu, frac):
+    """BF16x2 fitness of labelings `pop` against the oracle, per the route each one takes:
+    an individual within the cluster-pair limit is exact FP64 (oracle on C, 1e-9 M); the others
+    contract hi + lo with FP32 sums (oracle on hi + lo, rigorous FP32 accumulation bound).
+    Returns the largest |dL| / M against the FP64 oracle on C (the split's own error)."""
+    N = C.shape[0]
+    f_o, mag = O.fitness(C, pop, want_mag=True)
+    on_route = (pair_counts(pop, N) <= route_limit(frac, N)) if (frac > 0 and N <= 2048) else \
+        np.zeros(len(pop), dtype=bool)
+    if on_route.any():
+        d = np.abs(f_gpu[on_route] - f_o[on_route])
+        assert np.all(d <= fitness_tol(mag[on_route])), float(np.max(d / np.maximum(mag[on_route], 1e-300)))
+    dense = ~on_route
+    if dense.any():
+        Ce = bf16_emulated(C, hi_bits, lo_bits)
+        f_e, ns_e, cs_e = O.fitness(Ce, pop[dense], want_ns=True, want_cs=True)
+        bnd = cs_bound_fp32(Ce, pop[dense])
+        assert np.all(np.abs(f_gpu[dense] - f_e) <= l_bound_from_cs(ns_e, cs_e, bnd))
+    return float(np.max(np.abs(f_gpu - f_o) / np.maximum(mag, 1e-300)))

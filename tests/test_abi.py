@@ -97,6 +97,8 @@ def test_host_side_argument_errors(lib):
     assert lib.pga_fitness_ws_bytes(2048, 4096, 0) > lib.pga_fitness_noalloc_max_bytes()
     assert lib.pga_fitness_noalloc(fake, None, None, 2048, fake, 4096, 0, fake, None, None, None, None) == -4
     assert lib.pga_fitness_ws_bytes(1024, 4096, 1) <= lib.pga_fitness_noalloc_max_bytes() == 40 << 20
+    # graph count of a null context
+    assert lib.pga_ctx_graphs(None) == -1
     # best: P < 1
     assert lib.pga_best(fake, fake, 0, 4, None, None, None, wsp, 1 << 16, None) == -1
 
@@ -164,3 +166,30 @@ def test_route_limit_is_host_state_with_checked_range(lib):
         assert pga.route_get() == 1.0
     finally:
         pga.route_set(prev)
+
+
+def test_tuning_table_persists_to_a_file(lib, tmp_path):
+    """The tuning table round-trips through its text file; a malformed file is rejected whole."""
+    f = tmp_path / "tune.txt"
+    try:
+        assert pga.tune_get("bf16x2", 300, 512) == 0
+        pga.tune_set("bf16x2", 300, 512, 4)
+        pga.tune_set("fp64", 1024, 4096, 1)
+        n = pga.tune_save(str(f))
+        assert n >= 2
+        text = f.read_text()
+        assert "1 5 9 4" in text and "0 16 12 1" in text          # form ceil(N/64) ceil(log2 P) variant
+        pga.tune_set("bf16x2", 300, 512, -1)
+        pga.tune_set("fp64", 1024, 4096, -1)
+        assert pga.tune_get("bf16x2", 300, 512) == 0
+        assert pga.tune_load(str(f)) == n
+        assert pga.tune_get("bf16x2", 300, 512) == 4 and pga.tune_get("fp64", 1000, 3000) == 1
+        bad = tmp_path / "bad.txt"
+        bad.write_text("1 5 9 2\n1 5 9 99\n")                    # variant out of range
+        pga.tune_set("bf16x2", 300, 512, -1)
+        assert lib.pga_tune_load(str(bad).encode()) == -1
+        assert pga.tune_get("bf16x2", 300, 512) == 0                # nothing of it applied
+        assert lib.pga_tune_load(str(tmp_path / "missing.txt").encode()) == -1
+    finally:
+        pga.tune_set("bf16x2", 300, 512, -1)
+        pga.tune_set("fp64", 1024, 4096, -1)

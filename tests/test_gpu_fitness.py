@@ -136,7 +136,9 @@ def test_fitness_is_deterministic():
 
 
 # ---------------------------------------------------------------- correlation and split
-CORR_CASES = [(1, 5), (2, 3), (18, 500), (70, 300), (100, 2000), (257, 130)]
+CORR_CASES = [(1, 5), (2, 3), (18, 500), (70, 300), (100, 2000), (257, 130),
+              # slices of the Gram's t range: several per tile, ragged last chunks, one slice
+              (64, 390), (1024, 390), (130, 17), (513, 700), (4096, 40)]
 
 
 @pytest.mark.parametrize("N,T", CORR_CASES, ids=[f"N{n}-T{t}" for n, t in CORR_CASES])
@@ -156,14 +158,28 @@ def test_correlate_matches_oracle(N, T):
     assert np.array_equal(st.cpu().numpy(), st_o)
 
 
+def test_correlate_strided_rows():
+    """Rows of R with a leading dimension larger than T (a window of a longer series)."""
+    say("correlate strided rows")
+    rng = np.random.default_rng(5)
+    full = rng.standard_normal((300, 1000))
+    R = full[:, 100:777]
+    C_o = O.correlate(R)
+    Rg = _g(full)[:, 100:777]
+    assert Rg.stride(0) == 1000
+    C_g = pga.correlate(Rg).cpu().numpy()
+    assert np.max(np.abs(C_g - C_o)) <= 1e-12
+
+
 def test_correlate_config3_shape_and_split():
     say("correlate config-3 shape")
     w = synth.config3(T=1024)
     C_o = O.correlate(w.R)
-    C_g, hi, lo = pga.correlate(_g(w.R), split=True)
+    C_g, _, _ = pga.correlate(_g(w.R), split=True)
     C_g = C_g.cpu().numpy()
     assert np.max(np.abs(C_g - C_o)) <= 1e-12
-    hi_o, lo_o = O.split_bf16(C_g)           # split of the same FP64 values, bit for bit
+    hi, lo = pga.split(_g(C_o))              # the split of the oracle's matrix, bit for bit
+    hi_o, lo_o = O.split_bf16(C_o)
     N = w.N
     h = hi.cpu().numpy().view(np.uint16)
     l = lo.cpu().numpy().view(np.uint16)

@@ -182,3 +182,27 @@ def test_best_with_ties_and_invalid():
     pop = _g(np.array([[0, 0, 0], [2, 1, 2], [0, 1, 2], [1, 1, 1]], dtype=np.int32))
     lab, fb, idx = pga.best(f, pop)
     assert idx == 1 and fb == 3.0 and list(lab) == [0, 1, 0]
+
+
+def test_capacity_sized_graph_serves_mixes_that_round_alike():
+    """pga_evolve rounds its launch sizes up (four values per octave) and pads the instance list:
+    a mix whose sizes round to the same values replays the cached graph, padding workgroups and
+    slots do nothing, and every result equals its eager run bit for bit."""
+    say("capacity-sized graph reuse")
+    G = 3
+    mixes = [[(70, 64, 0), (130, 40, 1), (33, 10, 2)],       # 114 individuals -> launch size 128
+             [(71, 64, 3), (129, 40, 4), (35, 12, 5)]]       # 116 individuals -> 128 as well
+    ctx = pga.Context()
+    ctx.ws = torch.empty(64 << 20, dtype=torch.uint8, device=DEV)   # one workspace: one graph key
+    for form in ("fp64", "bf16x2"):
+        for mix in mixes:
+            Cs = [corr(N, seed=iid)[0] for N, P, iid in mix]
+            eager = [_inst(C, P, G, form=form, seed=9, instance_id=iid) for C, (N, P, iid) in zip(Cs, mix)]
+            pga.Context().evolve(eager, G, form=form, init=True, eager=True)
+            graph = [_inst(C, P, G, form=form, seed=9, instance_id=iid) for C, (N, P, iid) in zip(Cs, mix)]
+            ctx.evolve(graph, G, form=form, init=True)
+            torch.cuda.synchronize()
+            for a, b in zip(eager, graph):
+                assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness)
+                assert torch.equal(a.stats, b.stats)
+        assert ctx.graphs() == (1 if form == "fp64" else 2)

@@ -1,8 +1,9 @@
 """CPU tests of the continuous-batching scheduler's host logic with a fake engine
-(admission by HBM budget, one request per universe in flight, FIFO, retirement)."""
+(admission by HBM budget with resident populations counted, eviction of idle residents,
+one request per universe in flight, FIFO, retirement)."""
 import numpy as np
 
-from paper_1403_4099_amd.serve import Request, Scheduler, footprint_bytes
+from paper_1403_4099_amd.serve import Request, Scheduler, footprint_bytes, resident_bytes
 
 
 class FakeClock:
@@ -49,6 +50,10 @@ class FakeEngine:
 
     def keep(self, u, inst):
         self.pops[u] = inst["gen"]
+
+    def evict(self, u):
+        self.log.append(("evict", u))
+        self.pops.pop(u, None)
 
 
 def _reqs(spec):
@@ -110,3 +115,32 @@ def test_stopped_requests_retire_early_and_the_next_window_continues_from_their_
     starts = [e for e in eng.log if e[0] == "start" and e[2] == 0]
     assert [e[3] for e in starts] == [0, 12]
     assert res[1].gen_end == 40 and res[2].gen_end == 52
+
+
+def test_resident_populations_count_against_the_budget_and_idle_ones_are_evicted():
+    clk = FakeClock()
+    eng = FakeEngine(clk)
+    one = footprint_bytes(256, 64, 256, "fp64")
+    res = resident_bytes(256, 64)
+    budget = one + 3 * res                       # one request in flight plus three residents
+    s = Scheduler(eng, P=64, generations=10, chunk=5, hbm_budget=budget, clock=clk)
+    seen = []
+    orig = eng.start
+
+    def start(req, gen0, warm):
+        seen.append(s.used)
+        return orig(req, gen0, warm)
+
+    eng.start = start
+    # five universes in turn, then universe 0 again: its population was evicted by then
+    reqs = _reqs([(0.001 * i, u, 256) for i, u in enumerate([0, 1, 2, 3, 4, 0])])
+    out = {r.rid: r for r in s.run(reqs)}
+    assert sorted(out) == list(range(6)) and not s.rejected
+    assert max(seen) + one <= budget             # admission kept every moment within the budget
+    assert s.used <= budget and len(s.resident) <= 3
+    ev = [e[1] for e in eng.log if e[0] == "evict"]
+    assert ev[:2] == [0, 1] and s.evictions == len(ev)   # least recently used first
+    starts = [e for e in eng.log if e[0] == "start" and e[2] == 0]
+    assert [e[4] for e in starts] == [False, False]      # universe 0 starts cold again ...
+    assert [e[3] for e in starts] == [0, 10]             # ... at its next generation
+    assert s.summary()["evictions"] == s.evictions
