@@ -57,12 +57,21 @@ def parse():
                     help="timed evaluations per pair-sum kernel variant in the autotuning pass")
     ap.add_argument("--variants", default="",
                     help="use these pair-sum kernel variants instead of autotuning, e.g. bf16x2=3,fp64=3")
+    ap.add_argument("--tune-table", default="",
+                    help="write the tuning table (every tuned shape) to this file at the end")
+    ap.add_argument("--only", default="",
+                    help="run only these parts (comma list of: main, batched, serving) and print their JSON")
     return ap.parse_args()
 
 
-def batched_run(n_inst, form, generations=200, reps=2):
+def batched_run(n_inst, form, generations=200, reps=2, tune_table=None):
     """Ragged batched form: n_inst independent GA instances (N ~ U{32..512}, T = 1024,
-    P = 512 each) advanced together by ONE pga_evolve call (one graph launch) per rep."""
+    P = 512 each) advanced together by ONE pga_evolve call (one graph launch) per rep.
+    The pair-sum variant for this batch (keyed by its largest N and total P) is chosen by
+    timing short graph-replayed runs of every variant, and the tuning table is written to
+    `tune_table` when given. One more run, eager with per-launch events, gives the kernel
+    times of a generation and the launch gap of the graph replay."""
+    import numpy as np
     import torch
 
     from paper_1403_4099_amd import pga, synth
@@ -75,7 +84,29 @@ def batched_run(n_inst, form, generations=200, reps=2):
         C, hi, lo = out if form == "bf16x2" else (out, None, None)
         insts.append(pga.make_instance(C, w.P, hi=hi, lo=lo, stats_rows=generations + 1, elites=w.elites,
                                        seed=w.seed, instance_id=i))
+    max_n = max(I.N for I in insts)
+    Ps = sum(I.P for I in insts)
     ctx = pga.Context()
+    # ---- variant choice for this batch shape (short graph runs, best of 2 after a warm-up)
+    tg = 20
+    ms = {}
+    for v in range(len(pga.variants(form))):
+        pga.tune_set(form, max_n, Ps, v)
+        if pga.tune_get(form, max_n, Ps) != v:          # does not fit this N
+            continue
+        ctx.evolve(insts, tg, form=form, init=True)
+        best = float("inf")
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.evolve(insts, tg, form=form, init=True)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        ms[v] = 1e3 * best / tg
+    vbest = min(ms, key=lambda v: (ms[v] > min(ms.values()) * 1.03, v))   # near-ties to the lower index
+    pga.tune_set(form, max_n, Ps, vbest)
+    saved = pga.tune_save(tune_table) if tune_table else None
+    # ---- timed runs
     ctx.evolve(insts, generations, form=form, init=True)          # warm-up: captures the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -83,18 +114,33 @@ def batched_run(n_inst, form, generations=200, reps=2):
         ctx.evolve(insts, generations, form=form, init=True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    Ps = sum(I.P for I in insts)
     pairs = sum(I.P * I.N * (I.N - 1) / 2 for I in insts)
+    # ---- kernel times of the same run (eager launches with events)
+    pga.timing_enable(True)
+    pga.timing_reset()
+    ctx.evolve(insts, generations, form=form, init=True)
+    torch.cuda.synchronize()
+    kern = {}
+    for kname in ("cluster_pairs", "nsmask", "pairsum_fp64", "pairsum_mfma", "finish", "rank", "breed", "init"):
+        k_ms, n = pga.timing_read(kname)
+        if n:
+            kern[kname] = {"avg_us": 1e3 * k_ms / n, "launches": n}
+    pga.timing_enable(False)
+    per_gen_kernels = sum(v["avg_us"] * v["launches"] for k, v in kern.items() if k != "init") / (generations + 1)
     ctx.close()
     return {"instances": n_inst, "form": form, "generations": generations,
             "seconds_per_run": dt, "gens_per_s": generations / dt,
             "fitness_evals_per_s": Ps * (generations + 1) / dt,
             "pair_visits_per_s": pairs * (generations + 1) / dt,
-            "sum_N": int(sum(I.N for I in insts)),
+            "sum_N": int(sum(I.N for I in insts)), "max_N": max_n, "sum_P": Ps,
+            "variant": {"chosen": vbest, "ms_per_generation": {str(k): round(v, 4) for k, v in ms.items()},
+                        "table_entries_saved": saved},
+            "kernels_us": kern,
+            "generation_us": {"graph_wall": 1e6 * dt / generations, "eager_kernel_sum": per_gen_kernels},
             "workload": "256 instances, N ~ U{32..512}, T=1024, 2-12 planted clusters, P=512, G=200"}
 
 
-def serving_run(seconds, rate, form, stall_gens=0, tol=1e-5):
+def serving_run(seconds, rate, form, stall_gens=0, tol=1e-5, eager=False):
     """Continuous-batching run over a Poisson stream of correlation windows (N in {64, 256, 1024}
     at 6:3:1, T = 390, P = 1024 resident and warm-started per universe, up to 100 generations per
     request in chunks of 10, 8 GiB admission budget). Windows are staged in HBM beforehand. With
@@ -109,11 +155,12 @@ def serving_run(seconds, rate, form, stall_gens=0, tol=1e-5):
     reqs = [Request(i, u, t, torch.from_numpy(R).cuda(), R.shape[0], R.shape[1])
             for i, (t, u, R) in enumerate(stream)]
     torch.cuda.synchronize()
-    sch = Scheduler(GpuEngine(P=1024, form=form, stall_gens=stall_gens, tol=tol), P=1024, generations=100,
-                    chunk=10, hbm_budget=8 << 30, form=form)
+    eng = GpuEngine(P=1024, form=form, stall_gens=stall_gens, tol=tol, eager=eager)
+    sch = Scheduler(eng, P=1024, generations=100, chunk=10, hbm_budget=8 << 30, form=form)
     res = sch.run(reqs)
     out = sch.summary()
     out.update({"offered_rate_per_s": rate, "stream_seconds": seconds, "form": form,
+                "launch": "eager" if eager else f"HIP graphs ({eng.ctx.graphs()} cached at the end)",
                 "termination": {"stall_gens": stall_gens, "tol": tol} if stall_gens else None,
                 "workload": "Poisson windows, N in {64,256,1024} 6:3:1 over 16 universes, T=390, "
                             "P=1024, up to 100 generations, 5% drift per window"})
@@ -133,20 +180,66 @@ def _gens_per_request(results):
 
 
 # ---------------------------------------------------------------- launch geometry (issued work)
-def mfma_issued_flops(N: int, P: int, B: int = 8) -> float:
-    """MFMA flops the BF16x2 pair-sum kernel issues for one launch (all tiles, padding included;
-    B individuals per workgroup)."""
-    cols = 64
-    n_jb = -(-N // cols)
-    n_pb = -(-P // B)
-    mfmas = 0
-    for jb in range(n_jb):
-        for w in range(4):
-            jt0 = jb * cols + 16 * w
-            my_iend = min(jt0 + 16, N) if jt0 < N else 0
-            if my_iend > 0:
-                mfmas += -(-my_iend // 32) * 2 * B
-    return float(mfmas) * n_pb * 16 * 16 * 32 * 2
+def mfma_issued_flops(pop, B: int = 8, packed: int = 0) -> float:
+    """MFMA flops the BF16x2 pair-sum kernel issues for one launch on population `pop` (P x N,
+    on the device; every individual through the pair-sum), two MFMAs (hi, lo) of 16 x 16 x 32 x 2
+    flops per column group and 32-row chunk up to the 16-stock tile's diagonal. Column kernel:
+    one group per individual of each batch of B. Packed kernel: ceil(sum_b K_b / 16) groups per
+    tile and batch, run in pairs (K_b: labels of the tile held by >= 2 stocks of individual b)."""
+    import torch
+    P_, N_ = pop.shape
+    if not packed:
+        n_tiles = -(-N_ // 16)
+        chunks = sum(-(-min(16 * w + 16, N_) // 32) for w in range(n_tiles))
+        return float(chunks * 2 * B * -(-P_ // B)) * 16 * 16 * 32 * 2
+    pad = (-N_) % 16
+    lab = pop.long()
+    cnt = torch.zeros((P_, N_), dtype=torch.int32, device=pop.device)
+    cnt.scatter_add_(1, lab, torch.ones_like(pop))
+    key = torch.where(torch.gather(cnt, 1, lab) >= 2, lab, torch.full_like(lab, -1))
+    if pad:
+        key = torch.cat([key, torch.full((P_, pad), -1, dtype=key.dtype, device=key.device)], dim=1)
+    t = key.view(P_, -1, 16).sort(dim=2).values
+    first = torch.ones_like(t, dtype=torch.bool)
+    first[..., 1:] = t[..., 1:] != t[..., :-1]
+    k = (first & (t >= 0)).sum(dim=2)                               # K per (individual, tile)
+    bpad = (-P_) % B
+    if bpad:
+        k = torch.cat([k, torch.zeros((bpad, k.shape[1]), dtype=k.dtype, device=k.device)], dim=0)
+    s = k.view(-1, B, k.shape[1]).sum(dim=1)                        # columns per (batch, tile)
+    nq = (s + 15) // 16
+    nq2 = (nq + 1) // 2 * 2
+    tiles = torch.arange(k.shape[1], device=pop.device)
+    chunks = (torch.clamp(tiles * 16 + 16, max=N_) + 31) // 32      # chunks up to the tile's diagonal
+    mfmas = (nq2 * chunks[None, :]).sum().item() * 2
+    return float(mfmas) * 16 * 16 * 32 * 2
+
+
+def kbar_tiles(pop) -> float:
+    """Mean one-hot width of the compacted contraction: over every individual and every tile of
+    16 consecutive stocks, the number of distinct labels in the tile held by at least two stocks
+    of the individual (singletons need no column). Computed with torch on the device."""
+    import torch
+    P_, N_ = pop.shape
+    pad = (-N_) % 16
+    lab = pop.long()
+    cnt = torch.zeros((P_, N_), dtype=torch.int32, device=pop.device)
+    cnt.scatter_add_(1, lab, torch.ones_like(pop))
+    ns = torch.gather(cnt, 1, lab)                                # n_s of each stock's label
+    key = torch.where(ns >= 2, lab, torch.full_like(lab, -1))
+    if pad:
+        key = torch.cat([key, torch.full((P_, pad), -1, dtype=key.dtype, device=key.device)], dim=1)
+    t = key.view(P_, -1, 16).sort(dim=2).values
+    first = torch.ones_like(t, dtype=torch.bool)
+    first[..., 1:] = t[..., 1:] != t[..., :-1]
+    k = (first & (t >= 0)).sum(dim=2)
+    return float(k.double().mean())
+
+
+def method_flops_bf16x2(N: int, P: int, kbar: float) -> float:
+    """Flops of the compacted one-hot contraction per launch: hi and lo, 2 flops per
+    multiply-add, N^2 / 2 (the triangle i < j) times the mean one-hot width kbar, P individuals."""
+    return 2.0 * N * N * kbar * P
 
 
 def pair_visits(N: int, P: int) -> float:
@@ -191,10 +284,24 @@ def recorded_traffic(kernel_src: str, N: int, P: int, variant: int):
 
 
 # ---------------------------------------------------------------- CPU baseline (oracle)
-def cpu_baseline(w, P, seed):
-    """The oracle, unchanged, on the host cores: the population's fitness is split into row blocks
-    evaluated by concurrent calls into the oracle (each call is single-threaded C and releases
-    the GIL), then one breed step. A single-thread run of a slice gives the per-core rate."""
+def _cpu_info():
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": None}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(w, P, seed, gens=3, gpu_check=None):
+    """The oracle, unchanged, on the host cores: `gens` generations of the workload from its initial
+    population (fitness of the whole population split into row blocks evaluated by concurrent calls
+    into the oracle, each call single-threaded C that releases the GIL; then one breed step).
+    Threads: the CPUs this process may run on, at most 16 (the CPU share of a one-GPU job).
+    gpu_check(C, pop0, f0) may compare the GPU's results with the oracle's on the same inputs."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
@@ -206,28 +313,39 @@ def cpu_baseline(w, P, seed):
     C = O.correlate(w.R)
     t_corr = time.perf_counter() - t0
     pop = O.init_pop(w.N, P, seed=seed)
+    pop0, f0 = pop, None
     t0 = time.perf_counter()
     O.fitness(C, pop[: max(1, P // threads)])
     t_one = time.perf_counter() - t0
     blocks = np.array_split(np.arange(P), threads)
-    t0 = time.perf_counter()
+    t_fit = t_breed = 0.0
     with ThreadPoolExecutor(threads) as ex:
-        parts = list(ex.map(lambda ix: O.fitness(C, pop[ix]), blocks))
-    t_fit = time.perf_counter() - t0
-    f = np.concatenate(parts)
-    t0 = time.perf_counter()
-    O.breed(pop, f, E=2, seed=seed, gen=0)
-    t_breed = time.perf_counter() - t0
-    evals_per_s = P / (t_fit + t_breed)
-    return {
+        for g in range(gens):
+            t0 = time.perf_counter()
+            parts = list(ex.map(lambda ix, pop=pop: O.fitness(C, pop[ix]), blocks))
+            t_fit += time.perf_counter() - t0
+            f = np.concatenate(parts)
+            if g == 0:
+                f0 = f
+            t0 = time.perf_counter()
+            pop = O.breed(pop, f, E=2, seed=seed, gen=g)
+            t_breed += time.perf_counter() - t0
+    evals_per_s = gens * P / (t_fit + t_breed)
+    ci = _cpu_info()
+    out = {
         "value": evals_per_s, "unit": "fitness evals/s", "cores": threads, "kind": "oracle",
-        "sample": (f"one generation of the N={w.N}, P={P} workload on the CPU oracle with {threads} "
-                   f"threads: fitness of the {P} initial labelings ({t_fit:.2f} s) + one breed step "
-                   f"({t_breed:.2f} s); one thread alone: {max(1, P // threads) / t_one:.0f} evals/s; "
-                   f"correlation of the window took {t_corr:.2f} s and is not in the rate"),
-        "gens_per_s": 1.0 / (t_fit + t_breed),
+        "sample": (f"{gens} generations of the N={w.N}, P={P} workload on the CPU oracle with {threads} "
+                   f"threads ({ci['affinity']} CPUs allotted of nproc {ci['nproc']}, {ci['model']}): fitness "
+                   f"{t_fit:.2f} s + breed {t_breed:.2f} s; one thread alone: "
+                   f"{max(1, P // threads) / t_one:.0f} evals/s; the window's correlation took "
+                   f"{t_corr:.2f} s and is not in the rate"),
+        "gens_per_s": gens / (t_fit + t_breed),
         "correlate_s": t_corr,
+        "cpu": ci,
     }
+    if gpu_check is not None:
+        out["gpu_vs_oracle"] = gpu_check(C, pop0, f0, ex_threads=threads)
+    return out
 
 
 def route_section(args, forms, results, insts, timed, step, pop0, route_default, C, hi, lo, N, P, G):
@@ -319,6 +437,17 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only:
+        # one part alone (for profiling it): its JSON object on one line, no headline
+        parts = set(args.only.split(","))
+        out = {}
+        if "batched" in parts:
+            out["batched"] = batched_run(args.batched_instances or 256, args.form,
+                                         tune_table=args.tune_table or None)
+        if "serving" in parts:
+            out["serving"] = serving_run(args.serve_seconds or 5.0, args.serve_rate, args.form)
+        print(json.dumps(out))
+        return
     route_default = pga.route_get()
     pga.route_set(0.0)          # headline: every individual through the pair-sum of its form
     w = synth.config3()
@@ -380,9 +509,9 @@ def main():
         else:
             v, ms = pga.tune(C, pop_tune, form, hi=hi, lo=lo, reps=args.tune_reps)
         tuned[form] = {"variant": v, "individuals_per_group": pga.variants(form)[v][0],
-                       "xcd_order": pga.variants(form)[v][1],
+                       "xcd_order": pga.variants(form)[v][1], "packed": pga.variants(form)[v][2],
                        "ms_per_variant": None if ms is None else
-                       {f"{a}x{b}": round(m, 4) for (a, b), m in zip(pga.variants(form), ms)}}
+                       {f"{a}x{b}{'p' if c else ''}": round(m, 4) for (a, b, c), m in zip(pga.variants(form), ms)}}
         print(f"[bench] {'variant' if ms is None else 'autotune'} {form}: {tuned[form]}", file=sys.stderr,
               flush=True)
     del pop_tune
@@ -407,6 +536,28 @@ def main():
             if n:
                 kern.setdefault(form, {})[k] = {"avg_us": 1e3 * ms / n, "launches": n}
     pga.timing_enable(False)
+
+    # ---- mean one-hot width (compacted, per 16-stock tile) of every population the timed generation
+    # loop evaluates: the same run replayed one generation per call (identical trajectory)
+    kb_loop = {}
+    for form in forms:
+        if form != "bf16x2":
+            continue
+        I = insts[form]
+        B, pk = tuned[form]["individuals_per_group"], tuned[form]["packed"]
+        ctx.evolve([I], 0, form=form, init=True)
+        kbs = [kbar_tiles(I.pop)]
+        iss = [mfma_issued_flops(I.pop, B, pk)]
+        for g in range(G):
+            I.gen0 = g
+            ctx.evolve([I], 1, form=form)
+            kbs.append(kbar_tiles(I.pop))
+            iss.append(mfma_issued_flops(I.pop, B, pk))
+        I.gen0 = 0
+        kb_loop[form] = {"mean": float(np.mean(kbs)), "generation_0": kbs[0], "final": kbs[-1],
+                         "issued_flops_mean": float(np.mean(iss))}
+        print(f"[bench] one-hot width per 16-stock tile over the loop ({form}): {kb_loop[form]}",
+              file=sys.stderr, flush=True)
 
     # ---- precision: BF16x2 vs FP64 fitness on the same populations
     prec = {}
@@ -462,14 +613,19 @@ def main():
             pga.timing_enable(False)
             t_call = float(np.median(calls))
             t_ps = 1e-3 * ms / n
+            entry = {"fitness_call_us": 1e6 * t_call, "fitness_evals_per_s": P / t_call,
+                     "pair_equivalent_per_s": pair_visits(N, P) / t_call,
+                     "pairsum_us": 1e6 * t_ps, "mean_K": kbar(pop)}
             if form == "bf16x2":
-                frac = mfma_issued_flops(N, P, tuned[form]["individuals_per_group"]) / t_ps / 1e12 / PEAK_MFMA_BF16
+                kt = kbar_tiles(pop)
+                entry["kbar_tile"] = kt
+                entry["pairsum_roofline_frac"] = method_flops_bf16x2(N, P, kt) / t_ps / 1e12 / PEAK_MFMA_BF16
+                entry["pairsum_issued_frac"] = (mfma_issued_flops(pop, tuned[form]["individuals_per_group"],
+                                                                  tuned[form]["packed"])
+                                                / t_ps / 1e12 / PEAK_MFMA_BF16)
             else:
-                frac = 2 * pair_visits(N, P) / t_ps / 1e12 / PEAK_ALU
-            by_pop.setdefault(form, {})[tag] = {
-                "fitness_call_us": 1e6 * t_call, "fitness_evals_per_s": P / t_call,
-                "pair_equivalent_per_s": pair_visits(N, P) / t_call,
-                "pairsum_us": 1e6 * t_ps, "pairsum_roofline_frac": frac, "mean_K": kbar(pop)}
+                entry["pairsum_roofline_frac"] = 2 * pair_visits(N, P) / t_ps / 1e12 / PEAK_ALU
+            by_pop.setdefault(form, {})[tag] = entry
 
     # ---- the generation loop: wall time per generation minus the kernels it runs
     loop = {}
@@ -505,9 +661,14 @@ def main():
         torch.cuda.synchronize()
         t_copy = min(t_copy, e0.elapsed_time(e1) * 1e-3)
     del a, b
+    fp64_tf = pga.peak_fp64()
     peaks = {"hbm_copy_GBps": 2 * nb / t_copy / 1e9, "mfma_bf16_TFLOPs": pga.peak_mfma_bf16(),
-             "published": {"hbm_GBps": 8000.0, "mfma_bf16_TFLOPs": PEAK_MFMA_BF16, "alu_Tops": PEAK_ALU},
-             "note": "sustained rates measured on this GPU; roofline.frac uses the published peak"}
+             "fp64_fma_TFLOPs": fp64_tf, "alu_lane_ops_Tops": fp64_tf / 2.0,
+             "published": {"hbm_GBps": 8000.0, "mfma_bf16_TFLOPs": PEAK_MFMA_BF16, "fp64_TFLOPs": 78.6,
+                           "alu_Tops": PEAK_ALU},
+             "note": "sustained rates measured on this GPU (HBM: device copy; MFMA: register-operand "
+                     "16x16x32 bf16 loop; FP64: register-operand v_fma_f64 loop, one lane-op = one FMA); "
+                     "roofline.frac uses the published peak"}
 
     form = args.form
     res = results[form]
@@ -517,11 +678,20 @@ def main():
     t_launch = k["avg_us"] * 1e-6
     src = os.path.join(ROOT, "paper_1403_4099_amd", "csrc", "k_mfma.hip" if form == "bf16x2" else "k_fitness.hip")
     if form == "bf16x2":
-        achieved = mfma_issued_flops(N, P, tuned[form]["individuals_per_group"]) / t_launch / 1e12
+        kb = kb_loop[form]["mean"]
+        achieved = method_flops_bf16x2(N, P, kb) / t_launch / 1e12
+        issued = kb_loop[form]["issued_flops_mean"] / t_launch / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_BF16, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_MFMA_BF16, "traffic": recorded_traffic(src, N, P, tuned[form]["variant"]),
                 "kernel": "k_pairsum_mfma", "avg_launch_us": k["avg_us"],
-                "work_per_launch": "issued v_mfma_f32_16x16x32_bf16 flops (hi and lo, 16x16 tile per 16 stocks)"}
+                "work_per_launch": (f"compacted one-hot contraction 2 * N^2 * Kbar * P flops (hi and lo, the "
+                                    f"triangle i < j, Kbar = {kb:.2f} distinct labels held by >= 2 stocks per "
+                                    f"16-stock tile, mean over the {G + 1} populations the loop evaluates)"),
+                "kbar": kb_loop[form],
+                "issued": {"achieved": issued, "frac": issued / PEAK_MFMA_BF16,
+                           "work_per_launch": "issued v_mfma_f32_16x16x32_bf16 flops (hi and lo; one column per "
+                                              "stock, or packed column groups of 16 run in pairs, as the tuned "
+                                              "variant has it), mean over the loop's populations"}}
     else:
         achieved = 2 * pair_visits(N, P) / t_launch / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU, "unit": "Tops/s",
@@ -530,6 +700,8 @@ def main():
                 "work_per_launch": "2 ops (label compare, FP64 add) per unordered pair per individual"}
     if form == "bf16x2":
         roof["frac_of_measured_peak"] = achieved / peaks["mfma_bf16_TFLOPs"]
+    else:
+        roof["frac_of_measured_peak"] = achieved / peaks["alu_lane_ops_Tops"]
     other = {}
     for f in results:
         if f == form:
@@ -573,21 +745,60 @@ def main():
     pga.route_set(route_default)
     # the batched and serving runs use the library's default route
     if args.batched_instances > 0:
-        line["batched"] = batched_run(args.batched_instances, form)
+        line["batched"] = batched_run(args.batched_instances, form, tune_table=args.tune_table or None)
         line["batched"]["route_frac"] = route_default
         print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
     if args.serve_seconds > 0:
         line["serving"] = serving_run(args.serve_seconds, args.serve_rate, form)
         line["serving"]["route_frac"] = route_default
         print(f"[bench] serving: {line['serving']}", file=sys.stderr, flush=True)
+        se = serving_run(args.serve_seconds, args.serve_rate, form, eager=True)
+        line["serving"]["eager_launches"] = {k: se[k] for k in ("p50_ms", "p99_ms", "requests_per_s", "chunks")}
         line["serving_with_termination"] = serving_run(args.serve_seconds, args.serve_rate, form,
                                                        stall_gens=10, tol=1e-5)
         line["serving_with_termination"]["route_frac"] = route_default
         print(f"[bench] serving with termination: {line['serving_with_termination']}", file=sys.stderr,
               flush=True)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(w, P, w.seed)
+        pga.route_set(0.0)      # the precision statement is for the pair-sum of the form
+
+        def gpu_check(C_o, pop0_o, f0_o, ex_threads):
+            """BF16x2 fitness (pair-sum route) against the FP64 oracle, per result, on the initial
+            population and on the BF16x2 GA run's final population; and whether both pick the same
+            best labeling."""
+            from concurrent.futures import ThreadPoolExecutor
+
+            import oracle as O
+            out = {}
+            with ThreadPoolExecutor(ex_threads) as ex:
+                for tag, popn in (("random_generation_0", pop0_o),
+                                  ("ga_final_population", insts["bf16x2"].pop.cpu().numpy()
+                                   if "bf16x2" in insts else None)):
+                    if popn is None:
+                        continue
+                    blocks = np.array_split(np.arange(P), ex_threads)
+                    parts = list(ex.map(lambda ix: O.fitness(C_o, popn[ix], want_mag=True), blocks))
+                    f_o = np.concatenate([a for a, _ in parts])
+                    mag = np.concatenate([b for _, b in parts])
+                    f_g = pga.fitness(C, torch.from_numpy(popn).to(dev), "bf16x2", hi=hi, lo=lo).cpu().numpy()
+                    d = np.abs(f_g - f_o)
+                    rel = d / np.maximum(np.abs(f_o), 1e-300)
+                    lg, _, _ = O.best(f_g, popn)
+                    lo_, _, _ = O.best(f_o, popn)
+                    out[tag] = {"max_rel_err": float(rel.max()), "median_rel_err": float(np.median(rel)),
+                                "max_err_over_M": float((d / np.maximum(mag, 1e-300)).max()),
+                                "identical_best_labeling": bool(np.array_equal(lg, lo_)),
+                                "individuals": int(P)}
+            out["note"] = ("every individual's BF16x2 L_c (MFMA pair-sum) against the FP64 oracle's; "
+                           "rel = |dL| / |L_oracle|, M = sum of |log terms|")
+            return out
+
+        cb = cpu_baseline(w, P, w.seed, gpu_check=gpu_check if "bf16x2" in insts else None)
+        pga.route_set(route_default)
         line["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}
+        line["cpu_baseline"]["cpu"] = cb["cpu"]
+        if "gpu_vs_oracle" in cb:
+            line["precision"]["bf16x2_vs_fp64_oracle"] = cb["gpu_vs_oracle"]
     else:
         line["cpu_baseline"] = None
     ctx.close()

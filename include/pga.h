@@ -254,8 +254,14 @@ double pga_route_get(void);
  * when there is none or when it does not fit N. The table is shared by all
  * threads and devices of the process and guarded by a lock.
  *
+ * For PGA_FORM_BF16X2 some variants use the packed kernel (packed = 1):
+ * columns only for the labels with n_s >= 2 of each individual's 16-stock
+ * tiles, packed over the workgroup's individuals into groups of 16 (fewer
+ * MFMAs, more LDS and scalar work; a small extra launch marks the labels with
+ * n_s >= 2); the others give every stock its own column.
  * pga_variant_count: number of variants of `form` (PGA_ERR_ARG for a bad form).
- * pga_variant_info: individuals per group and XCD ordering of one variant.
+ * pga_variant_info: individuals per group, XCD ordering and packing (each out
+ *   pointer nullable) of one variant.
  * pga_tune (SYNC): times every variant that fits N on `labels` (P x N, device):
  *   after 2 reps + 2 warm-up evaluations, three rounds in which each variant
  *   in turn runs `reps` evaluations, all back to back on `stream` and timed
@@ -270,7 +276,7 @@ double pga_route_get(void);
  * pga_tune_get: the variant a call with this (form, N, P) would use. */
 int pga_variant_count(int32_t form);
 int pga_variant_info(int32_t form, int32_t variant, int32_t *individuals_per_group,
-                     int32_t *xcd_order);
+                     int32_t *xcd_order, int32_t *packed);
 size_t pga_tune_ws_bytes(int32_t N, int32_t P, int32_t form);
 int pga_tune(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
              const int32_t *labels, int32_t P, int32_t form, int32_t reps, void *ws,

@@ -1,7 +1,7 @@
 // Correlation (Eq. 7 of Section 2.2.3) and the BF16 hi + lo split of C.
 //
 //   row stats : mean_i and s_i = sum_t (R_it - mean_i)^2 (two passes, FP64)
-//   corr      : C_ij = sum_t x_it x_jt / sqrt(s_i s_j): FP64 MFMA Gram on 64 x 64
+//   corr      : C_ij = sum_t x_it x_jt / sqrt(s_i s_j): FP64 MFMA Gram on 128 x 128
 //               output tiles of the upper triangle (t split into slices), x =
 //               R - mean staged through LDS; the slices added in order, C_ii =
 //               1, clamp to [-1, 1], zero-variance stocks get 0 off the
@@ -56,28 +56,32 @@ hipError_t launch_row_stats(const double *R, int N, int T, int64_t ld, double *m
 }
 
 // ---- Gram matrix on FP64 MFMA ----------------------------------------------------
-// G_ij = sum_t x_it x_jt over the upper triangle of 64 x 64 output tiles, each
-// tile's t range split into S slices (S from gram_split: enough workgroups to
-// fill the GPU), one workgroup per (tile, slice):
-//   * the workgroup stages x of its 64 + 64 rows, 16 samples at a time, in LDS
+// G_ij = sum_t x_it x_jt over the upper triangle of 128 x 128 output tiles,
+// each tile's t range split into S slices (gram_split: about one workgroup per
+// CU), one workgroup per (tile, slice):
+//   * the workgroup stages x of its 128 + 128 rows, 8 samples at a time, in LDS
 //     (two buffers: the next chunk's global loads are in flight while the
 //     current one is multiplied); x = R - mean for the correlation, the
 //     weighted returns as they are for the EWMA covariance;
-//   * wave w owns the 32 x 32 quadrant (w / 2, w % 2) of the tile: four 16 x 16
-//     blocks, each accumulated by v_mfma_f64_16x16x4_f64 (lane l supplies
-//     A[l % 16][l / 16] and B[l / 16][l % 16]: row l % 16 of A and column
-//     l % 16 of B at the four samples t0 + 4 (l / 16) .. + 3, one per MFMA, so
-//     both operands see the same t);
-//   * the slice's 64 x 64 partial Gram goes to the workspace; a finish kernel
-//     adds the S slices of a tile in slice order (a fixed order: the result
-//     does not depend on timing), applies the normalisation and writes the
-//     tile and its mirror image through LDS, both coalesced.
+//   * wave w owns the 64 x 64 quadrant (w / 2, w % 2) of the tile: sixteen
+//     16 x 16 blocks, each accumulated by v_mfma_f64_16x16x4_f64 (lane l
+//     supplies A[l % 16][l / 16] and B[l / 16][l % 16]: row l % 16 of A and
+//     column l % 16 of B at the samples t0 + 2 (l / 16) and + 1, one per MFMA,
+//     so both operands see the same t); 32 MFMAs per staged chunk and wave;
+//   * the slice's 128 x 128 partial Gram goes to the workspace; a finish kernel
+//     (one workgroup per 64 x 64 quarter of a tile) adds the S slices in slice
+//     order (a fixed order: the result does not depend on timing), applies the
+//     normalisation and writes the quarter and its mirror image through LDS,
+//     both coalesced.
+// A 128 x 128 tile moves half the bytes per flop of a 64 x 64 one: at N = 1024,
+// T = 4096 the rows of R are read from the shared caches about 9 times in all.
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGT = 64;                 // output tile edge
-constexpr int kGK = 16;                 // samples per staged chunk
+constexpr int kGT = 128;                // output tile edge
+constexpr int kGQ = 64;                 // quadrant edge of one wave (and the finish's quarter)
+constexpr int kGK = 8;                  // samples per staged chunk
 constexpr int kGPad = kGK + 2;          // LDS row stride (doubles): 16-byte aligned rows, spread banks
-constexpr int kGMaxSplit = 8;
+constexpr int kGMaxSplit = 16;
 
 int gram_tiles(int N) {
     const int nt = (N + kGT - 1) / kGT;
@@ -85,10 +89,11 @@ int gram_tiles(int N) {
 }
 
 // Slices per tile for a given N (upper bound) and, with T known, the slices used:
-// about 512 workgroups in all, at most kGMaxSplit, and at least 64 samples per slice.
+// about 256 workgroups in all (one per CU), at most kGMaxSplit, and at least 64
+// samples per slice.
 int gram_split_max(int N) {
     const int t = gram_tiles(N);
-    int S = (512 + t - 1) / t;
+    int S = (256 + t / 2) / t;
     return S < 1 ? 1 : (S > kGMaxSplit ? kGMaxSplit : S);
 }
 
@@ -126,53 +131,55 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double *X, int N, int T
     const int te = min(T, ts + per);
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    // staging: element x = e * 256 + tid of a 64 x 16 chunk is row x / 16, sample x % 16, so each load
-    // instruction of a wave reads four full 128-byte row segments
-    const int srow = tid >> 4, scol = tid & 15;
-    // Loads take clamped (always valid) addresses and the value is multiplied by a 0/1 weight
-    // afterwards, so every load is issued unconditionally and together with the others: rows past
-    // N and samples past the slice give 0 (a clamped address repeats an element of the same row
-    // or of row N - 1, whose entries are discarded).
-    double muA[4], muB[4], wA[4], wB[4];
-    const double *rowA[4], *rowB[4];
+    // staging: element x = e * 256 + tid of a 128 x 8 chunk is row x / 8, sample x % 8, so each load
+    // instruction of a wave reads eight 64-byte row segments
+    const int srow = tid >> 3, scol = tid & 7;
+    // Loads take clamped (always valid) addresses and the value is zeroed afterwards where the row is
+    // past N or the sample past the slice (a clamped address repeats an element of the same row or
+    // of row N - 1, whose entries are discarded), so every load is issued unconditionally and
+    // together with the others.
+    double muA[4], muB[4];
+    int rowA[4], rowB[4];
+    uint32_t valid = 0;                                      // bit e: row e of A; bit 4 + e: of B
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int ra = i0 + 16 * e + srow, rb = j0 + 16 * e + srow;
-        muA[e] = CENTER ? mu[min(ra, N - 1)] : 0.0;
-        muB[e] = CENTER ? mu[min(rb, N - 1)] : 0.0;
-        wA[e] = ra < N ? 1.0 : 0.0;
-        wB[e] = rb < N ? 1.0 : 0.0;
-        rowA[e] = X + (size_t)min(ra, N - 1) * ld;
-        rowB[e] = X + (size_t)min(rb, N - 1) * ld;
+        const int ra = i0 + 32 * e + srow, rb = j0 + 32 * e + srow;
+        rowA[e] = min(ra, N - 1);
+        rowB[e] = min(rb, N - 1);
+        muA[e] = CENTER ? mu[rowA[e]] : 0.0;
+        muB[e] = CENTER ? mu[rowB[e]] : 0.0;
+        valid |= (ra < N ? 1u : 0u) << e;
+        valid |= (rb < N ? 1u : 0u) << (4 + e);
     }
     // The raw values are loaded first and only used when they are stored into LDS, after the
     // current chunk's MFMAs have been issued, so the loads' latency is hidden behind them.
-    double va[4], vb[4], wt = 0.0;
+    double va[4], vb[4];
+    bool tin = false;
     auto load = [&](int t0) {
         const int t = t0 + scol;
-        wt = t < te ? 1.0 : 0.0;
+        tin = t < te;
         const int tc = min(t, te - 1);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            va[e] = rowA[e][tc];
-            vb[e] = rowB[e][tc];
+            va[e] = X[(size_t)rowA[e] * ld + tc];
+            vb[e] = X[(size_t)rowB[e] * ld + tc];
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            sA[buf][(16 * e + srow) * kGPad + scol] = (va[e] - muA[e]) * (wA[e] * wt);
-            sB[buf][(16 * e + srow) * kGPad + scol] = (vb[e] - muB[e]) * (wB[e] * wt);
+            sA[buf][(32 * e + srow) * kGPad + scol] = (tin && ((valid >> e) & 1u)) ? va[e] - muA[e] : 0.0;
+            sB[buf][(32 * e + srow) * kGPad + scol] = (tin && ((valid >> (4 + e)) & 1u)) ? vb[e] - muB[e] : 0.0;
         }
     };
 
     const int qr = wave >> 1, qc = wave & 1;
     const int m = lane & 15, kq = lane >> 4;
-    gram_d4 acc[2][2];
+    gram_d4 acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 4; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
 
     int buf = 0;
     if (ts < te) {
@@ -185,23 +192,22 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double *X, int N, int T
         if (more) load(t0 + kGK);
         const double *A = sA[buf];
         const double *B = sB[buf];
-        double xa[2][4], xb[2][4];
+        double xa[4][2], xb[4][2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const double *pa = A + (32 * qr + 16 * a + m) * kGPad + 4 * kq;
-            const double *pb = B + (32 * qc + 16 * a + m) * kGPad + 4 * kq;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                xa[a][e] = pa[e];
-                xb[a][e] = pb[e];
-            }
+        for (int a = 0; a < 4; ++a) {
+            const double *pa = A + (kGQ * qr + 16 * a + m) * kGPad + 2 * kq;
+            const double *pb = B + (kGQ * qc + 16 * a + m) * kGPad + 2 * kq;
+            xa[a][0] = pa[0];
+            xa[a][1] = pa[1];
+            xb[a][0] = pb[0];
+            xb[a][1] = pb[1];
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 2; ++e)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < 4; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a][e], xb[b][e], acc[a][b], 0, 0, 0);
         if (more) store(buf ^ 1);
         __syncthreads();
@@ -209,7 +215,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double *X, int N, int T
     }
     // Where each accumulator register sits in its 16 x 16 block is read off the hardware: one
     // MFMA with A[i][0] = i, B[0][j] = 1 (zero for k > 0) gives every register its row i, one with
-    // A[i][0] = 1, B[0][j] = j its column j (small integers, exact in FP64).
+    // A[i][0] = 1, B[0][j] = j its column j (small integers, exact in FP64). On this GPU register r
+    // of lane l holds D[l / 16 + 4 r][l % 16].
     const double idx = kq == 0 ? (double)m : 0.0, one = kq == 0 ? 1.0 : 0.0;
     const gram_d4 zero = {0.0, 0.0, 0.0, 0.0};
     const gram_d4 rowv = __builtin_amdgcn_mfma_f64_16x16x4f64(idx, one, zero, 0, 0, 0);
@@ -219,43 +226,47 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double *X, int N, int T
     for (int r = 0; r < 4; ++r) {
         const int ri = (int)rowv[r], ci = (int)colv[r];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) out[(32 * qr + 16 * a + ri) * kGT + 32 * qc + 16 * b + ci] = acc[a][b][r];
+            for (int b = 0; b < 4; ++b)
+                out[(kGQ * qr + 16 * a + ri) * kGT + kGQ * qc + 16 * b + ci] = acc[a][b][r];
     }
 }
 
-// Sum of the S slices of element e of tile `tile` (slice order).
-__device__ __forceinline__ double gram_sum(const double *part, int tiles, int S, int tile, int e) {
+// Sum of the S slices of element (r, c) of tile `tile` (slice order).
+__device__ __forceinline__ double gram_sum(const double *part, int tiles, int S, int tile, int r, int c) {
     double v = 0.0;
-    for (int s = 0; s < S; ++s) v += part[((size_t)s * tiles + tile) * (kGT * kGT) + e];
+    for (int s = 0; s < S; ++s) v += part[((size_t)s * tiles + tile) * (kGT * kGT) + (size_t)r * kGT + c];
     return v;
 }
 
-// Writes value f(i, j, g) of every element of the tile at (i, j) and, off the
-// diagonal, at (j, i), both row-wise through an LDS transpose.
+// One workgroup per 64 x 64 quarter of a tile (blockIdx.x = 4 tile + quarter): writes value
+// f(i, j, g) of every element of the quarter at (i, j) and, off the diagonal, at (j, i), both
+// row-wise through an LDS transpose. Only i <= j is written directly and i < j mirrored, so the
+// lower quarter of a diagonal tile writes nothing.
 template <class F>
 __device__ __forceinline__ void gram_emit(const double *part, int N, int nt, int tiles, int S, double *dst, F f) {
-    __shared__ double tr[kGT][kGT + 1];
-    const int tile = blockIdx.x;
+    __shared__ double tr[kGQ][kGQ + 1];
+    const int tile = blockIdx.x >> 2, quarter = blockIdx.x & 3;
     int ti, tj;
     gram_tile_ij(tile, nt, ti, tj);
-    const int i0 = ti * kGT, j0 = tj * kGT;
-    for (int e = threadIdx.x; e < kGT * kGT; e += 256) {
-        const int r = e / kGT, c = e % kGT;
+    const int r0 = kGQ * (quarter >> 1), c0 = kGQ * (quarter & 1);   // within the tile
+    const int i0 = ti * kGT + r0, j0 = tj * kGT + c0;
+    for (int e = threadIdx.x; e < kGQ * kGQ; e += 256) {
+        const int r = e / kGQ, c = e % kGQ;
         const int i = i0 + r, j = j0 + c;
         double v = 0.0;
-        if (i < N && j < N && (ti != tj || i <= j)) {
-            v = f(i, j, gram_sum(part, tiles, S, tile, e));
+        if (i < N && j < N && i <= j) {
+            v = f(i, j, gram_sum(part, tiles, S, tile, r0 + r, c0 + c));
             dst[(size_t)i * N + j] = v;
         }
         tr[c][r] = v;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kGT * kGT; e += 256) {
-        const int r = e / kGT, c = e % kGT;             // destination row j0 + r, column i0 + c
+    for (int e = threadIdx.x; e < kGQ * kGQ; e += 256) {
+        const int r = e / kGQ, c = e % kGQ;             // destination row j0 + r, column i0 + c
         const int j = j0 + r, i = i0 + c;
-        if (i < N && j < N && (ti != tj ? true : i < j)) dst[(size_t)j * N + i] = tr[r][c];
+        if (i < N && j < N && i < j) dst[(size_t)j * N + i] = tr[r][c];
     }
 }
 
@@ -275,7 +286,7 @@ hipError_t launch_corr(const double *R, int N, int T, int64_t ld, const double *
     hipLaunchKernelGGL(k_gram_mfma<true>, dim3(tiles * S), dim3(256), 0, s, R, N, T, ld, mu, nt, tiles, S, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_corr_finish, dim3(tiles), dim3(256), 0, s, part, N, nt, tiles, S, ss, C);
+    hipLaunchKernelGGL(k_corr_finish, dim3(4 * tiles), dim3(256), 0, s, part, N, nt, tiles, S, ss, C);
     return hipGetLastError();
 }
 
@@ -377,8 +388,8 @@ hipError_t launch_ewma(const double *R, int N, int T, int64_t ld, double lam, in
     hipLaunchKernelGGL(k_gram_mfma<false>, dim3(tiles * Sp), dim3(256), 0, s, X, N, T, (int64_t)T, nullptr, nt,
                        tiles, Sp, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ewma_finish, dim3(tiles), dim3(256), 0, s, part, N, nt, tiles, Sp, pow(lam, (double)T),
-                       reset, S);
+    hipLaunchKernelGGL(k_ewma_finish, dim3(4 * tiles), dim3(256), 0, s, part, N, nt, tiles, Sp,
+                       pow(lam, (double)T), reset, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t nn = (int64_t)N * N;
     hipLaunchKernelGGL(k_ewma_norm, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, S, N, C, status);

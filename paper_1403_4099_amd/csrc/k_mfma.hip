@@ -1,48 +1,55 @@
 // BF16x2 pair-sum on MFMA: v_pj = C_jj + 2 sum_{i<j} [s_pi = s_pj] (hi_ji + lo_ji),
-// the sum over i read off the compacted one-hot contraction Z = C Y (c_s is the
-// diagonal of Y^T C Y, Eq. 6).
+// the sum over i read off a one-hot contraction (c_s is the diagonal of
+// Y^T C Y, Eq. 6). Two kernels, chosen per shape by the tuner (Variant::packed):
 //
-// One wave owns 16 stocks j = jt0 .. jt0+15 and walks the rows i < j in chunks
-// of 32 with v_mfma_f32_16x16x32_bf16:
-//   A[m][k] = 2^125 C[jt0 + m][i0 + k]        (hi, then lo: two MFMAs)
-//   B[k][c] = 2^-125 [s^(b_c)_{i0 + k} = l_c]  (column c: individual b_c, label l_c)
-//   D[m][c] += sum_k A[m][k] B[k][c]
-// Compaction: the columns are not one per stock but one per distinct label
-// that the wave's 16 stocks carry in an individual and that at least one
-// other stock of that individual shares (n_s >= 2; a singleton's sum is 0),
-// packed over the workgroup's individuals into as few groups of 16 columns as
-// they need: a chunk issues ceil(sum_b K_b / 16) MFMA pairs instead of one per
-// individual (K_b: such labels of individual b in the wave's tile). Stock m of
-// individual b then reads its sum from D[m][column of (b, its label)]. The
-// label sets come from a bit mask per individual of the labels with n_s >= 2
-// (k_nsmask); individuals past P or evaluated by the cluster-pair kernel get
-// no columns.
+// Column kernel (one column per stock). One wave owns 16 stocks
+// j = jt0 .. jt0+15 and walks the rows i < j in chunks of 32 with
+// v_mfma_f32_16x16x32_bf16:
+//   A[m][k] = 2^125 C[jt0 + m][i0 + k]       (hi, then lo: two MFMAs)
+//   B[k][n] = 2^-125 [s_{i0+k} = s_{jt0+n}] [i0 + k < jt0 + n]
+//   D[m][n] += sum_k A[m][k] B[k][n];  D[n][n] = partial sum for stock jt0+n
+// Lane l supplies row m = l%16 of A and column n = l%16 of B over the same
+// eight k = 8(l/16)..+7, so its A row and B column are both stock jt0 + l%16.
+// In a chunk the 16 lanes of a row group need the same 8 row codes per
+// individual; each lane reads B/4 different dwords (two row codes each) and
+// the xor takes its row operand from the lane that holds it (DPP row
+// broadcast), so a chunk costs one B*64-byte LDS read per wave. The i < j mask
+// is applied to B in the chunk that reaches the diagonal.
 //
-// The triangle i < j is applied to A in the one chunk that reaches the
-// diagonal: A's row m is stock jt0 + m, and its element k is zeroed when row
-// i0 + k is not below that stock, once for all columns of the chunk.
+// Packed kernel (compacted columns). The columns are not one per stock but
+// one per distinct label that the wave's 16 stocks carry in an individual and
+// that at least one other stock of that individual shares (n_s >= 2; a
+// singleton's sum is 0), packed over the workgroup's individuals into as few
+// groups of 16 columns as they need: a chunk issues ceil(sum_b K_b / 16) MFMA
+// pairs (groups run in pairs) instead of one pair per individual. Stock m of
+// individual b reads its sum from D[m][column of (b, its label)]; the label
+// sets come from a bit mask per individual of the labels with n_s >= 2
+// (k_nsmask), and individuals past P or evaluated by the cluster-pair kernel
+// get no columns. A lane of a column group reads the 8 row codes of its own
+// column's individual (16 bytes, row codes staged per individual), the i < j
+// mask is applied to A (once per chunk: A's row m is stock jt0 + m), and the
+// FP32 sums are flushed through a wave-private LDS buffer. Fewer MFMAs, but
+// per-lane row-code reads, a per-block column set-up and the flushes cost
+// LDS and scalar work the column kernel does not have.
 //
-// Label codes. A workgroup serves one block of 64 stocks, which carry at most
-// 64 distinct labels per individual. Each such label gets a code (the block
-// position of one stock that has it, 0..63); a row whose label is not among
-// them gets the code kCodeNone. Codes are stored shifted into bits 8..15 of a
-// 16-bit word, so for a row word r and a column word c the saturating
-// difference 0x0100 - (r ^ c) is 0x0100 (the bf16 number 2^-125) when the
-// labels are equal and 0 otherwise: two packed 16-bit ALU ops build two B
-// elements. A column left unused in the last group gets the code kCodeFree,
-// which matches no row. The 2^-125 is undone by keeping A as the split parts
+// Label codes (both kernels). A workgroup serves one block of 64 stocks,
+// which carry at most 64 distinct labels per individual. Each such label gets
+// a code (the block position of one stock that has it, 0..63); a row whose
+// label is not among them gets the code kCodeNone. Codes are stored shifted
+// into bits 8..15 of a 16-bit word, so for a row word r and a column word c
+// the saturating difference 0x0100 - (r ^ c) is 0x0100 (the bf16 number
+// 2^-125) when the labels are equal and 0 otherwise: two packed 16-bit ALU ops
+// build two B elements. The 2^-125 is undone by keeping A as the split parts
 // times 2^125 (a workspace copy made once per call); every product is then
 // exactly the split part, as with a one-hot of 1.0.
 //
 // A is loaded once per (wave, chunk), one chunk ahead, by direct
 // global-to-LDS loads into a two-slot ring per wave (no registers hold it in
-// flight), and reused by every column group. Row codes are staged in LDS per
-// individual, RC rows at a time; lane (n, g) of a column group reads the 8
-// codes of rows i0 + 8g .. +7 of its column's individual in one 16-byte read.
-// FP32 accumulation is flushed into FP64 at every 512-row boundary (no FP32
-// partial sum spans more than 512 rows): each group's 16 x 16 accumulator goes
-// through a wave-private LDS buffer, from which every lane takes the sums of
-// its stock for the individuals it keeps (b = g, g + 4, ...).
+// flight), and reused by every individual or column group. FP32
+// accumulation is flushed into FP64 at every 512-row boundary (no FP32 partial
+// sum spans more than 512 rows). Both kernels give the same sums bit for bit:
+// a stock's column holds the same one-hot values in either, and its FP32
+// partial sums see the same products in the same chunks.
 #include "pga_internal.hpp"
 
 #include <type_traits>
@@ -65,9 +72,259 @@ __device__ __forceinline__ uint32_t onehot2(uint32_t rows2, uint32_t col2) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(one, x));
 }
 
+// Row codes in the xor of lane t of a row group come from lane T of that
+// group (DPP row broadcast; T a compile-time constant).
+template <int T>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + T, 0xF, 0xF, false);
+}
+
 template <int... I, typename F>
 __device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &&f) {
     (f(std::integral_constant<int, I>{}), ...);
+}
+
+// Position of individual b's dword within a staged row pair: lane t of a row
+// group reads positions (B/4)(t/4) .. +B/4-1, i.e. individuals t/4, t/4 + 4, ...
+template <int B>
+__host__ __device__ constexpr int mfma_pos(int b) {
+    return (B / 4) * (b & 3) + (b >> 2);
+}
+
+// LDS of one workgroup (dynamic): row codes, kMfmaRowCodes 16-bit words (the
+// code shifted into bits 8..15), as dwords [row pair][mfma_pos(b)] holding the
+// rows 2q (low half) and 2q + 1 of individual b; then the label -> code
+// tables [B][cstride] (bytes, cstride >= N); then each wave's ring of
+// kMfmaASlots A slots, 2 KB each (the 16 x 32 hi tile, then the lo tile, in
+// lane order), filled by direct global-to-LDS loads one chunk ahead.
+struct MfmaLdsCols {
+    uint32_t *rows;
+    uint8_t *code;
+    unsigned char *aring;
+    int cstride;
+};
+
+// One column block jb (64 stocks, 16 per wave) for the B individuals of batch pb.
+// On entry every code table entry below N holds kCodeNone; it is restored on exit.
+template <int B>
+__device__ __forceinline__ void mfma_block_cols(const InstDesc &d, int jb, int pb, int parity, const MfmaLdsCols &s) {
+    constexpr int RC = kMfmaRowCodes / B;                     // rows staged per pass
+    const int N = d.N, P = d.P, ld = d.ld_h;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, kept scalar
+    const int lane = threadIdx.x & 63;
+    const int n = lane & 15, g = lane >> 4;
+    const int q = 16 * wave + n;                              // position of this lane's stock in the block
+    const int jt0 = jb * kMfmaCols + 16 * wave;
+    const int j = jt0 + n;
+    const int pbase = pb * B;
+    const int32_t *__restrict__ labels = d.pop[parity];
+    const uint16_t *__restrict__ hs = d.hs;
+    const uint16_t *__restrict__ ls = d.ls;
+    auto code = [&](int b, int l) -> uint8_t & { return s.code[(size_t)b * s.cstride + l]; };
+
+    // Column labels; lanes with g == 0 register them in the code table. Stock,
+    // individual and label are clamped into range as in the staging below: a
+    // column past N or an individual past P is not stored, and a clamped
+    // duplicate only writes a consistent code (the position of some stock with
+    // that label) into its own individual's table.
+    const uint32_t lmax = (uint32_t)(N - 1);
+    const int jc = min(j, N - 1);
+    uint32_t lj[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+        lj[b] = min((uint32_t)gld(labels + (size_t)min(pbase + b, P - 1) * N + jc), lmax);
+    if (g == 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) code(b, (int)lj[b]) = (uint8_t)q;
+    }
+    __syncthreads();
+    uint32_t col2[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint32_t c = code(b, (int)lj[b]);
+        col2[b] = (c << kCodeShift) | (c << (16 + kCodeShift));
+    }
+
+    floatx4 acc[B];
+    double acc64[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc64[b] = 0.0;
+    }
+    const int dreg = n & 3;                                   // lane holds D[n][n] in register n & 3 ...
+    const bool diag_lane = (n >> 2) == g;                     // ... when its 4-row group contains row n
+
+    auto flush = [&]() {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const float v = dreg == 0 ? acc[b][0] : dreg == 1 ? acc[b][1] : dreg == 2 ? acc[b][2] : acc[b][3];
+            acc64[b] += (double)v;
+            acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    // Only waves with jt0 < N load A, and then j < ld for every lane (ld is a
+    // multiple of 32 and jt0 a multiple of 16), so the loads need no guard. The
+    // scaled copies are tile-major (a_tile_offset): the wave's 16 x 32 A block is
+    // 1 KB of consecutive bytes in lane order.
+    // Chunk i0's A goes to ring slot ((i0 - c0) / 32) % kMfmaASlots of this wave:
+    // a direct global-to-LDS load puts lane l's 16 bytes at slot + 16 l, exactly
+    // where the same lane reads them back.
+    const size_t a_row = (size_t)(jt0 >> 4) * (size_t)(ld >> 5);
+    unsigned char *const my_ring = s.aring + (size_t)wave * kMfmaASlots * 2048;
+    auto slot_of = [&](int i0, int c0) { return my_ring + (size_t)(((i0 - c0) >> 5) % kMfmaASlots) * 2048; };
+    auto load_a = [&](int i0, int c0) {
+        const size_t off = (a_row + (size_t)(i0 >> 5)) * 512 + (size_t)lane * 8;
+        unsigned char *sl = slot_of(i0, c0);
+        __builtin_amdgcn_global_load_lds((const void *)(hs + off), (__attribute__((address_space(3))) void *)sl, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)(ls + off), (__attribute__((address_space(3))) void *)(sl + 1024), 16,
+                                         0, 0);
+    };
+    auto read_a = [&](int i0, int c0, uint4 &ah, uint4 &al) {
+        const unsigned char *sl = slot_of(i0, c0);
+        ah = *(const uint4 *)(sl + 16 * lane);
+        al = *(const uint4 *)(sl + 1024 + 16 * lane);
+    };
+    // Lane t of row group g reads, into R[k], rows i0 + 8g + 2(t%4), +1 of individual 4k + t/4.
+    auto read_r = [&](int i0, int c0, uint32_t (&R)[B / 4]) {
+        const uint32_t *rp = s.rows + (size_t)(((i0 - c0) >> 1) + 4 * g + (n & 3)) * B + (B / 4) * (n >> 2);
+        if constexpr (B == 4) {
+            R[0] = *rp;
+        } else if constexpr (B == 8) {
+            const uint2 q2 = *(const uint2 *)rp;
+            R[0] = q2.x;
+            R[1] = q2.y;
+        } else {
+            const uint4 q4 = *(const uint4 *)rp;
+            R[0] = q4.x;
+            R[1] = q4.y;
+            R[2] = q4.z;
+            R[3] = q4.w;
+        }
+    };
+    auto chunk = [&](auto masked_tag, int i0, int c0, uint4 ah, uint4 al, const uint32_t (&R)[B / 4]) {
+        constexpr bool masked = decltype(masked_tag)::value;
+        const int ik = i0 + 8 * g;                            // first of this lane's 8 rows
+        uint32_t m[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+        if constexpr (masked) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                m[r] = ((ik + 2 * r < j) ? 0xFFFFu : 0u) | ((ik + 2 * r + 1 < j) ? 0xFFFF0000u : 0u);
+        }
+        const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah);
+        const bf16x8 Al = __builtin_bit_cast(bf16x8, al);
+        // B column of individual b: its dword e (rows ik + 2e, +1) is in R[b/4] of lane 4(b%4) + e.
+        auto bcol = [&](auto bc) -> bf16x8 {
+            constexpr int b = decltype(bc)::value;
+            constexpr int t = 4 * (b & 3);
+            uint4 v;
+            v.x = onehot2(row_bcast<t + 0>(R[b >> 2]), col2[b]);
+            v.y = onehot2(row_bcast<t + 1>(R[b >> 2]), col2[b]);
+            v.z = onehot2(row_bcast<t + 2>(R[b >> 2]), col2[b]);
+            v.w = onehot2(row_bcast<t + 3>(R[b >> 2]), col2[b]);
+            if constexpr (masked) {
+                v.x &= m[0]; v.y &= m[1]; v.z &= m[2]; v.w &= m[3];
+            }
+            return __builtin_bit_cast(bf16x8, v);
+        };
+        static_for(std::make_integer_sequence<int, B / 2>{}, [&](auto hb) {
+            constexpr int b = 2 * decltype(hb)::value;
+            const bf16x8 B0 = bcol(std::integral_constant<int, b>{});
+            const bf16x8 B1 = bcol(std::integral_constant<int, b + 1>{});
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B0, acc[b], 0, 0, 0);
+            acc[b + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B1, acc[b + 1], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B0, acc[b], 0, 0, 0);
+            acc[b + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B1, acc[b + 1], 0, 0, 0);
+        });
+        if (((i0 + 32) % kMfmaFlushRows) == 0) flush();
+    };
+    // Chunks [i0, end) of one kind. A chunk first reads its A and row codes from
+    // LDS (its A was loaded during the previous chunk), then starts the load of
+    // the next chunk's A into the other slot, then computes.
+    auto run = [&](auto masked_tag, int &i0, int end, int cend, int c0) {
+        for (; i0 < end; i0 += 32) {
+            uint4 ah, al;
+            read_a(i0, c0, ah, al);
+            uint32_t R[B / 4];
+            read_r(i0, c0, R);
+            if (i0 + 32 < cend) load_a(i0 + 32, c0);
+            chunk(masked_tag, i0, c0, ah, al, R);
+        }
+    };
+
+    const int wg_iend = min(jb * kMfmaCols + kMfmaCols, N);   // rows any wave of the group needs
+    const int my_iend = jt0 < N ? min(jt0 + 16, N) : 0;       // rows this wave needs (i < j <= jt0+15)
+    const int i_diag = (jt0 / 32) * 32;                       // first chunk that may hold i >= j
+
+    for (int c0 = 0; c0 < wg_iend; c0 += RC) {
+        const int rows = min(RC, wg_iend - c0);
+        const int rows32 = (rows + 31) & ~31;                 // chunks read whole 32-row groups
+        // Thread t stages row pairs t + 256k of every individual: all 2 * PK * B
+        // labels are loaded before the first table lookup, so the pass costs one
+        // memory latency; each row pair is written as B consecutive dwords.
+        // Nothing here needs a validity test, only in-bounds addresses: rows past
+        // the pass (only past N, in its last 32-row chunk) meet zero-padded A;
+        // individuals past P are not stored; a label outside [0, N) makes the
+        // finish kernel give its individual -inf whatever its sums. So row and
+        // individual indices are clamped into range, and labels to N - 1.
+        constexpr int PK = RC / 512;
+        const uint32_t rlast = (uint32_t)(rows - 1), lmax = (uint32_t)(N - 1);
+        uint32_t lab[PK][2][B];
+#pragma unroll
+        for (int k = 0; k < PK; ++k) {
+            const uint32_t r = 2u * (uint32_t)(threadIdx.x + 256 * k);
+            const uint32_t r0 = min(r, rlast), r1 = min(r + 1u, rlast);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int32_t *lp = labels + (size_t)min(pbase + b, P - 1) * N + c0;   // uniform
+                lab[k][0][b] = (uint32_t)gld(lp + r0);
+                lab[k][1][b] = (uint32_t)gld(lp + r1);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PK; ++k)                          // all table reads, then all writes
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int b = 0; b < B; ++b) lab[k][h][b] = code(b, (int)min(lab[k][h][b], lmax));
+#pragma unroll
+        for (int k = 0; k < PK; ++k) {
+            const int q = threadIdx.x + 256 * k;
+            if (2 * q < rows32) {
+                uint32_t w[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b)                       // code of row 2q in bits 8..15, of 2q+1 in 24..31
+                    w[mfma_pos<B>(b)] = __builtin_amdgcn_perm(lab[k][1][b], lab[k][0][b], 0x040C000Cu);
+#pragma unroll
+                for (int v = 0; v < B / 4; ++v)
+                    *(uint4 *)(s.rows + (size_t)q * B + 4 * v) = uint4{w[4 * v], w[4 * v + 1], w[4 * v + 2], w[4 * v + 3]};
+            }
+        }
+        __syncthreads();
+        const int cend = min(c0 + RC, my_iend);
+        if (c0 < cend) {
+            load_a(c0, c0);
+            int i0 = c0;
+            const int uend = min(cend, max(c0, i_diag));        // chunks entirely below the diagonal
+            run(std::false_type{}, i0, uend, cend, c0);
+            run(std::true_type{}, i0, cend, cend, c0);
+        }
+        __syncthreads();
+    }
+    flush();
+    if (diag_lane && j < N) {
+        const double cjj = gld(d.C + (size_t)j * N + j);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int p = pbase + b;
+            if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[b], cjj));
+        }
+    }
+    // Restore the table (every reader passed the barrier that closes the row loop).
+    if (g == 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) code(b, (int)lj[b]) = kCodeNone;
+    }
 }
 
 // ---- labels with n_s >= 2 ------------------------------------------------------
@@ -118,7 +375,7 @@ hipError_t launch_nsmask(Tables t, int total_inds, int max_n, int parity, hipStr
 // the 16 x 32 hi tile, then the lo tile, in lane order) filled by direct
 // global-to-LDS loads one chunk ahead, and 1 KB per wave for the column table
 // and the flushes.
-struct MfmaLds {
+struct MfmaLdsPacked {
     uint16_t *rows;
     uint8_t *code;
     unsigned char *aring;
@@ -133,7 +390,7 @@ __device__ __forceinline__ uint32_t shfl_xor32(uint32_t v, int m) {
 // One column block jb (64 stocks, 16 per wave) for the B individuals of batch pb.
 // On entry every code table entry below N holds kCodeNone; it is restored on exit.
 template <int B>
-__device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, int parity, const MfmaLds &s) {
+__device__ __forceinline__ void mfma_block_packed(const InstDesc &d, int jb, int pb, int parity, const MfmaLdsPacked &s) {
     constexpr int RC = mfma_rows(B);                          // rows staged per pass
     constexpr int RS = mfma_row_stride(B);
     constexpr int BU = B / 4;                                 // individuals a lane keeps: g, g + 4, ...
@@ -407,7 +664,7 @@ __device__ __forceinline__ void mfma_block(const InstDesc &d, int jb, int pb, in
 
 // The triangle is folded: column blocks n_jb-1-jp and jp share a workgroup, so every
 // workgroup processes the same number of row chunks.
-template <int B>
+template <int B, bool PACKED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(B == 16 ? 2 : 4))) void k_pairsum_mfma(Tables t, int parity,
                                                                                      int order, int cstride) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -429,20 +686,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(B == 16 ? 2
             if (pb * B + b < d.P) any |= gld(d.route + pb * B + b);
         if (!any) return;
     }
-    const MfmaLds s{(uint16_t *)lds, lds + mfma_lds_code_off(B), lds + mfma_lds_ring_off(B, cstride),
-                    (uint32_t *)(lds + mfma_lds_scratch_off(B, cstride)), cstride};
+    uint8_t *code = lds + mfma_lds_code_off(B, PACKED);
     {
         const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
 #pragma unroll
         for (int b = 0; b < B; ++b)
-            for (int w = threadIdx.x; w < words; w += 256) *(uint32_t *)(s.code + (size_t)b * cstride + 4 * w) = 0xFFFFFFFFu;
+            for (int w = threadIdx.x; w < words; w += 256) *(uint32_t *)(code + (size_t)b * cstride + 4 * w) = 0xFFFFFFFFu;
     }
     __syncthreads();
-    mfma_block<B>(d, n_jb - 1 - jp, pb, parity, s);
-    if (jp != n_jb - 1 - jp) {
-        __syncthreads();
-        mfma_block<B>(d, jp, pb, parity, s);
+    if constexpr (PACKED) {
+        const MfmaLdsPacked s{(uint16_t *)lds, code, lds + mfma_lds_ring_off(B, cstride, true),
+                              (uint32_t *)(lds + mfma_lds_scratch_off(B, cstride, true)), cstride};
+        mfma_block_packed<B>(d, n_jb - 1 - jp, pb, parity, s);
+        if (jp != n_jb - 1 - jp) {
+            __syncthreads();
+            mfma_block_packed<B>(d, jp, pb, parity, s);
+        }
+    } else {
+        const MfmaLdsCols s{(uint32_t *)lds, code, lds + mfma_lds_ring_off(B, cstride, false), cstride};
+        mfma_block_cols<B>(d, n_jb - 1 - jp, pb, parity, s);
+        if (jp != n_jb - 1 - jp) {
+            __syncthreads();
+            mfma_block_cols<B>(d, jp, pb, parity, s);
+        }
     }
+}
+
+template <bool PACKED>
+hipError_t launch_mfma_b(Tables t, int total_tiles, int parity, int ipg, int order, int cstride, size_t lds,
+                         hipStream_t s) {
+    if (ipg == 8)
+        hipLaunchKernelGGL((k_pairsum_mfma<8, PACKED>), dim3(total_tiles), dim3(256), lds, s, t, parity, order, cstride);
+    else if (ipg == 4)
+        hipLaunchKernelGGL((k_pairsum_mfma<4, PACKED>), dim3(total_tiles), dim3(256), lds, s, t, parity, order, cstride);
+    else if (ipg == 16)
+        hipLaunchKernelGGL((k_pairsum_mfma<16, PACKED>), dim3(total_tiles), dim3(256), lds, s, t, parity, order,
+                           cstride);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Variant &v, int max_n,
@@ -450,16 +732,9 @@ hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Vari
     if (total_tiles <= 0) return hipSuccess;
     if (!variant_ok(v, max_n)) return hipErrorInvalidValue;
     const int cstride = (int)mfma_code_stride(max_n);
-    const size_t lds = mfma_lds_bytes(v.ipg, max_n);
-    if (v.ipg == 8)
-        hipLaunchKernelGGL(k_pairsum_mfma<8>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.order, cstride);
-    else if (v.ipg == 4)
-        hipLaunchKernelGGL(k_pairsum_mfma<4>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.order, cstride);
-    else if (v.ipg == 16)
-        hipLaunchKernelGGL(k_pairsum_mfma<16>, dim3(total_tiles), dim3(256), lds, s, t, parity, v.order, cstride);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    const size_t lds = mfma_lds_bytes(v.ipg, max_n, v.packed != 0);
+    if (v.packed) return launch_mfma_b<true>(t, total_tiles, parity, v.ipg, v.order, cstride, lds, s);
+    return launch_mfma_b<false>(t, total_tiles, parity, v.ipg, v.order, cstride, lds, s);
 }
 
 // ---- scaled split parts ----------------------------------------------------------

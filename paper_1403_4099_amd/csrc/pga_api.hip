@@ -25,13 +25,16 @@ namespace {
 // and variant 0 is the default. XCD order 1 (column pairs fastest) comes first because it
 // keeps an individual batch's row labels in the XCD's L2 (a third of the HBM reads of the
 // other orders at N = 1024); then order 2, then round-robin tiles.
-const Variant kFp64Variants[] = {{PGA_FORM_FP64, 8, 1},  {PGA_FORM_FP64, 16, 1}, {PGA_FORM_FP64, 8, 2},
-                                 {PGA_FORM_FP64, 16, 2}, {PGA_FORM_FP64, 8, 0},  {PGA_FORM_FP64, 16, 0}};
-const Variant kMfmaVariants[] = {{PGA_FORM_BF16X2, 8, 1}, {PGA_FORM_BF16X2, 4, 1}, {PGA_FORM_BF16X2, 16, 1},
-                                 {PGA_FORM_BF16X2, 8, 2}, {PGA_FORM_BF16X2, 4, 2}, {PGA_FORM_BF16X2, 16, 2},
-                                 {PGA_FORM_BF16X2, 8, 0}, {PGA_FORM_BF16X2, 4, 0}, {PGA_FORM_BF16X2, 16, 0}};
+const Variant kFp64Variants[] = {{PGA_FORM_FP64, 8, 1, 0},  {PGA_FORM_FP64, 16, 1, 0}, {PGA_FORM_FP64, 8, 2, 0},
+                                 {PGA_FORM_FP64, 16, 2, 0}, {PGA_FORM_FP64, 8, 0, 0},  {PGA_FORM_FP64, 16, 0, 0}};
+// The packed (compacted-column) MFMA kernels come last: at the shapes measured here the
+// column kernel is faster, so ties go to it.
+const Variant kMfmaVariants[] = {{PGA_FORM_BF16X2, 8, 1, 0},  {PGA_FORM_BF16X2, 4, 1, 0}, {PGA_FORM_BF16X2, 16, 1, 0},
+                                 {PGA_FORM_BF16X2, 8, 2, 0},  {PGA_FORM_BF16X2, 4, 2, 0}, {PGA_FORM_BF16X2, 16, 2, 0},
+                                 {PGA_FORM_BF16X2, 8, 0, 0},  {PGA_FORM_BF16X2, 4, 0, 0}, {PGA_FORM_BF16X2, 16, 0, 0},
+                                 {PGA_FORM_BF16X2, 8, 1, 1},  {PGA_FORM_BF16X2, 16, 1, 1}, {PGA_FORM_BF16X2, 4, 1, 1}};
 }  // namespace
-constexpr int kMaxVariants = 9;
+constexpr int kMaxVariants = 12;
 static_assert(sizeof(kMfmaVariants) / sizeof(Variant) <= kMaxVariants &&
                   sizeof(kFp64Variants) / sizeof(Variant) <= kMaxVariants,
               "tuner arrays hold every variant");
@@ -236,7 +239,8 @@ hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, i
     if (form == PGA_FORM_FP64) {
         e = timed(0, s, [&] { return launch_pairsum_fp64(t, sh.tiles, parity, sh.v, s); });
     } else {
-        if ((e = timed(11, s, [&] { return launch_nsmask(t, sh.inds, sh.max_n, parity, s); })) != hipSuccess)
+        if (sh.v.packed &&
+            (e = timed(11, s, [&] { return launch_nsmask(t, sh.inds, sh.max_n, parity, s); })) != hipSuccess)
             return e;
         e = timed(1, s, [&] { return launch_pairsum_mfma(t, sh.tiles, parity, sh.v, sh.max_n, s); });
     }
@@ -270,11 +274,11 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
 struct GraphKey {
     void *ws;
     int32_t *status;
-    int n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus, stop;
+    int n_inst, form, G, tiles, inds, max_n, ipg, order, packed, max_p, sus, stop;
     double frac;
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, order, max_p, sus, stop, frac) <
-               std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles, o.inds, o.max_n, o.ipg, o.order,
+        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, order, packed, max_p, sus, stop, frac) <
+               std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles, o.inds, o.max_n, o.ipg, o.order, o.packed,
                         o.max_p, o.sus, o.stop, o.frac);
     }
 };
@@ -525,11 +529,12 @@ int pga_variant_count(int32_t form) {
     return n > 0 ? n : PGA_ERR_ARG;
 }
 
-int pga_variant_info(int32_t form, int32_t variant, int32_t *ipg, int32_t *xcd_order) {
+int pga_variant_info(int32_t form, int32_t variant, int32_t *ipg, int32_t *xcd_order, int32_t *packed) {
     if (variant < 0 || variant >= n_variants(form)) return PGA_ERR_ARG;
     const Variant v = variant_at(form, variant);
     if (ipg) *ipg = v.ipg;
     if (xcd_order) *xcd_order = v.order;
+    if (packed) *packed = v.packed;
     return PGA_OK;
 }
 
@@ -737,7 +742,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
     int32_t *pf = (int32_t *)(hb + L.pre_off);
     int32_t *pi = pf + (nb + 1);
     pf[0] = pi[0] = 0;
-    Shape sh{nb, 0, 0, 0, Variant{form, 0, 0}, 0, 0, 0, route_frac()};
+    Shape sh{nb, 0, 0, 0, Variant{form, 0, 0, 0}, 0, 0, 0, route_frac()};
     int total_p = 0;
     for (int k = 0; k < n_inst; ++k) {
         sh.max_n = std::max(sh.max_n, (int)inst[k].N);
@@ -813,7 +818,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         HIP_TRY(run_generations(t, sh, form, generations, status, s));
         return PGA_OK;
     }
-    GraphKey key{ws, status, nb, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.order,
+    GraphKey key{ws, status, nb, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.order, sh.v.packed,
                  sh.max_p, sh.sus, sh.stop, sh.frac};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {

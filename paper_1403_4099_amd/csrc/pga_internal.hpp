@@ -54,6 +54,7 @@ constexpr int kFp64Waves = 4;                      // waves per workgroup, one c
 constexpr int kFp64Cols = 64;                      // columns per workgroup
 constexpr int kMfmaWaves = 4;                      // waves per workgroup, 16 columns each
 constexpr int kMfmaCols = 16 * kMfmaWaves;         // columns per workgroup
+constexpr int kMfmaRowCodes = 8192;                // row codes staged in LDS per workgroup (column kernel)
 constexpr int kMfmaFlushRows = 512;                // FP32 accumulators are flushed to FP64 every 512 rows
 constexpr int kMaxLdsBytes = 65536;                // LDS a workgroup may allocate
 
@@ -69,11 +70,14 @@ inline int32_t split_ld(int32_t N) { return (int32_t)(((int64_t)N + 31) / 32 * 3
 //          1 tiles renumbered so each XCD gets a contiguous range, column
 //          pairs fastest (an XCD sees few individual batches, all columns);
 //          2 as 1 with individual batches fastest (an XCD sees few column
-//          pairs, so their C rows stay in its L2).
+//          pairs, so their C rows stay in its L2);
+//   packed MFMA form only: 1 for compacted columns (one per label with
+//          n_s >= 2, packed over the workgroup's individuals), 0 for one
+//          column per stock.
 // Every variant performs the same arithmetic in the same order per
 // individual, so all of them give bitwise identical results.
 struct Variant {
-    int32_t form, ipg, order;
+    int32_t form, ipg, order, packed;
 };
 int n_variants(int form);
 Variant variant_at(int form, int idx);
@@ -83,28 +87,33 @@ inline int32_t pair_tiles(int32_t N, int32_t P, const Variant &v) {
 }
 inline size_t mfma_code_stride(int max_n) { return ((size_t)max_n + 15) / 16 * 16; }
 constexpr int kMfmaASlots = 2;                     // A ring slots per wave (2 KB each) in the MFMA kernel
-// Rows of row codes staged per pass and individual (a multiple of 512), and the
-// per-individual stride of the staged codes in 16-bit words (16 bytes of padding).
+// Rows of row codes staged per pass and individual by the packed kernel (a
+// multiple of 512), and the per-individual stride of its staged codes in 16-bit
+// words (16 bytes of padding).
 __host__ __device__ constexpr int mfma_rows(int ipg) { return 4096 / ipg > 512 ? 4096 / ipg : 512; }
 __host__ __device__ constexpr int mfma_row_stride(int ipg) { return mfma_rows(ipg) + 8; }
-// LDS of the MFMA kernel: row codes, label -> code tables, A rings, 1 KB per wave of scratch.
+// LDS of the MFMA kernels: row codes (the column kernel: kMfmaRowCodes words for all individuals;
+// the packed kernel: [ipg][stride]), label -> code tables, A rings, and for the packed kernel 1 KB
+// per wave of scratch.
 __host__ __device__ constexpr size_t mfma_align256(size_t x) { return (x + 255) / 256 * 256; }
-__host__ __device__ constexpr size_t mfma_lds_code_off(int ipg) {
-    return mfma_align256(sizeof(uint16_t) * (size_t)ipg * mfma_row_stride(ipg));
+__host__ __device__ constexpr size_t mfma_lds_code_off(int ipg, bool packed) {
+    return packed ? mfma_align256(sizeof(uint16_t) * (size_t)ipg * mfma_row_stride(ipg))
+                  : sizeof(uint16_t) * (size_t)kMfmaRowCodes;
 }
-__host__ __device__ constexpr size_t mfma_lds_ring_off(int ipg, int cstride) {
-    return mfma_lds_code_off(ipg) + mfma_align256((size_t)ipg * cstride);
+__host__ __device__ constexpr size_t mfma_lds_ring_off(int ipg, int cstride, bool packed) {
+    return mfma_lds_code_off(ipg, packed) + mfma_align256((size_t)ipg * cstride);
 }
-__host__ __device__ constexpr size_t mfma_lds_scratch_off(int ipg, int cstride) {
-    return mfma_lds_ring_off(ipg, cstride) + (size_t)kMfmaWaves * kMfmaASlots * 2048;
+__host__ __device__ constexpr size_t mfma_lds_scratch_off(int ipg, int cstride, bool packed) {
+    return mfma_lds_ring_off(ipg, cstride, packed) + (size_t)kMfmaWaves * kMfmaASlots * 2048;
 }
-inline size_t mfma_lds_bytes(int ipg, int max_n) {
-    return mfma_lds_scratch_off(ipg, (int)mfma_code_stride(max_n)) + (size_t)kMfmaWaves * 1024;
+inline size_t mfma_lds_bytes(int ipg, int max_n, bool packed) {
+    return mfma_lds_scratch_off(ipg, (int)mfma_code_stride(max_n), packed) + (packed ? (size_t)kMfmaWaves * 1024 : 0);
 }
-static_assert(mfma_lds_code_off(4) % 256 == 0 && mfma_lds_code_off(8) % 256 == 0 && mfma_lds_code_off(16) % 256 == 0,
+static_assert(mfma_lds_code_off(4, true) % 256 == 0 && mfma_lds_code_off(8, true) % 256 == 0 &&
+                  mfma_lds_code_off(16, true) % 256 == 0 && mfma_lds_code_off(8, false) % 256 == 0,
               "MFMA LDS regions are 256-byte aligned");
 inline bool variant_ok(const Variant &v, int max_n) {
-    return v.form != PGA_FORM_BF16X2 || mfma_lds_bytes(v.ipg, max_n) <= (size_t)kMaxLdsBytes;
+    return v.form != PGA_FORM_BF16X2 || mfma_lds_bytes(v.ipg, max_n, v.packed != 0) <= (size_t)kMaxLdsBytes;
 }
 
 struct TilePos {

@@ -100,7 +100,7 @@ def load(path: str = LIB_PATH):
         "pga_timing_reset": ([], ct.c_int),
         "pga_timing_read": ([ct.c_int, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)], ct.c_int),
         "pga_variant_count": ([i32], ct.c_int),
-        "pga_variant_info": ([i32, i32, ct.POINTER(i32), ct.POINTER(i32)], ct.c_int),
+        "pga_variant_info": ([i32, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)], ct.c_int),
         "pga_tune_ws_bytes": ([i32, i32, i32], sz),
         "pga_tune": ([vp, vp, vp, i32, vp, i32, i32, i32, vp, sz, ct.POINTER(i32), ct.POINTER(ct.c_float), vp],
                      ct.c_int),
@@ -276,14 +276,15 @@ def ewma(R: torch.Tensor, S: torch.Tensor, lam: float = 0.98, reset: bool = Fals
 
 # ---------------------------------------------------------------- autotuning
 def variants(form: str = "fp64"):
-    """[(individuals per group, xcd order)] of the pair-sum kernel variants of a form."""
+    """[(individuals per group, xcd order, packed)] of the pair-sum kernel variants of a form."""
     L = load()
     n = L.pga_variant_count(FORMS[form])
     out = []
     for v in range(n):
-        ipg, xcd = ct.c_int32(), ct.c_int32()
-        _check(L.pga_variant_info(FORMS[form], v, ct.byref(ipg), ct.byref(xcd)), "pga_variant_info")
-        out.append((ipg.value, xcd.value))
+        ipg, xcd, packed = ct.c_int32(), ct.c_int32(), ct.c_int32()
+        _check(L.pga_variant_info(FORMS[form], v, ct.byref(ipg), ct.byref(xcd), ct.byref(packed)),
+               "pga_variant_info")
+        out.append((ipg.value, xcd.value, packed.value))
     return out
 
 

@@ -109,9 +109,13 @@ def test_variant_table_host_side(lib):
     assert lib.pga_variant_count(7) == -1
     ipg, xcd = ct.c_int32(), ct.c_int32()
     # variant 0 (the default) deals tiles to the XCDs in contiguous ranges, column pairs fastest
-    assert lib.pga_variant_info(1, 0, ct.byref(ipg), ct.byref(xcd)) == 0 and xcd.value == 1 and ipg.value == 8
-    assert lib.pga_variant_info(0, 0, ct.byref(ipg), ct.byref(xcd)) == 0 and xcd.value == 1 and ipg.value == 8
-    assert lib.pga_variant_info(1, lib.pga_variant_count(1), None, None) == -1
+    pk = ct.c_int32()
+    assert lib.pga_variant_info(1, 0, ct.byref(ipg), ct.byref(xcd), ct.byref(pk)) == 0 and xcd.value == 1 and ipg.value == 8 \
+        and pk.value == 0
+    assert any(lib.pga_variant_info(1, v, None, None, ct.byref(pk)) == 0 and pk.value == 1
+               for v in range(lib.pga_variant_count(1)))            # packed (compacted-column) variants exist
+    assert lib.pga_variant_info(0, 0, ct.byref(ipg), ct.byref(xcd), None) == 0 and xcd.value == 1 and ipg.value == 8
+    assert lib.pga_variant_info(1, lib.pga_variant_count(1), None, None, None) == -1
     assert lib.pga_tune_get(1, 1024, 4096) == 0
     assert lib.pga_tune_set(1, 1024, 4096, 2) == 0
     assert lib.pga_tune_get(1, 1000, 3000) == 2           # same bucket
@@ -122,7 +126,7 @@ def test_variant_table_host_side(lib):
     assert lib.pga_tune_set(1, 1024, 4096, 99) == -1
     # a variant that cannot hold N falls back to variant 0
     big = [v for v in range(lib.pga_variant_count(1))
-           if lib.pga_variant_info(1, v, ct.byref(ipg), ct.byref(xcd)) == 0 and ipg.value == 16][0]
+           if lib.pga_variant_info(1, v, ct.byref(ipg), ct.byref(xcd), None) == 0 and ipg.value == 16][0]
     assert lib.pga_tune_set(1, 4096, 512, big) == 0 and lib.pga_tune_get(1, 4096, 512) == 0
     assert lib.pga_tune_set(1, 4096, 512, -1) == 0
     # tune: argument and workspace errors come back before any GPU work
