@@ -251,16 +251,22 @@ double pga_route_get(void);
  * give bitwise identical results. pga_fitness and pga_evolve use the variant
  * the process-wide tuning table holds for (form, ceil(N / 64), ceil(log2 P))
  * (N: largest N of the call, P: its total number of individuals), variant 0
- * when there is none or when it does not fit N. The table is shared by all
+ * when there is none; a variant whose LDS does not fit N is replaced by the
+ * first variant, in index order, that fits. The table is shared by all
  * threads and devices of the process and guarded by a lock.
  *
- * For PGA_FORM_BF16X2 some variants use the packed kernel (packed = 1):
- * columns only for the labels with n_s >= 2 of each individual's 16-stock
- * tiles, packed over the workgroup's individuals into groups of 16 (fewer
- * MFMAs, more LDS and scalar work; a small extra launch marks the labels with
- * n_s >= 2); the others give every stock its own column.
+ * For PGA_FORM_BF16X2 the variants differ also in their kind:
+ *   kind 2 (the default kernel): one column per stock; the one-hot B operand
+ *     is read from LDS: an 8-bit row mask per (individual, label code, group
+ *     of 8 rows), set by LDS atomics when the rows are staged, indexes a
+ *     256-entry table of bf16 one-hot octets;
+ *   kind 0: one column per stock, the one-hot built in registers;
+ *   kind 1 (packed): columns only for the labels with n_s >= 2 of each
+ *     individual's 16-stock tiles, packed over the workgroup's individuals
+ *     into groups of 16 (fewer MFMAs, more LDS and scalar work; a small extra
+ *     launch marks the labels with n_s >= 2).
  * pga_variant_count: number of variants of `form` (PGA_ERR_ARG for a bad form).
- * pga_variant_info: individuals per group, XCD ordering and packing (each out
+ * pga_variant_info: individuals per group, XCD ordering and kind (each out
  *   pointer nullable) of one variant.
  * pga_tune (SYNC): times every variant that fits N on `labels` (P x N, device):
  *   after 2 reps + 2 warm-up evaluations, three rounds in which each variant
@@ -276,7 +282,7 @@ double pga_route_get(void);
  * pga_tune_get: the variant a call with this (form, N, P) would use. */
 int pga_variant_count(int32_t form);
 int pga_variant_info(int32_t form, int32_t variant, int32_t *individuals_per_group,
-                     int32_t *xcd_order, int32_t *packed);
+                     int32_t *xcd_order, int32_t *kind);
 size_t pga_tune_ws_bytes(int32_t N, int32_t P, int32_t form);
 int pga_tune(const double *C, const uint16_t *C_hi, const uint16_t *C_lo, int32_t N,
              const int32_t *labels, int32_t P, int32_t form, int32_t reps, void *ws,
@@ -374,6 +380,19 @@ int pga_peak_mfma_bf16(float *out, int32_t n_workgroups, int32_t iters, double *
  * caller times the launch. PGA_ERR_ARG for out == NULL, n_workgroups < 1 or
  * iters < 1. Async. */
 int pga_peak_fp64(double *out, int32_t n_workgroups, int32_t iters, double *flops, void *stream);
+
+/* Measurement aid (not part of the method): which pipes of a SIMD overlap.
+ * Launches n_workgroups x 256 threads; every wave runs iters rounds of the
+ * work `mode` selects (bits): 1 = 4 independent v_mfma_f32_16x16x32_bf16;
+ * 2 = the register one-hot of one individual's B operand (4 DPP-broadcast xors
+ * and 4 saturating 16-bit subtracts); 4 = 2 ds_read_b128 of conflict-free
+ * addresses (with bit 1 they feed the MFMAs); 8 = split: even waves do the
+ * MFMA work, odd waves the rest. Accepted modes: 1, 2, 3, 4, 5, 11, 13. Each
+ * wave writes one float to out (device, caller-owned, 4 * n_workgroups
+ * floats). The caller times the launch with events on `stream` and compares
+ * a combined mode's time with its parts' times. PGA_ERR_ARG for out == NULL,
+ * another mode, n_workgroups < 1 or iters < 1. Async. */
+int pga_pipe_mix(float *out, int32_t mode, int32_t n_workgroups, int32_t iters, void *stream);
 
 #ifdef __cplusplus
 }

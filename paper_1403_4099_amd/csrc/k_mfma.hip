@@ -213,24 +213,30 @@ __device__ __forceinline__ void mfma_block_cols(const InstDesc &d, int jb, int p
         }
         const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah);
         const bf16x8 Al = __builtin_bit_cast(bf16x8, al);
-        // B column of individual b: its dword e (rows ik + 2e, +1) is in R[b/4] of lane 4(b%4) + e.
-        auto bcol = [&](auto bc) -> bf16x8 {
+        // B columns of individuals b and b + 1: dword e of b (rows ik + 2e, +1) is in
+        // R[b/4] of lane 4(b%4) + e. All 8 broadcast xors are issued before the 8
+        // saturating subtracts, so no subtract waits on the xor just before it.
+        auto bcols = [&](auto bc, bf16x8 &B0, bf16x8 &B1) {
             constexpr int b = decltype(bc)::value;
-            constexpr int t = 4 * (b & 3);
-            uint4 v;
-            v.x = onehot2(row_bcast<t + 0>(R[b >> 2]), col2[b]);
-            v.y = onehot2(row_bcast<t + 1>(R[b >> 2]), col2[b]);
-            v.z = onehot2(row_bcast<t + 2>(R[b >> 2]), col2[b]);
-            v.w = onehot2(row_bcast<t + 3>(R[b >> 2]), col2[b]);
+            constexpr int t0 = 4 * (b & 3), t1 = 4 * ((b + 1) & 3);
+            const uint32_t r0 = R[b >> 2], r1 = R[(b + 1) >> 2];
+            const uint32_t x0 = row_bcast<t0 + 0>(r0) ^ col2[b], x1 = row_bcast<t0 + 1>(r0) ^ col2[b];
+            const uint32_t x2 = row_bcast<t0 + 2>(r0) ^ col2[b], x3 = row_bcast<t0 + 3>(r0) ^ col2[b];
+            const uint32_t y0 = row_bcast<t1 + 0>(r1) ^ col2[b + 1], y1 = row_bcast<t1 + 1>(r1) ^ col2[b + 1];
+            const uint32_t y2 = row_bcast<t1 + 2>(r1) ^ col2[b + 1], y3 = row_bcast<t1 + 3>(r1) ^ col2[b + 1];
+            uint4 v{onehot2(x0, 0u), onehot2(x1, 0u), onehot2(x2, 0u), onehot2(x3, 0u)};
+            uint4 u{onehot2(y0, 0u), onehot2(y1, 0u), onehot2(y2, 0u), onehot2(y3, 0u)};
             if constexpr (masked) {
                 v.x &= m[0]; v.y &= m[1]; v.z &= m[2]; v.w &= m[3];
+                u.x &= m[0]; u.y &= m[1]; u.z &= m[2]; u.w &= m[3];
             }
-            return __builtin_bit_cast(bf16x8, v);
+            B0 = __builtin_bit_cast(bf16x8, v);
+            B1 = __builtin_bit_cast(bf16x8, u);
         };
         static_for(std::make_integer_sequence<int, B / 2>{}, [&](auto hb) {
             constexpr int b = 2 * decltype(hb)::value;
-            const bf16x8 B0 = bcol(std::integral_constant<int, b>{});
-            const bf16x8 B1 = bcol(std::integral_constant<int, b + 1>{});
+            bf16x8 B0, B1;
+            bcols(std::integral_constant<int, b>{}, B0, B1);
             acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B0, acc[b], 0, 0, 0);
             acc[b + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, B1, acc[b + 1], 0, 0, 0);
             acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B0, acc[b], 0, 0, 0);
@@ -324,6 +330,274 @@ __device__ __forceinline__ void mfma_block_cols(const InstDesc &d, int jb, int p
     if (g == 0) {
 #pragma unroll
         for (int b = 0; b < B; ++b) code(b, (int)lj[b]) = kCodeNone;
+    }
+}
+
+// ---- LUT kernel: the one-hot read from LDS -----------------------------------------
+// Per pass of lut_rows(B) rows, each staged (row, individual) toggles a bit
+// pattern in a 16-bit row mask word: word [chunk][b][code][row group] encodes
+// in bits 4..11 which of the 8 rows of that row group of that 32-row chunk
+// carry the label whose block code is `code` in individual b, as the xor of
+// the patterns lut_pat(e) of those rows e. The patterns are linearly
+// independent, so the word identifies the row set, and shifted by 4 it is the
+// byte offset of the set's entry in the one-hot table at LDS offset 0 (16
+// bytes: the bf16 octet whose element e is 2^-125 for the rows e of the set
+// and 0 otherwise). The patterns' low nibbles differ, so the empty set and
+// the 8 single rows, the common words, fall in different LDS bank groups.
+// The B operand of lane (row group g, column n) for individual b is then one
+// 16-bit LDS read (its column code's word for row group g) and one 16-byte
+// LDS read, with no vector ALU work: LDS reads proceed beside the MFMAs,
+// while vector ALU work and MFMAs of a SIMD take turns. The i < j mask of the
+// diagonal chunk is applied to A (row m of A is stock jt0 + m, the stock whose
+// column meets it on the diagonal).
+// The row masks are double-buffered: while the waves compute pass p from one
+// buffer, each thread stages pass p + 1 into the other (its labels were
+// loaded during pass p - 1), so a pass costs one barrier and no exposed
+// global-memory latency. Patterns are toggled with LDS atomic xors; before
+// staging a pass into a buffer, a thread toggles off the patterns it set
+// there two passes earlier (xors of different threads commute).
+// lut_pat(e): low nibbles 1, 2, 4, 8, 3, 5, 6, 9; high nibble 0 for e < 4, 1 << (e - 4) above.
+__host__ __device__ constexpr uint32_t lut_pat(uint32_t e) {
+    return ((0x96538421u >> (4 * e)) & 0xFu) | (e >= 4 ? (1u << (e - 4)) << 4 : 0u);
+}
+static_assert(lut_pat(0) == 0x01 && lut_pat(3) == 0x08 && lut_pat(4) == 0x13 && lut_pat(5) == 0x25 &&
+                  lut_pat(6) == 0x46 && lut_pat(7) == 0x89,
+              "row patterns");
+
+__device__ __forceinline__ void lut_table_init(unsigned char *lds) {
+    const uint32_t x = threadIdx.x;                           // 256 threads: row set x, one entry each
+    uint32_t v = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v ^= (x >> e & 1u) ? lut_pat(e) : 0u;
+    uint4 o;
+    o.x = ((x & 1u) ? 0x0100u : 0u) | ((x & 2u) ? 0x01000000u : 0u);
+    o.y = ((x & 4u) ? 0x0100u : 0u) | ((x & 8u) ? 0x01000000u : 0u);
+    o.z = ((x & 16u) ? 0x0100u : 0u) | ((x & 32u) ? 0x01000000u : 0u);
+    o.w = ((x & 64u) ? 0x0100u : 0u) | ((x & 128u) ? 0x01000000u : 0u);
+    *(uint4 *)(lds + 16 * v) = o;
+    uint4 *mask = (uint4 *)(lds + kLutMaskOff);               // every row mask word starts clear
+    for (uint32_t w = threadIdx.x; w < 2 * kLutMaskBytes / 16; w += 256) mask[w] = uint4{0u, 0u, 0u, 0u};
+}
+
+// One column block jb (64 stocks, 16 per wave) for the B individuals of batch pb.
+// On entry every code table entry below N holds kCodeNone and every row mask
+// word is 0; both are restored on exit.
+template <int B>
+__device__ __forceinline__ void mfma_block_lut(const InstDesc &d, int jb, int pb, int parity, unsigned char *lds,
+                                               int cstride) {
+    constexpr int RC = lut_rows(B);                           // rows per pass
+    constexpr int NCH = RC / 32;                              // chunks per pass
+    constexpr int SL = RC * B / 256;                          // (row, individual) slots per thread and pass
+    constexpr uint32_t kChunkBytes = (uint32_t)B * 512;       // row mask words of one chunk
+    static_assert(RC * B == 1024 && SL == 4 && NCH % 2 == 0 && NCH * kChunkBytes == kLutMaskBytes,
+                  "LUT pass layout");
+    const int N = d.N, P = d.P, ld = d.ld_h;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, kept scalar
+    const int lane = threadIdx.x & 63;
+    const int n = lane & 15, g = lane >> 4;
+    const int q = 16 * wave + n;                              // position of this lane's stock in the block
+    const int jt0 = jb * kMfmaCols + 16 * wave;
+    const int j = jt0 + n;
+    const int pbase = pb * B;
+    const int32_t *__restrict__ labels = d.pop[parity];
+    const uint16_t *__restrict__ hs = d.hs;
+    const uint16_t *__restrict__ ls = d.ls;
+    uint8_t *const code_tab = lds + kLutCodeOff;
+    auto code = [&](int b, int l) -> uint8_t & { return code_tab[(size_t)b * cstride + l]; };
+
+    // Column labels, registered as in the column kernel (and read again at
+    // the end to restore the table, rather than held in registers).
+    const uint32_t lmax = (uint32_t)(N - 1);
+    const int jc = min(j, N - 1);
+    auto col_label = [&](int b) { return min((uint32_t)gld(labels + (size_t)min(pbase + b, P - 1) * N + jc), lmax); };
+    uint32_t madr[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) madr[b] = col_label(b);
+    if (g == 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) code(b, (int)madr[b]) = (uint8_t)q;
+    }
+    __syncthreads();
+    // LDS address of this lane's row mask word in chunk 0 of the buffer of the
+    // current pass, per individual; `flip` moves it to the other buffer.
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+        madr[b] = (uint32_t)kLutMaskOff + (uint32_t)(b * 64 + code(b, (int)madr[b])) * 8u + 2u * (uint32_t)g;
+    int flip = (int)kLutMaskBytes;
+
+    floatx4 acc[B];
+    double acc64[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc64[b] = 0.0;
+    }
+    const int dreg = n & 3;
+    const bool diag_lane = (n >> 2) == g;
+    auto flush = [&]() {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const float v = dreg == 0 ? acc[b][0] : dreg == 1 ? acc[b][1] : dreg == 2 ? acc[b][2] : acc[b][3];
+            acc64[b] += (double)v;
+            acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    // A goes to registers one chunk ahead (two sets, by chunk parity). The
+    // scaled copies are tile-major: a wave's 16 x 32 block of a part is 1 KB in
+    // lane order. Only waves with jt0 < N load, and then every address is
+    // inside the ld x ld copy.
+    const size_t a_row = (size_t)(jt0 >> 4) * (size_t)(ld >> 5);
+    auto load_a = [&](int i0, uint4 &h, uint4 &l) {
+        const size_t off = (a_row + (size_t)(i0 >> 5)) * 512 + (size_t)lane * 8;
+        h = gld_u4(hs + off);
+        l = gld_u4(ls + off);
+    };
+    uint4 a0h, a0l, a1h, a1l;
+    a1h = a1l = uint4{0u, 0u, 0u, 0u};
+
+    // Staging slots of this thread: slot u is row r_u = (t + 256 u) % RC of
+    // individual b_u = (t + 256 u) / RC of a pass. Per slot, fixed for the block:
+    // srow (r_u), slab (label offset of row 0 of individual b_u), scod (LDS
+    // address of b_u's code table), smsk (address of the slot's row mask word
+    // for code 0 in the first buffer). scur / snxt: the word whose pattern the
+    // slot toggled in the current pass's buffer / in the other buffer
+    // (0xFFFFFFFF: none).
+    const int wg_iend = min(jb * kMfmaCols + kMfmaCols, N);   // rows any wave of the group needs
+    const int my_iend = jt0 < N ? min(jt0 + 16, N) : 0;       // rows this wave needs (i < j <= jt0+15)
+    int srow[SL];
+    uint32_t slab[SL], scod[SL], smsk[SL], scur[SL], snxt[SL], lab[SL];
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+        const int s = threadIdx.x + 256 * u;
+        const int b = s / RC, r = s % RC, rg = (r & 31) >> 3;
+        srow[u] = r;
+        slab[u] = (uint32_t)min(pbase + b, P - 1) * (uint32_t)N;
+        scod[u] = (uint32_t)kLutCodeOff + (uint32_t)(b * cstride);
+        smsk[u] = (uint32_t)kLutMaskOff + (uint32_t)(r >> 5) * kChunkBytes + (uint32_t)b * 512u + 4u * (uint32_t)(rg >> 1);
+        scur[u] = snxt[u] = 0xFFFFFFFFu;
+    }
+    auto slot_pat = [&](int u) {
+        const int r = srow[u], rg = (r & 31) >> 3;
+        return (lut_pat((uint32_t)(r & 7)) << 4) << (16 * (rg & 1));
+    };
+    auto toggle = [&](uint32_t addr, int u) {
+        if (addr != 0xFFFFFFFFu)
+            __hip_atomic_fetch_xor((uint32_t *)(lds + addr), slot_pat(u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    auto load_labels = [&](int c0) {                          // rows past N are clamped (and set nothing)
+#pragma unroll
+        for (int u = 0; u < SL; ++u) lab[u] = (uint32_t)gld(labels + slab[u] + min(c0 + srow[u], N - 1));
+    };
+    // Toggle off the patterns recorded in sa, then toggle on those of the pass
+    // at c0 (labels in lab) in the buffer at byte offset buf from the first,
+    // recording them in sa.
+    auto stage = [&](int c0, uint32_t buf, uint32_t (&sa)[SL]) {
+        uint32_t cd[SL];
+#pragma unroll
+        for (int u = 0; u < SL; ++u) cd[u] = lds[scod[u] + min(lab[u], lmax)];
+#pragma unroll
+        for (int u = 0; u < SL; ++u) toggle(sa[u], u);
+#pragma unroll
+        for (int u = 0; u < SL; ++u) {
+            sa[u] = c0 + srow[u] < wg_iend && cd[u] != kCodeNone ? smsk[u] + buf + cd[u] * 8u : 0xFFFFFFFFu;
+            toggle(sa[u], u);
+        }
+    };
+
+    load_labels(0);
+    stage(0, 0u, scur);
+    if (RC < wg_iend) load_labels(RC);
+    __syncthreads();
+    // Per chunk: read the B operands (their row mask words were read during the
+    // previous chunk), read the next chunk's words, load the next chunk's A
+    // (two register sets by chunk parity; a pass is an even number of chunks,
+    // so the parity carries over), then the MFMAs.
+    if (my_iend > 0) load_a(0, a0h, a0l);
+    uint32_t buf = 0;                                         // byte offset of the current pass's buffer
+    for (int c0 = 0; c0 < wg_iend; c0 += RC) {
+        const int cend = min(c0 + RC, my_iend);
+        if (c0 < cend) {
+            uint32_t idx[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) idx[b] = *(const uint16_t *)(lds + madr[b]);
+            static_for(std::make_integer_sequence<int, NCH>{}, [&](auto chc) {
+                constexpr int ch = decltype(chc)::value;
+                const int i0 = c0 + 32 * ch;
+                if (i0 < cend) {
+                    uint4 &ch_h = (ch & 1) ? a1h : a0h, &ch_l = (ch & 1) ? a1l : a0l;
+                    uint4 &nx_h = (ch & 1) ? a0h : a1h, &nx_l = (ch & 1) ? a0l : a1l;
+                    // The table sits at the start of the dynamic LDS, which is LDS
+                    // address 0 (the kernel has no static LDS; the launcher checks
+                    // this), so a row mask word is the entry's LDS address as is.
+                    pga_u32x4 bo[B];
+#pragma unroll
+                    for (int b = 0; b < B; ++b) bo[b] = *(const __attribute__((address_space(3))) pga_u32x4 *)(size_t)idx[b];
+                    if constexpr (ch + 1 < NCH) {
+                        if (i0 + 32 < cend) {
+#pragma unroll
+                            for (int b = 0; b < B; ++b) idx[b] = *(const uint16_t *)(lds + madr[b] + (ch + 1) * kChunkBytes);
+                        }
+                    }
+                    if (i0 + 32 < my_iend) load_a(i0 + 32, nx_h, nx_l);
+                    if (i0 + 32 > jt0) {                          // the chunk reaches the diagonal: keep i < j
+                        const int ik = i0 + 8 * g;
+                        uint32_t m[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            m[r] = ((ik + 2 * r < j) ? 0xFFFFu : 0u) | ((ik + 2 * r + 1 < j) ? 0xFFFF0000u : 0u);
+                        ch_h.x &= m[0]; ch_h.y &= m[1]; ch_h.z &= m[2]; ch_h.w &= m[3];
+                        ch_l.x &= m[0]; ch_l.y &= m[1]; ch_l.z &= m[2]; ch_l.w &= m[3];
+                    }
+                    const bf16x8 Ah = __builtin_bit_cast(bf16x8, ch_h);
+                    const bf16x8 Al = __builtin_bit_cast(bf16x8, ch_l);
+                    // All hi products, then all lo: consecutive MFMAs are independent.
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, __builtin_bit_cast(bf16x8, bo[b]), acc[b], 0, 0, 0);
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, __builtin_bit_cast(bf16x8, bo[b]), acc[b], 0, 0, 0);
+                    if (((i0 + 32) % kMfmaFlushRows) == 0) flush();
+                }
+            });
+        }
+        // Stage the next pass into the other buffer, start the label loads of
+        // the pass after, then let every wave move on.
+        const int cn = c0 + RC;
+        if (cn < wg_iend) {
+            stage(cn, buf ^ (uint32_t)kLutMaskBytes, snxt);
+            if (cn + RC < wg_iend) load_labels(cn + RC);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SL; ++u) {
+            const uint32_t t = scur[u];
+            scur[u] = snxt[u];
+            snxt[u] = t;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) madr[b] += (uint32_t)flip;
+        flip = -flip;
+        buf ^= (uint32_t)kLutMaskBytes;
+    }
+    // Toggle off the patterns of the last two passes (every wave is past the last barrier).
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+        toggle(scur[u], u);
+        toggle(snxt[u], u);
+    }
+    flush();
+    if (diag_lane && j < N) {
+        const double cjj = gld(d.C + (size_t)j * N + j);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int p = pbase + b;
+            if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[b], cjj));
+        }
+    }
+    if (g == 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) code(b, (int)col_label(b)) = kCodeNone;
     }
 }
 
@@ -664,8 +938,9 @@ __device__ __forceinline__ void mfma_block_packed(const InstDesc &d, int jb, int
 
 // The triangle is folded: column blocks n_jb-1-jp and jp share a workgroup, so every
 // workgroup processes the same number of row chunks.
-template <int B, bool PACKED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(B == 16 ? 2 : 4))) void k_pairsum_mfma(Tables t, int parity,
+template <int B, int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    KIND == kKindLut ? (B == 8 ? 2 : 3) : (B == 16 ? 2 : 4)))) void k_pairsum_mfma(Tables t, int parity,
                                                                                      int order, int cstride) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int total = t.tiles[t.n_inst];                  // the grid may exceed it (capacity-sized graph)
@@ -686,24 +961,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(B == 16 ? 2
             if (pb * B + b < d.P) any |= gld(d.route + pb * B + b);
         if (!any) return;
     }
-    uint8_t *code = lds + mfma_lds_code_off(B, PACKED);
+    uint8_t *code = lds + mfma_lds_code_off(B, KIND);
     {
         const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
 #pragma unroll
         for (int b = 0; b < B; ++b)
             for (int w = threadIdx.x; w < words; w += 256) *(uint32_t *)(code + (size_t)b * cstride + 4 * w) = 0xFFFFFFFFu;
     }
+    if constexpr (KIND == kKindLut) lut_table_init(lds);
     __syncthreads();
-    if constexpr (PACKED) {
-        const MfmaLdsPacked s{(uint16_t *)lds, code, lds + mfma_lds_ring_off(B, cstride, true),
-                              (uint32_t *)(lds + mfma_lds_scratch_off(B, cstride, true)), cstride};
+    if constexpr (KIND == kKindPacked) {
+        const MfmaLdsPacked s{(uint16_t *)lds, code, lds + mfma_lds_ring_off(B, cstride, KIND),
+                              (uint32_t *)(lds + mfma_lds_scratch_off(B, cstride, KIND)), cstride};
         mfma_block_packed<B>(d, n_jb - 1 - jp, pb, parity, s);
         if (jp != n_jb - 1 - jp) {
             __syncthreads();
             mfma_block_packed<B>(d, jp, pb, parity, s);
         }
+    } else if constexpr (KIND == kKindLut) {
+        mfma_block_lut<B>(d, n_jb - 1 - jp, pb, parity, lds, cstride);
+        if (jp != n_jb - 1 - jp) {
+            __syncthreads();
+            mfma_block_lut<B>(d, jp, pb, parity, lds, cstride);
+        }
     } else {
-        const MfmaLdsCols s{(uint32_t *)lds, code, lds + mfma_lds_ring_off(B, cstride, false), cstride};
+        const MfmaLdsCols s{(uint32_t *)lds, code, lds + mfma_lds_ring_off(B, cstride, KIND), cstride};
         mfma_block_cols<B>(d, n_jb - 1 - jp, pb, parity, s);
         if (jp != n_jb - 1 - jp) {
             __syncthreads();
@@ -712,18 +994,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(B == 16 ? 2
     }
 }
 
-template <bool PACKED>
+// The LUT kernel addresses its table by absolute LDS address, which requires
+// the dynamic LDS to start at address 0: no static LDS in the kernel.
+template <int B, int KIND>
+bool mfma_static_lds_ok() {
+    if constexpr (KIND != kKindLut) {
+        return true;
+    } else {
+        static const bool ok = [] {
+            hipFuncAttributes a{};
+            return hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_pairsum_mfma<B, KIND>)) == hipSuccess &&
+                   a.sharedSizeBytes == 0;
+        }();
+        return ok;
+    }
+}
+
+template <int KIND>
 hipError_t launch_mfma_b(Tables t, int total_tiles, int parity, int ipg, int order, int cstride, size_t lds,
                          hipStream_t s) {
-    if (ipg == 8)
-        hipLaunchKernelGGL((k_pairsum_mfma<8, PACKED>), dim3(total_tiles), dim3(256), lds, s, t, parity, order, cstride);
-    else if (ipg == 4)
-        hipLaunchKernelGGL((k_pairsum_mfma<4, PACKED>), dim3(total_tiles), dim3(256), lds, s, t, parity, order, cstride);
-    else if (ipg == 16)
-        hipLaunchKernelGGL((k_pairsum_mfma<16, PACKED>), dim3(total_tiles), dim3(256), lds, s, t, parity, order,
-                           cstride);
-    else
+    if (ipg == 8) {
+        if (!mfma_static_lds_ok<8, KIND>()) return hipErrorInvalidKernelFile;
+        hipLaunchKernelGGL((k_pairsum_mfma<8, KIND>), dim3(total_tiles), dim3(256), lds, s, t, parity, order, cstride);
+    } else if (ipg == 4) {
+        if (!mfma_static_lds_ok<4, KIND>()) return hipErrorInvalidKernelFile;
+        hipLaunchKernelGGL((k_pairsum_mfma<4, KIND>), dim3(total_tiles), dim3(256), lds, s, t, parity, order, cstride);
+    } else if (ipg == 16 && KIND != kKindLut) {               // the LUT kernel has no 16-individual form
+        if constexpr (KIND != kKindLut)
+            hipLaunchKernelGGL((k_pairsum_mfma<16, KIND>), dim3(total_tiles), dim3(256), lds, s, t, parity, order,
+                               cstride);
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -732,9 +1034,10 @@ hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Vari
     if (total_tiles <= 0) return hipSuccess;
     if (!variant_ok(v, max_n)) return hipErrorInvalidValue;
     const int cstride = (int)mfma_code_stride(max_n);
-    const size_t lds = mfma_lds_bytes(v.ipg, max_n, v.packed != 0);
-    if (v.packed) return launch_mfma_b<true>(t, total_tiles, parity, v.ipg, v.order, cstride, lds, s);
-    return launch_mfma_b<false>(t, total_tiles, parity, v.ipg, v.order, cstride, lds, s);
+    const size_t lds = mfma_lds_bytes(v.ipg, max_n, v.kind);
+    if (v.kind == kKindPacked) return launch_mfma_b<kKindPacked>(t, total_tiles, parity, v.ipg, v.order, cstride, lds, s);
+    if (v.kind == kKindLut) return launch_mfma_b<kKindLut>(t, total_tiles, parity, v.ipg, v.order, cstride, lds, s);
+    return launch_mfma_b<kKindCols>(t, total_tiles, parity, v.ipg, v.order, cstride, lds, s);
 }
 
 // ---- scaled split parts ----------------------------------------------------------

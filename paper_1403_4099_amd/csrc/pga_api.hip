@@ -27,14 +27,16 @@ namespace {
 // other orders at N = 1024); then order 2, then round-robin tiles.
 const Variant kFp64Variants[] = {{PGA_FORM_FP64, 8, 1, 0},  {PGA_FORM_FP64, 16, 1, 0}, {PGA_FORM_FP64, 8, 2, 0},
                                  {PGA_FORM_FP64, 16, 2, 0}, {PGA_FORM_FP64, 8, 0, 0},  {PGA_FORM_FP64, 16, 0, 0}};
-// The packed (compacted-column) MFMA kernels come last: at the shapes measured here the
-// column kernel is faster, so ties go to it.
-const Variant kMfmaVariants[] = {{PGA_FORM_BF16X2, 8, 1, 0},  {PGA_FORM_BF16X2, 4, 1, 0}, {PGA_FORM_BF16X2, 16, 1, 0},
-                                 {PGA_FORM_BF16X2, 8, 2, 0},  {PGA_FORM_BF16X2, 4, 2, 0}, {PGA_FORM_BF16X2, 16, 2, 0},
-                                 {PGA_FORM_BF16X2, 8, 0, 0},  {PGA_FORM_BF16X2, 4, 0, 0}, {PGA_FORM_BF16X2, 16, 0, 0},
-                                 {PGA_FORM_BF16X2, 8, 1, 1},  {PGA_FORM_BF16X2, 16, 1, 1}, {PGA_FORM_BF16X2, 4, 1, 1}};
+// MFMA kernels: the register one-hot column kernel first (the fastest at the
+// shapes measured here), then the LDS-table column kernel, then the packed
+// (compacted-column) kernel.
+const Variant kMfmaVariants[] = {
+    {PGA_FORM_BF16X2, 8, 1, kKindCols}, {PGA_FORM_BF16X2, 4, 1, kKindCols},   {PGA_FORM_BF16X2, 16, 1, kKindCols},
+    {PGA_FORM_BF16X2, 8, 2, kKindCols}, {PGA_FORM_BF16X2, 4, 2, kKindCols},   {PGA_FORM_BF16X2, 8, 0, kKindCols},
+    {PGA_FORM_BF16X2, 4, 1, kKindLut},  {PGA_FORM_BF16X2, 8, 1, kKindLut},    {PGA_FORM_BF16X2, 4, 2, kKindLut},
+    {PGA_FORM_BF16X2, 8, 1, kKindPacked}, {PGA_FORM_BF16X2, 16, 1, kKindPacked}, {PGA_FORM_BF16X2, 4, 1, kKindPacked}};
 }  // namespace
-constexpr int kMaxVariants = 12;
+constexpr int kMaxVariants = 16;
 static_assert(sizeof(kMfmaVariants) / sizeof(Variant) <= kMaxVariants &&
                   sizeof(kFp64Variants) / sizeof(Variant) <= kMaxVariants,
               "tuner arrays hold every variant");
@@ -126,7 +128,8 @@ double route_frac() {
 // ---- tuning table ----------------------------------------------------------------
 // Variant index per (form, ceil(N / 64), ceil(log2 P)); N is the largest N of
 // a launch and P its total number of individuals. Filled by pga_tune or
-// pga_tune_set; absent keys use variant 0.
+// pga_tune_set; absent keys use variant 0, and a variant whose LDS does not fit
+// N is replaced by the first one that does.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, int> g_tune;
 
@@ -143,8 +146,10 @@ int pick_variant(int form, int max_n, int total_p) {
         auto it = g_tune.find(tune_key(form, max_n, total_p));
         if (it != g_tune.end()) v = it->second;
     }
-    if (v < 0 || v >= n_variants(form) || !variant_ok(variant_at(form, v), max_n)) v = 0;
-    return v;
+    if (v >= 0 && v < n_variants(form) && variant_ok(variant_at(form, v), max_n)) return v;
+    for (v = 0; v < n_variants(form); ++v)                   // the first variant whose LDS fits max_n
+        if (variant_ok(variant_at(form, v), max_n)) return v;
+    return 0;
 }
 
 // ---- workspace layout ----------------------------------------------------------
@@ -239,7 +244,7 @@ hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, i
     if (form == PGA_FORM_FP64) {
         e = timed(0, s, [&] { return launch_pairsum_fp64(t, sh.tiles, parity, sh.v, s); });
     } else {
-        if (sh.v.packed &&
+        if (sh.v.kind == kKindPacked &&
             (e = timed(11, s, [&] { return launch_nsmask(t, sh.inds, sh.max_n, parity, s); })) != hipSuccess)
             return e;
         e = timed(1, s, [&] { return launch_pairsum_mfma(t, sh.tiles, parity, sh.v, sh.max_n, s); });
@@ -274,11 +279,11 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
 struct GraphKey {
     void *ws;
     int32_t *status;
-    int n_inst, form, G, tiles, inds, max_n, ipg, order, packed, max_p, sus, stop;
+    int n_inst, form, G, tiles, inds, max_n, ipg, order, kind, max_p, sus, stop;
     double frac;
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, order, packed, max_p, sus, stop, frac) <
-               std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles, o.inds, o.max_n, o.ipg, o.order, o.packed,
+        return std::tie(ws, status, n_inst, form, G, tiles, inds, max_n, ipg, order, kind, max_p, sus, stop, frac) <
+               std::tie(o.ws, o.status, o.n_inst, o.form, o.G, o.tiles, o.inds, o.max_n, o.ipg, o.order, o.kind,
                         o.max_p, o.sus, o.stop, o.frac);
     }
 };
@@ -306,6 +311,7 @@ hipError_t launch_peak_mfma(float *out, int n_workgroups, int iters, hipStream_t
 double peak_mfma_flops(int n_workgroups, int iters);
 hipError_t launch_peak_fp64(double *out, int n_workgroups, int iters, hipStream_t s);
 double peak_fp64_flops(int n_workgroups, int iters);
+hipError_t launch_pipe_mix(float *out, int mode, int n_workgroups, int iters, hipStream_t s);
 }  // namespace pga
 
 extern "C" {
@@ -529,12 +535,12 @@ int pga_variant_count(int32_t form) {
     return n > 0 ? n : PGA_ERR_ARG;
 }
 
-int pga_variant_info(int32_t form, int32_t variant, int32_t *ipg, int32_t *xcd_order, int32_t *packed) {
+int pga_variant_info(int32_t form, int32_t variant, int32_t *ipg, int32_t *xcd_order, int32_t *kind) {
     if (variant < 0 || variant >= n_variants(form)) return PGA_ERR_ARG;
     const Variant v = variant_at(form, variant);
     if (ipg) *ipg = v.ipg;
     if (xcd_order) *xcd_order = v.order;
-    if (packed) *packed = v.packed;
+    if (kind) *kind = v.kind;
     return PGA_OK;
 }
 
@@ -818,7 +824,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
         HIP_TRY(run_generations(t, sh, form, generations, status, s));
         return PGA_OK;
     }
-    GraphKey key{ws, status, nb, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.order, sh.v.packed,
+    GraphKey key{ws, status, nb, form, generations, sh.tiles, sh.inds, sh.max_n, sh.v.ipg, sh.v.order, sh.v.kind,
                  sh.max_p, sh.sus, sh.stop, sh.frac};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
@@ -942,6 +948,13 @@ int pga_peak_fp64(double *out, int32_t n_workgroups, int32_t iters, double *flop
     if (!out || n_workgroups < 1 || iters < 1) return PGA_ERR_ARG;
     if (flops) *flops = pga::peak_fp64_flops(n_workgroups, iters);
     HIP_TRY(pga::launch_peak_fp64(out, n_workgroups, iters, (hipStream_t)stream));
+    return PGA_OK;
+}
+
+int pga_pipe_mix(float *out, int32_t mode, int32_t n_workgroups, int32_t iters, void *stream) {
+    const bool known = mode == 1 || mode == 2 || mode == 3 || mode == 4 || mode == 5 || mode == 11 || mode == 13;
+    if (!out || !known || n_workgroups < 1 || iters < 1) return PGA_ERR_ARG;
+    HIP_TRY(pga::launch_pipe_mix(out, mode, n_workgroups, iters, (hipStream_t)stream));
     return PGA_OK;
 }
 

@@ -71,13 +71,22 @@ inline int32_t split_ld(int32_t N) { return (int32_t)(((int64_t)N + 31) / 32 * 3
 //          pairs fastest (an XCD sees few individual batches, all columns);
 //          2 as 1 with individual batches fastest (an XCD sees few column
 //          pairs, so their C rows stay in its L2);
-//   packed MFMA form only: 1 for compacted columns (one per label with
-//          n_s >= 2, packed over the workgroup's individuals), 0 for one
-//          column per stock.
+//   kind   MFMA form only: how the B operand (the one-hot) is made and how
+//          many columns there are:
+//          kKindCols   one column per stock, one-hot built in registers from
+//                      row codes (a DPP broadcast, an xor and a saturating
+//                      subtract per two elements);
+//          kKindPacked compacted columns (one per label with n_s >= 2, packed
+//                      over the workgroup's individuals), one-hot built in
+//                      registers from each lane's own row codes;
+//          kKindLut    one column per stock, one-hot read from LDS: an 8-bit
+//                      row mask per (individual, label code, row group) indexes
+//                      a 256-entry table of bf16 one-hot octets.
 // Every variant performs the same arithmetic in the same order per
 // individual, so all of them give bitwise identical results.
+constexpr int32_t kKindCols = 0, kKindPacked = 1, kKindLut = 2;
 struct Variant {
-    int32_t form, ipg, order, packed;
+    int32_t form, ipg, order, kind;
 };
 int n_variants(int form);
 Variant variant_at(int form, int idx);
@@ -92,28 +101,45 @@ constexpr int kMfmaASlots = 2;                     // A ring slots per wave (2 K
 // words (16 bytes of padding).
 __host__ __device__ constexpr int mfma_rows(int ipg) { return 4096 / ipg > 512 ? 4096 / ipg : 512; }
 __host__ __device__ constexpr int mfma_row_stride(int ipg) { return mfma_rows(ipg) + 8; }
-// LDS of the MFMA kernels: row codes (the column kernel: kMfmaRowCodes words for all individuals;
-// the packed kernel: [ipg][stride]), label -> code tables, A rings, and for the packed kernel 1 KB
-// per wave of scratch.
+// LDS of the MFMA kernels.
+// Column and packed kernels: row codes (the column kernel: kMfmaRowCodes words
+// for all individuals; the packed kernel: [ipg][stride]), label -> code tables,
+// A rings, and for the packed kernel 1 KB per wave of scratch.
+// LUT kernel, at fixed offsets: the one-hot table (256 x 16 bytes), two
+// buffers of row masks (16 KB each: [chunk][ipg][64 codes][4 row groups]
+// 16-bit words of lut_rows(ipg) rows, one pass), then the label -> code tables.
 __host__ __device__ constexpr size_t mfma_align256(size_t x) { return (x + 255) / 256 * 256; }
-__host__ __device__ constexpr size_t mfma_lds_code_off(int ipg, bool packed) {
-    return packed ? mfma_align256(sizeof(uint16_t) * (size_t)ipg * mfma_row_stride(ipg))
-                  : sizeof(uint16_t) * (size_t)kMfmaRowCodes;
+constexpr size_t kLutTableBytes = 256 * 16;
+constexpr size_t kLutMaskOff = kLutTableBytes;
+constexpr size_t kLutMaskBytes = 16384;             // one buffer
+constexpr size_t kLutCodeOff = kLutMaskOff + 2 * kLutMaskBytes;
+__host__ __device__ constexpr int lut_rows(int ipg) { return (int)(kLutMaskBytes / 512) * 32 / ipg; }
+__host__ __device__ constexpr size_t mfma_lds_code_off(int ipg, int kind) {
+    return kind == kKindLut      ? kLutCodeOff
+           : kind == kKindPacked ? mfma_align256(sizeof(uint16_t) * (size_t)ipg * mfma_row_stride(ipg))
+                                 : sizeof(uint16_t) * (size_t)kMfmaRowCodes;
 }
-__host__ __device__ constexpr size_t mfma_lds_ring_off(int ipg, int cstride, bool packed) {
-    return mfma_lds_code_off(ipg, packed) + mfma_align256((size_t)ipg * cstride);
+__host__ __device__ constexpr size_t mfma_lds_ring_off(int ipg, int cstride, int kind) {
+    return mfma_lds_code_off(ipg, kind) + mfma_align256((size_t)ipg * cstride);
 }
-__host__ __device__ constexpr size_t mfma_lds_scratch_off(int ipg, int cstride, bool packed) {
-    return mfma_lds_ring_off(ipg, cstride, packed) + (size_t)kMfmaWaves * kMfmaASlots * 2048;
+__host__ __device__ constexpr size_t mfma_lds_scratch_off(int ipg, int cstride, int kind) {
+    return mfma_lds_ring_off(ipg, cstride, kind) + (size_t)kMfmaWaves * kMfmaASlots * 2048;
 }
-inline size_t mfma_lds_bytes(int ipg, int max_n, bool packed) {
-    return mfma_lds_scratch_off(ipg, (int)mfma_code_stride(max_n), packed) + (packed ? (size_t)kMfmaWaves * 1024 : 0);
+inline size_t mfma_lds_bytes(int ipg, int max_n, int kind) {
+    const int cstride = (int)mfma_code_stride(max_n);
+    if (kind == kKindLut) return kLutCodeOff + (size_t)ipg * cstride;
+    return mfma_lds_scratch_off(ipg, cstride, kind) + (kind == kKindPacked ? (size_t)kMfmaWaves * 1024 : 0);
 }
-static_assert(mfma_lds_code_off(4, true) % 256 == 0 && mfma_lds_code_off(8, true) % 256 == 0 &&
-                  mfma_lds_code_off(16, true) % 256 == 0 && mfma_lds_code_off(8, false) % 256 == 0,
+static_assert(mfma_lds_code_off(4, kKindPacked) % 256 == 0 && mfma_lds_code_off(8, kKindPacked) % 256 == 0 &&
+                  mfma_lds_code_off(16, kKindPacked) % 256 == 0 && mfma_lds_code_off(8, kKindCols) % 256 == 0 &&
+                  kLutMaskOff % 256 == 0 && kLutCodeOff % 256 == 0,
               "MFMA LDS regions are 256-byte aligned");
+static_assert(lut_rows(4) % 32 == 0 && lut_rows(8) % 32 == 0 && lut_rows(16) % 32 == 0 &&
+                  lut_rows(8) * 8 / 32 * 512 == (int)kLutMaskBytes,
+              "a LUT pass is whole 32-row chunks and its row masks fill the mask region");
 inline bool variant_ok(const Variant &v, int max_n) {
-    return v.form != PGA_FORM_BF16X2 || mfma_lds_bytes(v.ipg, max_n, v.packed != 0) <= (size_t)kMaxLdsBytes;
+    return v.form != PGA_FORM_BF16X2 ||
+           (mfma_lds_bytes(v.ipg, max_n, v.kind) <= (size_t)kMaxLdsBytes && (v.kind != kKindLut || v.ipg <= 8));
 }
 
 struct TilePos {

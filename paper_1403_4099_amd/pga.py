@@ -41,7 +41,7 @@ SYMBOLS = [
     "pga_best_ws_bytes", "pga_best", "pga_timing_enable", "pga_timing_reset", "pga_timing_read",
     "pga_variant_count", "pga_variant_info", "pga_tune_ws_bytes", "pga_tune", "pga_tune_set",
     "pga_tune_get", "pga_tune_save", "pga_tune_load", "pga_ewma_ws_bytes", "pga_ewma", "pga_peak_mfma_bf16", "pga_route_set",
-    "pga_route_get", "pga_fitness_noalloc", "pga_fitness_noalloc_max_bytes", "pga_peak_fp64",
+    "pga_route_get", "pga_fitness_noalloc", "pga_fitness_noalloc_max_bytes", "pga_peak_fp64", "pga_pipe_mix",
 ]
 
 
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
         "pga_ewma": ([vp, i32, i32, i32, ct.c_double, i32, vp, vp, vp, vp, vp, vp, sz, vp], ct.c_int),
         "pga_peak_mfma_bf16": ([vp, i32, i32, ct.POINTER(ct.c_double), vp], ct.c_int),
         "pga_peak_fp64": ([vp, i32, i32, ct.POINTER(ct.c_double), vp], ct.c_int),
+        "pga_pipe_mix": ([vp, i32, i32, i32, vp], ct.c_int),
         "pga_route_set": ([ct.c_double], ct.c_int),
         "pga_route_get": ([], ct.c_double),
         "pga_fitness_noalloc": ([vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp], ct.c_int),
@@ -276,15 +277,17 @@ def ewma(R: torch.Tensor, S: torch.Tensor, lam: float = 0.98, reset: bool = Fals
 
 # ---------------------------------------------------------------- autotuning
 def variants(form: str = "fp64"):
-    """[(individuals per group, xcd order, packed)] of the pair-sum kernel variants of a form."""
+    """[(individuals per group, xcd order, kind)] of the pair-sum kernel variants of a form
+    (kind, MFMA form only: 0 per-stock columns, one-hot built in registers; 1 compacted columns;
+    2 per-stock columns, one-hot read from an LDS table)."""
     L = load()
     n = L.pga_variant_count(FORMS[form])
     out = []
     for v in range(n):
-        ipg, xcd, packed = ct.c_int32(), ct.c_int32(), ct.c_int32()
-        _check(L.pga_variant_info(FORMS[form], v, ct.byref(ipg), ct.byref(xcd), ct.byref(packed)),
+        ipg, xcd, kind = ct.c_int32(), ct.c_int32(), ct.c_int32()
+        _check(L.pga_variant_info(FORMS[form], v, ct.byref(ipg), ct.byref(xcd), ct.byref(kind)),
                "pga_variant_info")
-        out.append((ipg.value, xcd.value, packed.value))
+        out.append((ipg.value, xcd.value, kind.value))
     return out
 
 
@@ -521,6 +524,35 @@ def peak_fp64(n_workgroups: int = 4096, iters: int = 2000, reps: int = 5) -> flo
     if not bool(torch.isfinite(out).all()):
         raise PgaError("pga_peak_fp64: non-finite sink values")
     return flops.value / best / 1e12
+
+
+PIPE_MIX_MODES = {"mfma": 1, "valu": 2, "mfma+valu": 3, "lds": 4, "mfma+lds": 5,
+                  "mfma|valu": 11, "mfma|lds": 13}
+
+
+def pipe_mix(n_workgroups: int = 2048, iters: int = 2000, reps: int = 3) -> dict:
+    """Cycles per round per wave on one SIMD of each pipe-mix mode (pga_pipe_mix): the best of
+    `reps` timed launches, converted at 2.4 GHz over the GPU's SIMDs (4 per compute unit).
+    "a+b" runs both in every wave, "a|b" splits them over alternate waves."""
+    out = torch.empty(4 * n_workgroups, dtype=torch.float32, device="cuda")
+    L = load()
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    waves_per_simd = n_workgroups * 4 / simds
+    res = {}
+    for name, mode in PIPE_MIX_MODES.items():
+        _check(L.pga_pipe_mix(_ptr(out), mode, n_workgroups, 10, _stream()), "pga_pipe_mix")
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _check(L.pga_pipe_mix(_ptr(out), mode, n_workgroups, iters, _stream()), "pga_pipe_mix")
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        res[name] = best * 2.4e9 / (iters * waves_per_simd)
+    if not bool(torch.isfinite(out).all()):
+        raise PgaError("pga_pipe_mix: non-finite sink values")
+    return res
 
 
 # ---------------------------------------------------------------- timing

@@ -109,11 +109,15 @@ def test_variant_table_host_side(lib):
     assert lib.pga_variant_count(7) == -1
     ipg, xcd = ct.c_int32(), ct.c_int32()
     # variant 0 (the default) deals tiles to the XCDs in contiguous ranges, column pairs fastest
-    pk = ct.c_int32()
-    assert lib.pga_variant_info(1, 0, ct.byref(ipg), ct.byref(xcd), ct.byref(pk)) == 0 and xcd.value == 1 and ipg.value == 8 \
-        and pk.value == 0
-    assert any(lib.pga_variant_info(1, v, None, None, ct.byref(pk)) == 0 and pk.value == 1
-               for v in range(lib.pga_variant_count(1)))            # packed (compacted-column) variants exist
+    # MFMA kinds: 0 register one-hot (the default), 1 compacted columns, 2 one-hot from the LDS table
+    kind = ct.c_int32()
+    assert lib.pga_variant_info(1, 0, ct.byref(ipg), ct.byref(xcd), ct.byref(kind)) == 0 and xcd.value == 1 \
+        and ipg.value == 8 and kind.value == 0
+    kinds = set()
+    for v in range(lib.pga_variant_count(1)):
+        assert lib.pga_variant_info(1, v, None, None, ct.byref(kind)) == 0
+        kinds.add(kind.value)
+    assert kinds == {0, 1, 2}
     assert lib.pga_variant_info(0, 0, ct.byref(ipg), ct.byref(xcd), None) == 0 and xcd.value == 1 and ipg.value == 8
     assert lib.pga_variant_info(1, lib.pga_variant_count(1), None, None, None) == -1
     assert lib.pga_tune_get(1, 1024, 4096) == 0
@@ -124,11 +128,14 @@ def test_variant_table_host_side(lib):
     assert lib.pga_tune_set(1, 1024, 4096, -1) == 0
     assert lib.pga_tune_get(1, 1024, 4096) == 0
     assert lib.pga_tune_set(1, 1024, 4096, 99) == -1
-    # a variant that cannot hold N falls back to variant 0
+    # a variant that cannot hold N falls back to the first variant that can
     big = [v for v in range(lib.pga_variant_count(1))
            if lib.pga_variant_info(1, v, ct.byref(ipg), ct.byref(xcd), None) == 0 and ipg.value == 16][0]
-    assert lib.pga_tune_set(1, 4096, 512, big) == 0 and lib.pga_tune_get(1, 4096, 512) == 0
+    first_fit = lib.pga_tune_get(1, 4096, 512)
+    assert first_fit != big
+    assert lib.pga_tune_set(1, 4096, 512, big) == 0 and lib.pga_tune_get(1, 4096, 512) == first_fit
     assert lib.pga_tune_set(1, 4096, 512, -1) == 0
+    assert lib.pga_tune_get(1, 1024, 512) == 0
     # tune: argument and workspace errors come back before any GPU work
     assert lib.pga_tune(None, None, None, 64, None, 64, 0, 0, None, 0, None, None, None) == -1
     fake = ct.c_void_p(0x1000)
@@ -152,6 +159,12 @@ def test_peak_mfma_rejects_bad_arguments():
     buf = ct.create_string_buffer(64)
     assert L.pga_peak_mfma_bf16(ct.cast(buf, ct.c_void_p), 0, 1, None, None) == -1  # PGA_ERR_ARG
     assert L.pga_peak_mfma_bf16(ct.cast(buf, ct.c_void_p), 1, 0, None, None) == -1  # PGA_ERR_ARG
+    # the pipe-mix loops: a null sink, an unknown mode or an empty launch
+    assert L.pga_pipe_mix(None, 1, 1, 1, None) == -1
+    for mode in (0, 6, 7, 8, 9, 12, 15, 16, -1):
+        assert L.pga_pipe_mix(ct.cast(buf, ct.c_void_p), mode, 1, 1, None) == -1, mode
+    assert L.pga_pipe_mix(ct.cast(buf, ct.c_void_p), 1, 0, 1, None) == -1
+    assert L.pga_pipe_mix(ct.cast(buf, ct.c_void_p), 1, 1, 0, None) == -1
 
 
 def test_route_limit_is_host_state_with_checked_range(lib):
