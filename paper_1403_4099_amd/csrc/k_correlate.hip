@@ -59,27 +59,28 @@ hipError_t launch_row_stats(const double *R, int N, int T, int64_t ld, double *m
 // G_ij = sum_t x_it x_jt over the upper triangle of 128 x 128 output tiles,
 // each tile's t range split into S slices (gram_split: about one workgroup per
 // CU), one workgroup per (tile, slice):
-//   * the workgroup stages x of its 128 + 128 rows, 8 samples at a time, in LDS
-//     (two buffers: the next chunk's global loads are in flight while the
-//     current one is multiplied); x = R - mean for the correlation, the
-//     weighted returns as they are for the EWMA covariance;
+//   * the workgroup stages x of its 128 + 128 rows, 16 samples at a time, in
+//     LDS (two buffers: the next chunk's global loads are in flight while the
+//     current one is multiplied, 64 MFMAs per wave and chunk, enough to cover
+//     a memory latency); x = R - mean for the correlation, the weighted
+//     returns as they are for the EWMA covariance;
 //   * wave w owns the 64 x 64 quadrant (w / 2, w % 2) of the tile: sixteen
 //     16 x 16 blocks, each accumulated by v_mfma_f64_16x16x4_f64 (lane l
 //     supplies A[l % 16][l / 16] and B[l / 16][l % 16]: row l % 16 of A and
-//     column l % 16 of B at the samples t0 + 2 (l / 16) and + 1, one per MFMA,
-//     so both operands see the same t); 32 MFMAs per staged chunk and wave;
+//     column l % 16 of B at the samples t0 + 4 (l / 16) + e, e = 0..3, one per
+//     MFMA, so both operands see the same t);
 //   * the slice's 128 x 128 partial Gram goes to the workspace; a finish kernel
-//     (one workgroup per 64 x 64 quarter of a tile) adds the S slices in slice
+//     (one workgroup per 32 x 32 block of a tile) adds the S slices in slice
 //     order (a fixed order: the result does not depend on timing), applies the
-//     normalisation and writes the quarter and its mirror image through LDS,
+//     normalisation and writes the block and its mirror image through LDS,
 //     both coalesced.
 // A 128 x 128 tile moves half the bytes per flop of a 64 x 64 one: at N = 1024,
 // T = 4096 the rows of R are read from the shared caches about 9 times in all.
 typedef double gram_d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 128;                // output tile edge
-constexpr int kGQ = 64;                 // quadrant edge of one wave (and the finish's quarter)
-constexpr int kGK = 8;                  // samples per staged chunk
+constexpr int kGQ = 64;                 // quadrant edge of one wave
+constexpr int kGK = 16;                 // samples per staged chunk
 constexpr int kGPad = kGK + 2;          // LDS row stride (doubles): 16-byte aligned rows, spread banks
 constexpr int kGMaxSplit = 16;
 
@@ -90,7 +91,8 @@ int gram_tiles(int N) {
 
 // Slices per tile for a given N (upper bound) and, with T known, the slices used:
 // about 256 workgroups in all (one per CU), at most kGMaxSplit, and at least 64
-// samples per slice.
+// samples per slice. (Two per CU measured slower: the doubled partial traffic
+// of the finish outweighs the second wave per SIMD.)
 int gram_split_max(int N) {
     const int t = gram_tiles(N);
     int S = (256 + t / 2) / t;
@@ -131,9 +133,10 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double *X, int N, int T
     const int te = min(T, ts + per);
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    // staging: element x = e * 256 + tid of a 128 x 8 chunk is row x / 8, sample x % 8, so each load
-    // instruction of a wave reads eight 64-byte row segments
-    const int srow = tid >> 3, scol = tid & 7;
+    // staging: thread t takes samples 2 (t % 8), +1 of rows t / 8 + 32 e (e = 0..3) of each
+    // panel, so 8 threads read a row's 16-sample segment and a load instruction of a wave
+    // covers eight rows
+    const int srow = tid >> 3, scol = 2 * (tid & 7);
     // Loads take clamped (always valid) addresses and the value is zeroed afterwards where the row is
     // past N or the sample past the slice (a clamped address repeats an element of the same row or
     // of row N - 1, whose entries are discarded), so every load is issued unconditionally and
@@ -153,23 +156,31 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double *X, int N, int T
     }
     // The raw values are loaded first and only used when they are stored into LDS, after the
     // current chunk's MFMAs have been issued, so the loads' latency is hidden behind them.
-    double va[4], vb[4];
-    bool tin = false;
+    double va[4][2], vb[4][2];
+    bool tin0 = false, tin1 = false;
     auto load = [&](int t0) {
         const int t = t0 + scol;
-        tin = t < te;
-        const int tc = min(t, te - 1);
+        tin0 = t < te;
+        tin1 = t + 1 < te;
+        const int tc0 = min(t, te - 1), tc1 = min(t + 1, te - 1);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            va[e] = X[(size_t)rowA[e] * ld + tc];
-            vb[e] = X[(size_t)rowB[e] * ld + tc];
+            va[e][0] = X[(size_t)rowA[e] * ld + tc0];
+            va[e][1] = X[(size_t)rowA[e] * ld + tc1];
+            vb[e][0] = X[(size_t)rowB[e] * ld + tc0];
+            vb[e][1] = X[(size_t)rowB[e] * ld + tc1];
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            sA[buf][(32 * e + srow) * kGPad + scol] = (tin && ((valid >> e) & 1u)) ? va[e] - muA[e] : 0.0;
-            sB[buf][(32 * e + srow) * kGPad + scol] = (tin && ((valid >> (4 + e)) & 1u)) ? vb[e] - muB[e] : 0.0;
+            const bool a = (valid >> e) & 1u, b = (valid >> (4 + e)) & 1u;
+            double *pa = &sA[buf][(32 * e + srow) * kGPad + scol];
+            double *pb = &sB[buf][(32 * e + srow) * kGPad + scol];
+            pa[0] = (tin0 && a) ? va[e][0] - muA[e] : 0.0;
+            pa[1] = (tin1 && a) ? va[e][1] - muA[e] : 0.0;
+            pb[0] = (tin0 && b) ? vb[e][0] - muB[e] : 0.0;
+            pb[1] = (tin1 && b) ? vb[e][1] - muB[e] : 0.0;
         }
     };
 
@@ -192,23 +203,20 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double *X, int N, int T
         if (more) load(t0 + kGK);
         const double *A = sA[buf];
         const double *B = sB[buf];
-        double xa[4][2], xb[4][2];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const double *pa = A + (kGQ * qr + 16 * a + m) * kGPad + 2 * kq;
-            const double *pb = B + (kGQ * qc + 16 * a + m) * kGPad + 2 * kq;
-            xa[a][0] = pa[0];
-            xa[a][1] = pa[1];
-            xb[a][0] = pb[0];
-            xb[a][1] = pb[1];
-        }
+        for (int e = 0; e < 4; ++e) {
+            double xa[4], xb[4];
 #pragma unroll
-        for (int e = 0; e < 2; ++e)
+            for (int a = 0; a < 4; ++a) {
+                xa[a] = A[(kGQ * qr + 16 * a + m) * kGPad + 4 * kq + e];
+                xb[a] = B[(kGQ * qc + 16 * a + m) * kGPad + 4 * kq + e];
+            }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a][e], xb[b][e], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], xb[b], acc[a][b], 0, 0, 0);
+        }
         if (more) store(buf ^ 1);
         __syncthreads();
         buf ^= 1;
@@ -233,38 +241,51 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double *X, int N, int T
     }
 }
 
-// Sum of the S slices of element (r, c) of tile `tile` (slice order).
-__device__ __forceinline__ double gram_sum(const double *part, int tiles, int S, int tile, int r, int c) {
-    double v = 0.0;
-    for (int s = 0; s < S; ++s) v += part[((size_t)s * tiles + tile) * (kGT * kGT) + (size_t)r * kGT + c];
-    return v;
-}
-
-// One workgroup per 64 x 64 quarter of a tile (blockIdx.x = 4 tile + quarter): writes value
-// f(i, j, g) of every element of the quarter at (i, j) and, off the diagonal, at (j, i), both
-// row-wise through an LDS transpose. Only i <= j is written directly and i < j mirrored, so the
-// lower quarter of a diagonal tile writes nothing.
+// One workgroup per 32 x 32 block of a tile (blockIdx.x = 16 tile + block): writes value
+// f(i, j, g) of every element of the block at (i, j) and, off the diagonal, at (j, i), both
+// row-wise through an LDS transpose. g is the sum of the element's S slice partials in slice
+// order; a thread issues the partial loads of its 4 elements together (one memory latency for
+// all). Only i <= j is written directly and i < j mirrored, so the blocks below the diagonal of
+// a diagonal tile write nothing.
+constexpr int kGE = 32;
 template <class F>
 __device__ __forceinline__ void gram_emit(const double *part, int N, int nt, int tiles, int S, double *dst, F f) {
-    __shared__ double tr[kGQ][kGQ + 1];
-    const int tile = blockIdx.x >> 2, quarter = blockIdx.x & 3;
+    __shared__ double tr[kGE][kGE + 1];
+    const int tile = blockIdx.x >> 4, blk = blockIdx.x & 15;
     int ti, tj;
     gram_tile_ij(tile, nt, ti, tj);
-    const int r0 = kGQ * (quarter >> 1), c0 = kGQ * (quarter & 1);   // within the tile
+    const int r0 = kGE * (blk >> 2), c0 = kGE * (blk & 3);   // within the tile
+    if (ti == tj && r0 > c0) return;                          // uniform: every element has i > j
     const int i0 = ti * kGT + r0, j0 = tj * kGT + c0;
-    for (int e = threadIdx.x; e < kGQ * kGQ; e += 256) {
-        const int r = e / kGQ, c = e % kGQ;
+    const size_t sstride = (size_t)tiles * (kGT * kGT);
+    const double *base = part + (size_t)tile * (kGT * kGT);
+    double g[4][kGMaxSplit];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = threadIdx.x + 256 * u, r = e / kGE, c = e % kGE;
+        const double *p = base + (size_t)(r0 + r) * kGT + c0 + c;
+#pragma unroll
+        for (int s = 0; s < kGMaxSplit; ++s) g[u][s] = s < S ? p[(size_t)s * sstride] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = threadIdx.x + 256 * u, r = e / kGE, c = e % kGE;
         const int i = i0 + r, j = j0 + c;
+        double sum = 0.0;
+#pragma unroll
+        for (int s = 0; s < kGMaxSplit; ++s)
+            if (s < S) sum += g[u][s];
         double v = 0.0;
         if (i < N && j < N && i <= j) {
-            v = f(i, j, gram_sum(part, tiles, S, tile, r0 + r, c0 + c));
+            v = f(i, j, sum);
             dst[(size_t)i * N + j] = v;
         }
         tr[c][r] = v;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kGQ * kGQ; e += 256) {
-        const int r = e / kGQ, c = e % kGQ;             // destination row j0 + r, column i0 + c
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = threadIdx.x + 256 * u, r = e / kGE, c = e % kGE;   // destination row j0 + r, column i0 + c
         const int j = j0 + r, i = i0 + c;
         if (i < N && j < N && i < j) dst[(size_t)j * N + i] = tr[r][c];
     }
@@ -286,7 +307,7 @@ hipError_t launch_corr(const double *R, int N, int T, int64_t ld, const double *
     hipLaunchKernelGGL(k_gram_mfma<true>, dim3(tiles * S), dim3(256), 0, s, R, N, T, ld, mu, nt, tiles, S, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_corr_finish, dim3(4 * tiles), dim3(256), 0, s, part, N, nt, tiles, S, ss, C);
+    hipLaunchKernelGGL(k_corr_finish, dim3(16 * tiles), dim3(256), 0, s, part, N, nt, tiles, S, ss, C);
     return hipGetLastError();
 }
 
@@ -388,7 +409,7 @@ hipError_t launch_ewma(const double *R, int N, int T, int64_t ld, double lam, in
     hipLaunchKernelGGL(k_gram_mfma<false>, dim3(tiles * Sp), dim3(256), 0, s, X, N, T, (int64_t)T, nullptr, nt,
                        tiles, Sp, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ewma_finish, dim3(4 * tiles), dim3(256), 0, s, part, N, nt, tiles, Sp,
+    hipLaunchKernelGGL(k_ewma_finish, dim3(16 * tiles), dim3(256), 0, s, part, N, nt, tiles, Sp,
                        pow(lam, (double)T), reset, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t nn = (int64_t)N * N;
