@@ -29,6 +29,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+KIND_TAG = {0: "", 1: "p", 2: "l"}          # pair-sum MFMA kinds: register one-hot, packed, LDS table
 PEAK_MFMA_BF16 = 2500.0          # TFLOP/s, dense bf16 MFMA (MI355X published)
 PEAK_HBM = 8000.0                # GB/s
 CU, SIMD, LANES, CLOCK = 256, 4, 16, 2.4e9
@@ -180,15 +181,16 @@ def _gens_per_request(results):
 
 
 # ---------------------------------------------------------------- launch geometry (issued work)
-def mfma_issued_flops(pop, B: int = 8, packed: int = 0) -> float:
+def mfma_issued_flops(pop, B: int = 8, kind: int = 0) -> float:
     """MFMA flops the BF16x2 pair-sum kernel issues for one launch on population `pop` (P x N,
     on the device; every individual through the pair-sum), two MFMAs (hi, lo) of 16 x 16 x 32 x 2
-    flops per column group and 32-row chunk up to the 16-stock tile's diagonal. Column kernel:
-    one group per individual of each batch of B. Packed kernel: ceil(sum_b K_b / 16) groups per
-    tile and batch, run in pairs (K_b: labels of the tile held by >= 2 stocks of individual b)."""
+    flops per column group and 32-row chunk up to the 16-stock tile's diagonal. Column kernels
+    (kind 0, register one-hot; kind 2, LDS-table one-hot): one group per individual of each batch
+    of B. Packed kernel (kind 1): ceil(sum_b K_b / 16) groups per tile and batch, run in pairs
+    (K_b: labels of the tile held by >= 2 stocks of individual b)."""
     import torch
     P_, N_ = pop.shape
-    if not packed:
+    if kind != 1:
         n_tiles = -(-N_ // 16)
         chunks = sum(-(-min(16 * w + 16, N_) // 32) for w in range(n_tiles))
         return float(chunks * 2 * B * -(-P_ // B)) * 16 * 16 * 32 * 2
@@ -509,9 +511,9 @@ def main():
         else:
             v, ms = pga.tune(C, pop_tune, form, hi=hi, lo=lo, reps=args.tune_reps)
         tuned[form] = {"variant": v, "individuals_per_group": pga.variants(form)[v][0],
-                       "xcd_order": pga.variants(form)[v][1], "packed": pga.variants(form)[v][2],
+                       "xcd_order": pga.variants(form)[v][1], "kind": pga.variants(form)[v][2],
                        "ms_per_variant": None if ms is None else
-                       {f"{a}x{b}{'p' if c else ''}": round(m, 4) for (a, b, c), m in zip(pga.variants(form), ms)}}
+                       {f"{a}x{b}{KIND_TAG[c]}": round(m, 4) for (a, b, c), m in zip(pga.variants(form), ms)}}
         print(f"[bench] {'variant' if ms is None else 'autotune'} {form}: {tuned[form]}", file=sys.stderr,
               flush=True)
     del pop_tune
@@ -544,7 +546,7 @@ def main():
         if form != "bf16x2":
             continue
         I = insts[form]
-        B, pk = tuned[form]["individuals_per_group"], tuned[form]["packed"]
+        B, pk = tuned[form]["individuals_per_group"], tuned[form]["kind"]
         ctx.evolve([I], 0, form=form, init=True)
         kbs = [kbar_tiles(I.pop)]
         iss = [mfma_issued_flops(I.pop, B, pk)]
@@ -621,7 +623,7 @@ def main():
                 entry["kbar_tile"] = kt
                 entry["pairsum_roofline_frac"] = method_flops_bf16x2(N, P, kt) / t_ps / 1e12 / PEAK_MFMA_BF16
                 entry["pairsum_issued_frac"] = (mfma_issued_flops(pop, tuned[form]["individuals_per_group"],
-                                                                  tuned[form]["packed"])
+                                                                  tuned[form]["kind"])
                                                 / t_ps / 1e12 / PEAK_MFMA_BF16)
             else:
                 entry["pairsum_roofline_frac"] = 2 * pair_visits(N, P) / t_ps / 1e12 / PEAK_ALU
@@ -662,8 +664,13 @@ def main():
         t_copy = min(t_copy, e0.elapsed_time(e1) * 1e-3)
     del a, b
     fp64_tf = pga.peak_fp64()
+    mix = {k: round(v, 1) for k, v in pga.pipe_mix(n_workgroups=4096, iters=2000).items()}
     peaks = {"hbm_copy_GBps": 2 * nb / t_copy / 1e9, "mfma_bf16_TFLOPs": pga.peak_mfma_bf16(),
              "fp64_fma_TFLOPs": fp64_tf, "alu_lane_ops_Tops": fp64_tf / 2.0,
+             "pipe_mix_cycles_per_round": mix,
+             "pipe_mix_note": ("cycles per round per wave on one SIMD (pga_pipe_mix): a round is 4 MFMAs, or "
+                               "one individual's register one-hot (8 VALU ops), or 2 LDS 16-byte reads; "
+                               "'a+b' both in each wave, 'a|b' on alternate waves"),
              "published": {"hbm_GBps": 8000.0, "mfma_bf16_TFLOPs": PEAK_MFMA_BF16, "fp64_TFLOPs": 78.6,
                            "alu_Tops": PEAK_ALU},
              "note": "sustained rates measured on this GPU (HBM: device copy; MFMA: register-operand "
@@ -691,7 +698,7 @@ def main():
                 "issued": {"achieved": issued, "frac": issued / PEAK_MFMA_BF16,
                            "work_per_launch": "issued v_mfma_f32_16x16x32_bf16 flops (hi and lo; one column per "
                                               "stock, or packed column groups of 16 run in pairs, as the tuned "
-                                              "variant has it), mean over the loop's populations"}}
+                                              "variant's kind has it), mean over the loop's populations"}}
     else:
         achieved = 2 * pair_visits(N, P) / t_launch / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU, "unit": "Tops/s",
