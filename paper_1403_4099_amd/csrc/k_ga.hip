@@ -140,10 +140,20 @@ struct RankBlock {
             if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fr[v], p)) continue;
             if (c.i < 0 || ranks_before(fr[v], p, c.f, c.i)) c = Cand{fr[v], p};
         }
-        for (int p = threadIdx.x + CACHE * kRankThreads; p < P; p += kRankThreads) {
-            const double fp = gld(f + p);
-            if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fp, p)) continue;
-            if (c.i < 0 || ranks_before(fp, p, c.f, c.i)) c = Cand{fp, p};
+        for (int p0 = threadIdx.x + CACHE * kRankThreads; p0 < P; p0 += 4 * kRankThreads) {
+            double fq[4];                                  // four loads in flight, then the compares
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = p0 + u * kRankThreads;
+                fq[u] = p < P ? gld(f + p) : -INFINITY;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = p0 + u * kRankThreads;
+                if (p >= P) break;
+                if (prev.i >= 0 && !ranks_before(prev.f, prev.i, fq[u], p)) continue;
+                if (c.i < 0 || ranks_before(fq[u], p, c.f, c.i)) c = Cand{fq[u], p};
+            }
         }
         return c;
     }
@@ -181,6 +191,83 @@ struct RankBlock {
             prev = b;
         }
     }
+    // Ranks 0 .. rounds-1 (rounds <= kTop) from ONE read of the values: each
+    // thread keeps its kTop best in rank order, and round r takes the best of the
+    // threads' heads (the r-th ranked individual cannot be a thread's (kTop+1)-th
+    // best). The same read accumulates the statistics partials in the order
+    // write_stats takes them.
+    static constexpr int kTop = 4;
+    template <typename F>
+    __device__ void ranked_once(int rounds, double &sum, double &ninv, F &&visit) {
+        Cand top[kTop];
+#pragma unroll
+        for (int k = 0; k < kTop; ++k) top[k] = Cand{0.0, -1};
+        sum = 0.0;
+        ninv = 0.0;
+        auto take = [&](double fp, int p) {
+            if (isfinite(fp)) sum += fp;
+            else ninv += 1.0;
+            Cand x{fp, p};
+#pragma unroll
+            for (int k = 0; k < kTop; ++k)
+                if (x.i >= 0 && (top[k].i < 0 || ranks_before(x.f, x.i, top[k].f, top[k].i))) {
+                    const Cand y = top[k];
+                    top[k] = x;
+                    x = y;
+                }
+        };
+#pragma unroll
+        for (int v = 0; v < CACHE; ++v) {
+            const int p = threadIdx.x + v * kRankThreads;
+            if (p >= P) break;
+            take(fr[v], p);
+        }
+        for (int p0 = threadIdx.x + CACHE * kRankThreads; p0 < P; p0 += 4 * kRankThreads) {
+            double fq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = p0 + u * kRankThreads;
+                fq[u] = p < P ? gld(f + p) : -INFINITY;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = p0 + u * kRankThreads;
+                if (p >= P) break;
+                take(fq[u], p);
+            }
+        }
+        for (int r = 0; r < rounds; ++r) {
+            const Cand b = block_best(top[0]);
+            if (b.i >= 0 && b.i == top[0].i) {                 // this thread's head was taken
+#pragma unroll
+                for (int k = 0; k + 1 < kTop; ++k) top[k] = top[k + 1];
+                top[kTop - 1] = Cand{0.0, -1};
+            }
+            visit(r, b);
+        }
+    }
+    // Ranks 0 .. rounds-1 (visit(r, cand) in order) and, with stats set, the
+    // statistics row gen_off; returns the best. A single read of the values
+    // serves up to kTop ranks, more take one read per rank.
+    template <typename F>
+    __device__ Cand rank_and_stats(const InstDesc &d, int rounds, int gen_off, bool stats, F &&visit) {
+        Cand best{-INFINITY, 0};
+        if (rounds <= kTop) {
+            double sum, ninv;
+            ranked_once(rounds, sum, ninv, [&](int r, Cand b) {
+                if (r == 0) best = b;
+                visit(r, b);
+            });
+            if (stats) store_stats(d, gen_off, best, block_sum(sum), block_sum(ninv));
+        } else {
+            ranked(rounds, [&](int r, Cand b) {
+                if (r == 0) best = b;
+                visit(r, b);
+            });
+            if (stats) write_stats(d, gen_off, best);
+        }
+        return best;
+    }
     // Statistics row gen_off: {best, mean of finite fitnesses (-inf if none), #-inf, argbest}.
     __device__ void write_stats(const InstDesc &d, int gen_off, Cand best) {
         double sum = 0.0, ninv = 0.0;
@@ -196,8 +283,9 @@ struct RankBlock {
             if (isfinite(fp)) sum += fp;
             else ninv += 1.0;
         }
-        const double total = block_sum(sum);
-        const double inv = block_sum(ninv);
+        store_stats(d, gen_off, best, block_sum(sum), block_sum(ninv));
+    }
+    __device__ void store_stats(const InstDesc &d, int gen_off, Cand best, double total, double inv) const {
         if (threadIdx.x == 0) {
             double *row = d.stats + 4 * (size_t)gen_off;
             const double nfin = (double)P - inv;
@@ -258,13 +346,10 @@ __global__ __launch_bounds__(kRankThreads) void k_rank(Tables t, int gen_off, in
     }
     if (d.selection == PGA_SELECT_SUS)                     // the SUS rank kernel adds into these
         for (int p = threadIdx.x; p < P; p += kRankThreads) gst(d.sus_rank + p, 1);
-    Cand best{-INFINITY, 0};
-    rb.ranked(E > 1 ? E : 1, [&](int r, Cand b) {
-        if (r == 0) best = b;
+    const Cand best = rb.rank_and_stats(d, E > 1 ? E : 1, gen_off, d.stats != nullptr, [&](int r, Cand b) {
         if (r < E && threadIdx.x == 0) d.elite[r] = b.i;
     });
     if (d.term && threadIdx.x == 0) term_update(d, st, best.f, final, gen_off == 0);
-    if (d.stats) rb.write_stats(d, gen_off, best);
 }
 
 hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s) {
@@ -399,6 +484,54 @@ __device__ int sus_pick(const InstDesc &d, uint32_t k, uint32_t n, uint64_t u, u
     return lo;
 }
 
+// Parent pair of child c (c >= E): two tournaments of two on draw (0, c, g,
+// SELECT), or, with SUS, the individuals under shuffled pointers 2(c - E) and
+// 2(c - E) + 1 (which = 0, 1).
+__device__ int sus_parent(const InstDesc &d, int c, uint32_t gen, int which) {
+    const int P = d.P, E = d.E;
+    const uint32_t n = 2u * (uint32_t)(P - E);
+    const uint64_t W = gld(d.sus_cum + (P - 1));
+    const uint32_t w0 = draw(0u, 0xFFFFFFFFu, gen, kTagSus, d.inst_id, d.seed).x;
+    const uint64_t u = __umul64hi((uint64_t)w0 << 32, W);              // floor(w0 W / 2^32)
+    const uint32_t k = shuffle_index(2u * (uint32_t)(c - E) + (uint32_t)which, n, d, gen);
+    return sus_pick(d, k, n, u, W);
+}
+
+// Genes of child c from parents A and B (crossover and mutation), written to
+// out by `width` threads with index tid: a whole workgroup or one wave. Every
+// draw is keyed by gene pair, so the child does not depend on the split. One
+// wave covers 128 consecutive genes per pass in either split, so the
+// crossover-bit draw is the same for the whole wave.
+__device__ __forceinline__ void breed_genes(const InstDesc &d, int c, uint32_t gen, const int32_t *__restrict__ ra,
+                                            const int32_t *__restrict__ rb, int32_t *__restrict__ out, int tid,
+                                            int width) {
+    const int N = d.N;
+    const bool cross = draw(0u, (uint32_t)c, gen, kTagXov, d.inst_id, d.seed).x < d.p_cross;
+    const uint32_t pm = d.p_mut;
+    const int npair = (N + 1) >> 1;
+    for (int jp = tid; jp < npair; jp += width) {
+        const int j = 2 * jp;
+        const bool has1 = j + 1 < N;
+        int32_t g0 = ra[j];
+        int32_t g1 = has1 ? ra[j + 1] : 0;
+        if (cross) {
+            const uint32_t q = __builtin_amdgcn_readfirstlane((uint32_t)(j >> 7));
+            const U4 xb = draw(1u + q, (uint32_t)c, gen, kTagXov, d.inst_id, d.seed);
+            const int r = j & 127;
+            const int wsel = r >> 5;
+            const uint32_t word = wsel == 0 ? xb.x : wsel == 1 ? xb.y : wsel == 2 ? xb.z : xb.w;
+            const int bit = r & 31;
+            if ((word >> bit) & 1u) g0 = rb[j];
+            if (has1 && ((word >> (bit + 1)) & 1u)) g1 = rb[j + 1];
+        }
+        const U4 m = draw((uint32_t)jp, (uint32_t)c, gen, kTagMut, d.inst_id, d.seed);
+        if (m.x < pm) g0 = (int32_t)scale_u32(m.y, (uint32_t)N);
+        if (m.z < pm) g1 = (int32_t)scale_u32(m.w, (uint32_t)N);
+        out[j] = g0;
+        if (has1) out[j + 1] = g1;
+    }
+}
+
 // With `fold` set (no instance selects by SUS or can stop early), the breed
 // workgroups of the elite slots rank the population themselves: workgroup
 // c < E finds the c-th ranked individual and copies it, and workgroup 0 also
@@ -427,17 +560,11 @@ __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off
         rb.load();
         pga_term_state st{};
         if (c == 0 && d.term && threadIdx.x == 0) st = *d.term;
-        Cand best{-INFINITY, 0}, pick{-INFINITY, 0};
-        rb.ranked(c + 1, [&](int r, Cand b) {
-            if (r == 0) best = b;
-            pick = b;
-        });
-        if (c == 0) {
-            if (d.term && threadIdx.x == 0) {
-                if (gen_off == 0) st.call_gens = 0;
-                term_update(d, st, best.f, 0, gen_off == 0);
-            }
-            if (d.stats) rb.write_stats(d, gen_off, best);
+        Cand pick{-INFINITY, 0};
+        const Cand best = rb.rank_and_stats(d, c + 1, gen_off, c == 0 && d.stats, [&](int, Cand b) { pick = b; });
+        if (c == 0 && d.term && threadIdx.x == 0) {
+            if (gen_off == 0) st.call_gens = 0;
+            term_update(d, st, best.f, 0, gen_off == 0);
         }
         ec = pick.i;
     }
@@ -448,58 +575,125 @@ __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off
         return;
     }
     const uint32_t gen = d.gen0 + (uint32_t)gen_off;
-    const double *__restrict__ f = d.fitness;
     int A, B;
     if (d.selection == PGA_SELECT_SUS) {
         __shared__ int par_s[2];
-        if (threadIdx.x < 2) {
-            const uint32_t n = 2u * (uint32_t)(P - E);
-            const uint64_t W = gld(d.sus_cum + (P - 1));
-            const uint32_t w0 = draw(0u, 0xFFFFFFFFu, gen, kTagSus, d.inst_id, d.seed).x;
-            const uint64_t u = __umul64hi((uint64_t)w0 << 32, W);          // floor(w0 W / 2^32)
-            const uint32_t k = shuffle_index(2u * (uint32_t)(c - E) + threadIdx.x, n, d, gen);
-            par_s[threadIdx.x] = sus_pick(d, k, n, u, W);
-        }
+        if (threadIdx.x < 2) par_s[threadIdx.x] = sus_parent(d, c, gen, threadIdx.x);
         __syncthreads();
         A = par_s[0];
         B = par_s[1];
     } else {
+        const double *__restrict__ f = d.fitness;
         const U4 sel = draw(0u, (uint32_t)c, gen, kTagSel, d.inst_id, d.seed);
         A = tournament2(f, (int)scale_u32(sel.x, (uint32_t)P), (int)scale_u32(sel.y, (uint32_t)P));
         B = tournament2(f, (int)scale_u32(sel.z, (uint32_t)P), (int)scale_u32(sel.w, (uint32_t)P));
     }
-    const bool cross = draw(0u, (uint32_t)c, gen, kTagXov, d.inst_id, d.seed).x < d.p_cross;
-    const int32_t *__restrict__ ra = src + (size_t)A * N;
-    const int32_t *__restrict__ rb = src + (size_t)B * N;
-    const uint32_t pm = d.p_mut;
-
-    const int npair = (N + 1) >> 1;
-    for (int jp = threadIdx.x; jp < npair; jp += 256) {
-        const int j = 2 * jp;
-        const bool has1 = j + 1 < N;
-        int32_t g0 = ra[j];
-        int32_t g1 = has1 ? ra[j + 1] : 0;
-        if (cross) {
-            const uint32_t q = __builtin_amdgcn_readfirstlane((uint32_t)(j >> 7));
-            const U4 xb = draw(1u + q, (uint32_t)c, gen, kTagXov, d.inst_id, d.seed);
-            const int r = j & 127;
-            const int wsel = r >> 5;
-            const uint32_t word = wsel == 0 ? xb.x : wsel == 1 ? xb.y : wsel == 2 ? xb.z : xb.w;
-            const int bit = r & 31;
-            if ((word >> bit) & 1u) g0 = rb[j];
-            if (has1 && ((word >> (bit + 1)) & 1u)) g1 = rb[j + 1];
-        }
-        const U4 m = draw((uint32_t)jp, (uint32_t)c, gen, kTagMut, d.inst_id, d.seed);
-        if (m.x < pm) g0 = (int32_t)scale_u32(m.y, (uint32_t)N);
-        if (m.z < pm) g1 = (int32_t)scale_u32(m.w, (uint32_t)N);
-        out[j] = g0;
-        if (has1) out[j + 1] = g1;
-    }
+    breed_genes(d, c, gen, src + (size_t)A * N, src + (size_t)B * N, out, threadIdx.x, 256);
 }
 
-hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, hipStream_t s) {
+// The same step with one wave per slot of the next population (four slots per
+// workgroup, possibly of different instances): at small N a workgroup per slot
+// leaves most of its threads idle and bounds the slots in flight by the
+// workgroup limit per compute unit. With `fold` set, workgroup k < n_inst
+// ranks instance k instead (the same RankBlock code and thread count as the
+// rank kernel, so the statistics are the same bits), copies its elites and
+// keeps its termination state and statistics row, and the slot workgroups
+// follow; otherwise the elite slots copy the individuals the rank kernel
+// listed.
+__device__ void fold_rank(const Tables &t, int k, int parity, int gen_off) {
+    __shared__ RankLds sh;
+    const InstDesc &d = t.desc[k];
+    const int P = d.P, E = d.E, N = d.N;
+    if (P == 0 || (E == 0 && !d.term && !d.stats)) return;   // a padding slot, or nothing to rank
+    // This workgroup's chain of reductions is the longest path of the launch:
+    // its waves issue ahead of the slot waves that share their SIMDs.
+    __builtin_amdgcn_s_setprio(3);
+    RankBlock<4> rb{d.fitness, P, sh};                     // the slot waves share the register budget
+    rb.load();
+    pga_term_state st{};
+    if (d.term && threadIdx.x == 0) st = *d.term;
+    const int32_t *__restrict__ src = d.pop[parity];
+    int32_t *__restrict__ dst = d.pop[parity ^ 1];
+    // Up to four elites are copied after the ranking, their loads in flight
+    // together; more are copied as they are found.
+    constexpr int kQ = RankBlock<4>::kTop;
+    int eq[kQ] = {0, 0, 0, 0};
+    const Cand best = rb.rank_and_stats(d, E > 1 ? E : 1, gen_off, d.stats != nullptr, [&](int r, Cand b) {
+        if (r >= E) return;
+        if (E <= kQ) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q)
+                if (q == r) eq[q] = b.i;
+            return;
+        }
+        const int32_t *__restrict__ e = src + (size_t)b.i * N;
+        int32_t *__restrict__ o = dst + (size_t)r * N;
+        for (int j = threadIdx.x; j < N; j += kRankThreads) o[j] = e[j];
+    });
+    if (d.term && threadIdx.x == 0) {
+        if (gen_off == 0) st.call_gens = 0;
+        term_update(d, st, best.f, 0, gen_off == 0);
+    }
+    if (E <= kQ)
+        for (int j = threadIdx.x; j < N; j += kRankThreads) {
+            int32_t v[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q)
+                if (q < E) v[q] = src[(size_t)eq[q] * N + j];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q)
+                if (q < E) dst[(size_t)q * N + j] = v[q];
+        }
+}
+
+__global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int gen_off, int fold) {
+    int wg = blockIdx.x;
+    if (fold) {
+        if (wg < t.n_inst) {
+            fold_rank(t, wg, parity, gen_off);
+            return;
+        }
+        wg -= t.n_inst;
+    }
+    const int g = __builtin_amdgcn_readfirstlane(4 * wg + (int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (g >= t.inds[t.n_inst]) return;                     // the grid may exceed the total (capacity-sized graph)
+    const int k = find_inst(t.inds, t.n_inst, g);
+    const InstDesc &d = t.desc[k];
+    if (inst_stopped(d)) return;                           // set by this generation's rank
+    const int N = d.N, P = d.P, E = d.E;
+    const int c = g - t.inds[k];
+    const int32_t *__restrict__ src = d.pop[parity];
+    int32_t *__restrict__ out = d.pop[parity ^ 1] + (size_t)c * N;
+    if (c < E) {
+        if (fold) return;                                  // copied by the instance's ranking workgroup
+        const int32_t *__restrict__ e = src + (size_t)d.elite[c] * N;
+        for (int j = lane; j < N; j += 64) out[j] = e[j];
+        return;
+    }
+    const uint32_t gen = d.gen0 + (uint32_t)gen_off;
+    int A, B;
+    if (d.selection == PGA_SELECT_SUS) {
+        int pick = 0;
+        if (lane < 2) pick = sus_parent(d, c, gen, lane);
+        A = __builtin_amdgcn_readlane(pick, 0);
+        B = __builtin_amdgcn_readlane(pick, 1);
+    } else {
+        const double *__restrict__ f = d.fitness;
+        const U4 sel = draw(0u, (uint32_t)c, gen, kTagSel, d.inst_id, d.seed);
+        A = tournament2(f, (int)scale_u32(sel.x, (uint32_t)P), (int)scale_u32(sel.y, (uint32_t)P));
+        B = tournament2(f, (int)scale_u32(sel.z, (uint32_t)P), (int)scale_u32(sel.w, (uint32_t)P));
+    }
+    breed_genes(d, c, gen, src + (size_t)A * N, src + (size_t)B * N, out, lane, 64);
+}
+
+hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_breed, dim3(total_inds), dim3(256), 0, s, t, parity, gen_off, fold);
+    if (by_wave)
+        hipLaunchKernelGGL(k_breed_wave, dim3((fold ? t.n_inst : 0) + (total_inds + 3) / 4), dim3(256), 0, s, t,
+                           parity, gen_off, fold);
+    else
+        hipLaunchKernelGGL(k_breed, dim3(total_inds), dim3(256), 0, s, t, parity, gen_off, fold);
     return hipGetLastError();
 }
 

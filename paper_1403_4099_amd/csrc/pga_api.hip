@@ -260,11 +260,12 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
         const int parity = k & 1;
         if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
         // Without SUS or an early stop, breeding needs the ranking only for the elite
-        // slots, and the breed kernel does it there (fold); otherwise rank first.
+        // slots, and the breed kernel does it itself (fold); otherwise rank first.
+        const int by_wave = sh.max_n <= kBreedWaveMaxN ? 1 : 0;
         const int fold = (!sh.sus && !sh.stop) ? 1 : 0;
         if (!fold && (e = timed(3, s, [&] { return launch_rank(t, k, 0, s); })) != hipSuccess) return e;
         if (sh.sus && (e = timed(8, s, [&] { return launch_sus(t, sh.max_p, s); })) != hipSuccess) return e;
-        if ((e = timed(4, s, [&] { return launch_breed(t, sh.inds, parity, k, fold, s); })) != hipSuccess)
+        if ((e = timed(4, s, [&] { return launch_breed(t, sh.inds, parity, k, fold, by_wave, s); })) != hipSuccess)
             return e;
     }
     const int parity = G & 1;

@@ -252,7 +252,11 @@ hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double
 
 hipError_t launch_init(Tables t, int total_inds, hipStream_t s);
 hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s);
-hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, hipStream_t s);
+// by_wave: one wave per slot instead of one workgroup per slot.
+hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, hipStream_t s);
+// Largest N bred with one wave per slot: above it a workgroup per slot keeps more
+// genes of one child in flight.
+constexpr int kBreedWaveMaxN = 1024;
 hipError_t launch_sus(Tables t, int max_p, hipStream_t s);
 hipError_t launch_copy_back(Tables t, int total_inds, int G, hipStream_t s);
 // Records a hipError_t for pga_last_hip_error() on this thread.

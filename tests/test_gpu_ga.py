@@ -206,3 +206,28 @@ def test_capacity_sized_graph_serves_mixes_that_round_alike():
                 assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness)
                 assert torch.equal(a.stats, b.stats)
         assert ctx.graphs() == (1 if form == "fp64" else 2)
+
+
+@pytest.mark.parametrize("N,P,E", [(40, 600, 2), (300, 96, 4), (300, 96, 6), (1100, 80, 3), (1100, 80, 0)],
+                         ids=["N40-E2", "N300-E4", "N300-E6", "N1100-E3", "N1100-E0"])
+def test_breed_ranking_paths_agree_bitwise(N, P, E):
+    # Without SUS or an early stop the breed launch ranks each instance itself;
+    # an armed termination test that never fires runs the rank kernel first.
+    # Both must give the same populations, fitnesses and statistics bits, for
+    # the wave-per-slot (N <= 1024) and workgroup-per-slot breed, with elites
+    # within and beyond what a single read of the fitnesses ranks.
+    say(f"ranking paths N={N} P={P} E={E}")
+    C, _ = corr(N, seed=8)
+    G = 5
+    runs = []
+    for stall in (0, 10**6):
+        I = _inst(C, P, G, form="fp64", elites=E, seed=13, instance_id=1, stall_gens=stall, tol=1e300)
+        pga.Context().evolve([I], G, form="fp64", init=True)
+        torch.cuda.synchronize()
+        runs.append(I)
+    a, b = runs
+    assert b.term_state()["stopped"] == 0
+    assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness) and torch.equal(a.stats, b.stats)
+    st = a.stats.cpu().numpy()[-1]
+    so = O.stats(a.fitness.cpu().numpy())
+    assert st[0] == so[0] and st[2] == so[2] and st[3] == so[3]
