@@ -23,12 +23,13 @@ namespace pga {
 // tables travel as kernel arguments, so no host buffer has to outlive the call.
 struct DescBlob {
     InstDesc d;
-    int32_t prefix[4];   // {0, tiles}, {0, P}
+    int32_t prefix[4];   // {0, tiles}, {0, P}; the route list counters follow, zeroed
 };
 
 __global__ void k_write_desc(DescBlob b, InstDesc *dst, int32_t *prefix) {
     if (threadIdx.x == 0) *dst = b.d;
     if (threadIdx.x < 4) prefix[threadIdx.x] = b.prefix[threadIdx.x];
+    for (int i = threadIdx.x; i < kListCounters; i += blockDim.x) prefix[4 + i] = 0;
 }
 
 hipError_t launch_write_desc(const InstDesc &d, int32_t tiles, InstDesc *dst, int32_t *prefix, hipStream_t s) {
@@ -38,7 +39,7 @@ hipError_t launch_write_desc(const InstDesc &d, int32_t tiles, InstDesc *dst, in
     b.prefix[1] = tiles;
     b.prefix[2] = 0;
     b.prefix[3] = d.P;
-    hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, s, b, dst, prefix);
+    hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(256), 0, s, b, dst, prefix);
     return hipGetLastError();
 }
 
@@ -433,16 +434,30 @@ __device__ __forceinline__ void finish_terms(const InstDesc &d, int p, int N, co
     }
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int parity, int32_t *status) {
+// Listed (cluster-pair route on): workgroup i takes entry i / slices of
+// slice i mod slices of this parity's dense list, and the workgroups past
+// their slice's length end at once; else workgroup g takes individual g.
+__global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int parity, int listed, int slices,
+                                                        int cap, int32_t *status) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
-    const int g = blockIdx.x;
-    if (g >= t.inds[t.n_inst]) return;               // the grid may exceed the total (capacity-sized graph)
-    const int k = find_inst(t.inds, t.n_inst, g);
+    int k, p;
+    if (listed) {
+        const int slice = (int)blockIdx.x % slices, at = (int)blockIdx.x / slices;
+        const int32_t *e = list_entry(t, kListDense, slice, cap, at);   // read with the count: in bounds
+        const int n = *list_count(t, parity, kListDense, slice);
+        p = __builtin_amdgcn_readfirstlane(gld(e));
+        k = __builtin_amdgcn_readfirstlane(gld(e + 1));
+        if (at >= n) return;
+    } else {
+        const int g = blockIdx.x;
+        if (g >= t.inds[t.n_inst]) return;           // the grid may exceed the total (capacity-sized graph)
+        k = find_inst(t.inds, t.n_inst, g);
+        p = g - t.inds[k];
+    }
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;                     // uniform over the workgroup
     const int N = d.N;
-    const int p = g - t.inds[k];
     if (d.route && gld(d.route + p) == 0) return;    // evaluated by the cluster-pair kernel
     const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
     const double *__restrict__ v = d.wsum + (size_t)p * N;
@@ -539,11 +554,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int
     finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(max_n), red, (int *)(red + 2 * kFinWaves), status);
 }
 
-hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status,
+hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int listed, int32_t *status,
                          hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finish, dim3(total_inds), dim3(kFinThreads), finish_lds_bytes(max_n), s, t, max_n,
-                       parity, status);
+    const int n_wg = (total_inds + 3) / 4, slices = list_slices(n_wg), cap = list_slice_cap(n_wg);
+    hipLaunchKernelGGL(k_finish, dim3(listed ? slices * cap : total_inds), dim3(kFinThreads),
+                       finish_lds_bytes(max_n), s, t, max_n, parity, listed, slices, cap, status);
     return hipGetLastError();
 }
 
@@ -683,19 +699,107 @@ __device__ __forceinline__ unsigned long long fixed_pt(double c, int sc) {
     return (unsigned long long)llrint(ldexp(c, sc));
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int parity, double frac,
-                                                        int32_t *status) {
+// Route of every individual, one wave each (four per workgroup): n_s by LDS
+// atomics, whose return values add up to the pair count sum_s n_s (n_s - 1) / 2
+// exactly. An individual at or under the limit, or with a label outside
+// [0, N), goes to the sparse list (route 0), the others to the dense list
+// (route 1). Workgroup w appends to slice w mod slices of each list with
+// one atomic per list; the order within a slice depends on timing, the
+// content does not. Workgroup 0 also empties the other parity's lists.
+__global__ __launch_bounds__(256) void k_route(Tables t, int lds_n, int parity, double frac, int slices, int cap) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int kind[4], ent[4][2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < 2 * kListSlices; i += 256) gst(t.sq + (2 * (parity ^ 1)) * kListSlices + i, 0);
+    const int g = __builtin_amdgcn_readfirstlane(4 * (int)blockIdx.x + wave);
+    int mine = -1, k = 0, p = 0;                     // mine: the list this wave's individual joins
+    if (g < t.inds[t.n_inst]) {                      // the grid may exceed the total (capacity-sized graph)
+        k = find_inst(t.inds, t.n_inst, g);
+        const InstDesc &d = t.desc[k];
+        const int N = d.N;
+        p = g - t.inds[k];
+        if (inst_stopped(d)) {
+        } else if (N > lds_n) {                      // lds_n <= kSparseMaxN
+            if (lane == 0) gst(d.route + p, 1);
+            mine = kListDense;
+        } else {
+            int *cnt = (int *)(smem + (size_t)wave * pad16(4 * (size_t)lds_n));
+            for (int s = lane; s < N; s += 64) cnt[s] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
+            int pairs = 0, bad = 0;
+            for (int j0 = lane; j0 < N; j0 += 4 * 64) {     // four labels per lane in flight
+                int l[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) l[u] = j0 + 64 * u < N ? gld(lab + j0 + 64 * u) : 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (j0 + 64 * u >= N) break;
+                    if (l[u] < 0 || l[u] >= N) bad = 1;
+                    else pairs += atomicAdd(&cnt[l[u]], 1);
+                }
+            }
+#pragma unroll
+            for (int m = 32; m > 0; m >>= 1) pairs += __shfl_xor(pairs, m, 64);
+            const bool sparse = __any(bad) || (double)pairs <= floor(frac * 0.5 * (double)N * (double)(N - 1));
+            if (lane == 0) gst(d.route + p, sparse ? 0 : 1);
+            mine = sparse ? kListSparse : kListDense;
+        }
+    }
+    if (lane == 0) {
+        kind[wave] = mine;
+        ent[wave][0] = p;
+        ent[wave][1] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {                           // thread L appends this workgroup's individuals of list L
+        const int L = threadIdx.x;
+        int n = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) n += kind[w] == L ? 1 : 0;
+        if (n > 0) {
+            const int slice = (int)blockIdx.x % slices;
+            int at = atomicAdd(list_count(t, parity, L, slice), n);
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (kind[w] == L) {
+                    int32_t *e = list_entry(t, L, slice, cap, at++);
+                    gst(e, ent[w][0]);
+                    gst(e + 1, ent[w][1]);
+                }
+        }
+    }
+}
+
+// An individual the cluster-pair kernel hands back to the pair-sum route joins
+// the dense list (one thread; the slice it came from has room for it there).
+// slice < 0: no lists in use (the finish reads every individual's route).
+__device__ __forceinline__ void list_dense(const Tables &t, int parity, int slice, int cap, int p, int k) {
+    if (slice < 0) return;
+    int32_t *e = list_entry(t, kListDense, slice, cap, atomicAdd(list_count(t, parity, kListDense, slice), 1));
+    gst(e, p);
+    gst(e + 1, k);
+}
+
+__host__ __device__ constexpr size_t route_lds_bytes(int n) { return 4 * pad16(4 * (size_t)n); }
+static_assert(route_lds_bytes(kSparseMaxN) <= (size_t)kMaxLdsBytes, "route LDS within the limit");
+
+// The cluster-pair evaluation of individual p of instance k (all threads of the
+// workgroup), taken from slice `slice` of the sparse list. An individual it
+// hands to the pair-sum route (route 1) joins the dense list.
+__device__ void sparse_one(const Tables &t, int k, int p, int slice, int cap, int lds_n, int parity, double frac,
+                           int32_t *status, unsigned char *smem) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
-    const int g = blockIdx.x;
-    if (g >= t.inds[t.n_inst]) return;               // the grid may exceed the total (capacity-sized graph)
-    const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;                     // uniform over the workgroup
     const int N = d.N;
-    const int p = g - t.inds[k];
     if (N > lds_n) {                                 // lds_n <= kSparseMaxN
-        if (tid == 0) gst(d.route + p, 1);
+        if (tid == 0) {
+            gst(d.route + p, 1);
+            list_dense(t, parity, slice, cap, p, k);
+        }
         return;
     }
     const size_t n = (size_t)lds_n;
@@ -764,7 +868,10 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     int nmax;
     const int T = block_exscan_cnt_pairs(cnt, begin, PP, N, ired + 4, nmax);   // T == pairs
     if ((double)T > floor(frac * 0.5 * (double)N * (double)(N - 1))) {
-        if (tid == 0) gst(d.route + p, 1);
+        if (tid == 0) {
+            gst(d.route + p, 1);
+            list_dense(t, parity, slice, cap, p, k);
+        }
         return;                                      // uniform
     }
     int e;
@@ -855,19 +962,363 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     if (lane == 0) ired[wave] = wbadc;
     __syncthreads();
     if (ired[0] | ired[1] | ired[2] | ired[3]) {
-        if (tid == 0) gst(d.route + p, 1);
+        if (tid == 0) {
+            gst(d.route + p, 1);
+            list_dense(t, parity, slice, cap, p, k);
+        }
         return;
     }
     if (tid == 0) gst(d.route + p, 0);
     finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(lds_n), red, ired + 12, status);
 }
 
-hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int32_t *status,
+// The same evaluation by one wave (a 64-thread workgroup) for N <= 512: at the
+// batched form's sizes a whole workgroup per individual repeats its scans,
+// reductions and barriers in every wave and holds eight individuals per
+// compute unit. The steps and their integer results are those of sparse_one;
+// the log terms are added in the workgroup kernel's order (entry m of the
+// label list to virtual thread m mod 256, each virtual wave's lanes by the
+// same butterfly, the four virtual waves in order), so the fitness has the
+// same bits whichever of the two kernels evaluates it.
+// LDS (18 N bytes): csum int64 [N] | n_s, then the cluster starts, then their
+// ends, int32 [N + 1] | PP int32 [N + 1] | members uint16 [N], later the list
+// of labels with n_s > 1.
+constexpr int kSparseWaveMaxN = 512;
+constexpr int kSwCache = kSparseWaveMaxN / 64;     // stocks per lane, all in registers
+
+__host__ __device__ constexpr size_t sparse_wave_lds_bytes(int n) {
+    return pad16(8 * (size_t)n) + 2 * pad16(4 * ((size_t)n + 1)) + pad16(2 * (size_t)n);
+}
+static_assert(sparse_wave_lds_bytes(kSparseWaveMaxN) <= (size_t)kMaxLdsBytes, "wave cluster-pair LDS");
+
+// Orders the LDS accesses of the wave's lanes (one wave: no barrier needed).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ void sparse_one_wave(const Tables &t, int k, int p, int slice, int cap, int lds_n, int parity,
+                                double frac, int32_t *status, unsigned char *smem) {
+    const int lane = threadIdx.x;
+    const InstDesc &d = t.desc[k];
+    if (inst_stopped(d)) return;
+    const int N = d.N;
+    if (N > lds_n) {                                 // lds_n <= kSparseWaveMaxN
+        if (lane == 0) {
+            gst(d.route + p, 1);
+            list_dense(t, parity, slice, cap, p, k);
+        }
+        return;
+    }
+    const size_t n = (size_t)lds_n;
+    unsigned char *b = smem;
+    long long *csum = (long long *)b;   b += pad16(8 * n);
+    int *cb = (int *)b;                 b += pad16(4 * (n + 1));
+    int *PP = (int *)b;                 b += pad16(4 * (n + 1));
+    uint16_t *members = (uint16_t *)b;
+    const int32_t *__restrict__ lab = d.pop[parity] + (size_t)p * N;
+    const double *__restrict__ C = d.C;
+
+    const int ucache = (N + 63) / 64;                // uniform
+    int lr[kSwCache];
+    double dg[kSwCache];
+#pragma unroll
+    for (int u = 0; u < kSwCache; ++u) {             // the labels are requested first, then the flag
+        if (u >= ucache) break;
+        const int j = lane + 64 * u;
+        lr[u] = j < N ? gld(lab + j) : 0;
+    }
+    const bool ones = gld(d.diag + N) == 1.0;
+#pragma unroll
+    for (int u = 0; u < kSwCache; ++u) {
+        if (u >= ucache) break;
+        const int j = lane + 64 * u;
+        dg[u] = (!ones && j < N) ? gld(d.diag + j) : 1.0;
+    }
+    int bad = 0;
+#pragma unroll
+    for (int u = 0; u < kSwCache; ++u) {
+        if (u >= ucache) break;
+        const int j = lane + 64 * u;
+        if (j < N) {
+            if (lr[u] < 0 || lr[u] >= N) bad = 1;
+            cb[j] = 0;
+            csum[j] = 0;
+        }
+    }
+    if (__any(bad)) {                                // as the finish: labels outside [0, N)
+        if (lane == 0) {
+            gst(d.route + p, 0);
+            d.fitness[p] = -INFINITY;
+            if (status) {
+                atomicAdd(&status[PGA_ST_LABEL], 1);
+                atomicAdd(&status[PGA_ST_NONFINITE], 1);
+            }
+        }
+        if (d.n_s_out)
+            for (int s = lane; s < N; s += 64) d.n_s_out[(size_t)p * N + s] = 0;
+        if (d.c_s_out)
+            for (int s = lane; s < N; s += 64) d.c_s_out[(size_t)p * N + s] = 0.0;
+        return;
+    }
+    wave_lds_sync();
+    // n_s; the atomics' old values add up to the pair count, their maximum + 1 is max n_s
+    int T = 0, nmax = 0;
+#pragma unroll
+    for (int u = 0; u < kSwCache; ++u) {
+        if (u >= ucache) break;
+        if (lane + 64 * u < N) {
+            const int old = atomicAdd(&cb[lr[u]], 1);
+            T += old;
+            nmax = max(nmax, old + 1);
+        }
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        T += __shfl_xor(T, m, 64);
+        nmax = max(nmax, __shfl_xor(nmax, m, 64));
+    }
+    if ((double)T > floor(frac * 0.5 * (double)N * (double)(N - 1))) {
+        if (lane == 0) {
+            gst(d.route + p, 1);
+            list_dense(t, parity, slice, cap, p, k);
+        }
+        return;
+    }
+    int e;
+    frexp((double)nmax * (double)nmax, &e);          // max n_s^2 < 2^e
+    const int sc = 61 - e;
+    wave_lds_sync();
+    // exclusive prefixes of n_s (in place: cluster starts) and of the pair counts
+    {
+        const int per = (N + 63) / 64;
+        const int b0 = min(N, lane * per), b1 = min(N, b0 + per);
+        int own = 0, ownp = 0;
+        for (int x = b0; x < b1; ++x) {
+            const int c = cb[x];
+            own += c;
+            ownp += c * (c - 1) / 2;
+        }
+        int inc = own, incp = ownp;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(inc, o, 64), yp = __shfl_up(incp, o, 64);
+            if (lane >= o) {
+                inc += y;
+                incp += yp;
+            }
+        }
+        int run = inc - own, runp = incp - ownp;
+        for (int x = b0; x < b1; ++x) {
+            const int c = cb[x];
+            cb[x] = run;
+            PP[x] = runp;
+            run += c;
+            runp += c * (c - 1) / 2;
+        }
+        if (lane == 0) PP[N] = T;
+    }
+    wave_lds_sync();
+    // members grouped by cluster; cb[s] becomes the end of cluster s, whose start is cb[s - 1]
+    int badc = 0;
+#pragma unroll
+    for (int u = 0; u < kSwCache; ++u) {
+        if (u >= ucache) break;
+        const int j = lane + 64 * u;
+        if (j < N) {
+            members[atomicAdd(&cb[lr[u]], 1)] = (uint16_t)j;
+            if (!ones) {
+                if (!(fabs(dg[u]) <= 1.0)) badc = 1;
+                else atomicAdd((unsigned long long *)&csum[lr[u]], fixed_pt(dg[u], sc));
+            }
+        }
+    }
+    wave_lds_sync();
+    if (ones)                                        // sum of n_s diagonal ones, exact
+        for (int s = lane; s < N; s += 64) csum[s] = (long long)(cb[s] - (s ? cb[s - 1] : 0)) << sc;
+    wave_lds_sync();
+
+    // pairs: kq consecutive ones per lane and round, as the workgroup kernel takes them
+    constexpr int kQ = 8;
+    const int kq = min(kQ, max(1, (T + 63) / 64));   // uniform
+    for (int q0 = lane * kq; q0 < T; q0 += kq * 64) {
+        int cs = 0, hi = N;                          // PP[cs] <= q0 < PP[hi]
+        while (hi - cs > 1) {
+            const int mid = (cs + hi) >> 1;
+            if (PP[mid] <= q0) cs = mid;
+            else hi = mid;
+        }
+        const int r = q0 - PP[cs];                   // = bq (bq - 1) / 2 + aq, aq < bq
+        int bq = (int)((1.0 + sqrt(1.0 + 8.0 * (double)r)) * 0.5);
+        while (bq * (bq - 1) / 2 > r) --bq;
+        while ((bq + 1) * bq / 2 <= r) ++bq;
+        int aq = r - bq * (bq - 1) / 2;
+        int st = cs ? cb[cs - 1] : 0;                // first position of cluster cs
+        int pend = PP[cs + 1];
+        double c[kQ];
+        int l[kQ];
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) {
+            const int q = q0 + u;
+            l[u] = -1;
+            c[u] = 0.0;
+            if (u < kq && q < T) {
+                while (q >= pend) {                  // next cluster with pairs (PP[N] = T > q)
+                    st = cb[cs];
+                    ++cs;
+                    pend = PP[cs + 1];
+                    aq = 0;
+                    bq = 1;
+                }
+                const int j = members[st + bq], i = members[st + aq];
+                c[u] = gld(C + (size_t)min(i, j) * N + max(i, j));
+                l[u] = cs;
+                if (++aq == bq) {
+                    ++bq;
+                    aq = 0;
+                }
+            }
+        }
+        long long run = 0;
+        int cur = -1;
+#pragma unroll
+        for (int u = 0; u < kQ; ++u) {
+            if (l[u] < 0) continue;
+            if (!(fabs(c[u]) <= 1.0)) {
+                badc = 1;
+                continue;
+            }
+            if (l[u] != cur) {
+                if (cur >= 0) atomicAdd((unsigned long long *)&csum[cur], (unsigned long long)run);
+                cur = l[u];
+                run = 0;
+            }
+            run += fixed_pt(2.0 * c[u], sc);
+        }
+        if (cur >= 0) atomicAdd((unsigned long long *)&csum[cur], (unsigned long long)run);
+    }
+    if (__any(badc)) {
+        if (lane == 0) {
+            gst(d.route + p, 1);
+            list_dense(t, parity, slice, cap, p, k);
+        }
+        return;
+    }
+    if (lane == 0) gst(d.route + p, 0);
+    wave_lds_sync();
+
+    // per-label outputs and the list of labels with n_s > 1, ascending (into members)
+    uint16_t *lst = members;
+    int nlist = 0;
+    for (int s0 = 0; s0 < N; s0 += 64) {
+        const int s = s0 + lane;
+        const int ns = s < N ? cb[s] - (s ? cb[s - 1] : 0) : 0;
+        if (s < N) {
+            if (d.n_s_out) gst(d.n_s_out + (size_t)p * N + s, ns);
+            if (d.c_s_out) gst(d.c_s_out + (size_t)p * N + s, ldexp((double)csum[s], -sc));
+        }
+        const uint64_t m = __ballot(ns > 1);
+        if (ns > 1) lst[nlist + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)s;
+        nlist += __popcll(m);
+    }
+    wave_lds_sync();
+    // entry m belongs to virtual thread m mod 256, i.e. virtual wave (m / 64) mod 4
+    double L[kFinWaves] = {0.0, 0.0, 0.0, 0.0};
+    int nbad[kFinWaves] = {0, 0, 0, 0};
+    for (int m = lane; m < nlist; m += 64) {
+        const int w = (m >> 6) & (kFinWaves - 1);
+        const int s = lst[m];
+        const int ni = cb[s] - (s ? cb[s - 1] : 0);
+        const double nd = (double)ni;
+        const double c = ldexp((double)csum[s], -sc);
+        const double n2 = nd * nd;
+        const bool ok = c > 0.0 && c < n2;
+        const double term = ok ? log(nd / c) + (nd - 1.0) * log((n2 - nd) / (n2 - c)) : 0.0;
+#pragma unroll
+        for (int v = 0; v < kFinWaves; ++v)
+            if (v == w) {
+                if (ok) L[v] += term;
+                else nbad[v] += 1;
+            }
+    }
+    double Ltot = 0.0, badtot = 0.0;
+#pragma unroll
+    for (int v = 0; v < kFinWaves; ++v) {
+        Ltot += wave_sum(L[v]);
+        badtot += wave_sum((double)nbad[v]);
+    }
+    if (lane == 0) {
+        if (badtot > 0.0) {
+            d.fitness[p] = -INFINITY;
+            if (status) {
+                atomicAdd(&status[PGA_ST_DOMAIN], (int)badtot);
+                atomicAdd(&status[PGA_ST_NONFINITE], 1);
+            }
+        } else {
+            d.fitness[p] = 0.5 * Ltot;
+        }
+    }
+}
+
+// Listed: entry i / slices of slice i mod slices of this parity's sparse list
+// (workgroups past their slice's length end at once). Else individual i, the
+// route decided here as in the workgroup kernel.
+__device__ __forceinline__ bool sparse_target(const Tables &t, int listed, int parity, int slices, int cap, int &k,
+                                              int &p, int &slice) {
+    if (listed) {
+        slice = (int)blockIdx.x % slices;
+        const int at = (int)blockIdx.x / slices;
+        const int32_t *e = list_entry(t, kListSparse, slice, cap, at);   // read with the count: in bounds
+        const int n = *list_count(t, parity, kListSparse, slice);
+        p = __builtin_amdgcn_readfirstlane(gld(e));
+        k = __builtin_amdgcn_readfirstlane(gld(e + 1));
+        return at < n;
+    }
+    const int g = blockIdx.x;
+    if (g >= t.inds[t.n_inst]) return false;         // the grid may exceed the total (capacity-sized graph)
+    k = find_inst(t.inds, t.n_inst, g);
+    p = g - t.inds[k];
+    slice = -1;
+    return true;
+}
+
+__global__ __launch_bounds__(64) void k_sparse_wave(Tables t, int lds_n, int parity, double frac, int listed,
+                                                    int slices, int cap, int32_t *status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int k, p, slice;
+    if (!sparse_target(t, listed, parity, slices, cap, k, p, slice)) return;
+    sparse_one_wave(t, k, p, slice, cap, lds_n, parity, frac, status, smem);
+}
+
+// A workgroup per list entry or individual (see sparse_target). (A grid-stride
+// loop over a smaller grid holds the per-thread values of the body across
+// iterations: 85 registers instead of 52, five waves per SIMD instead of
+// eight.)
+__global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int parity, double frac, int listed,
+                                                        int slices, int cap, int32_t *status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int k, p, slice;
+    if (!sparse_target(t, listed, parity, slices, cap, k, p, slice)) return;
+    sparse_one(t, k, p, slice, cap, lds_n, parity, frac, status, smem);
+}
+
+hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int listed, int32_t *status,
                          hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
     const int n = std::min(max_n, kSparseMaxN);
-    hipLaunchKernelGGL(k_sparse, dim3(total_inds), dim3(kFinThreads), sparse_lds_bytes(n), s, t, n, parity,
-                       frac, status);
+    const int n_wg = (total_inds + 3) / 4, slices = list_slices(n_wg), cap = list_slice_cap(n_wg);
+    if (listed) {
+        hipLaunchKernelGGL(k_route, dim3(n_wg), dim3(256), route_lds_bytes(n), s, t, n, parity, frac, slices, cap);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int grid = listed ? slices * cap : total_inds;
+    if (n <= kSparseWaveMaxN)
+        hipLaunchKernelGGL(k_sparse_wave, dim3(grid), dim3(64), sparse_wave_lds_bytes(n), s, t, n, parity, frac,
+                           listed, slices, cap, status);
+    else
+        hipLaunchKernelGGL(k_sparse, dim3(grid), dim3(kFinThreads), sparse_lds_bytes(n), s, t, n, parity, frac,
+                           listed, slices, cap, status);
     return hipGetLastError();
 }
 

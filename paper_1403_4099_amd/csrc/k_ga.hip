@@ -646,7 +646,10 @@ __device__ void fold_rank(const Tables &t, int k, int parity, int gen_off) {
         }
 }
 
-__global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int gen_off, int fold) {
+// The slot workgroups are taken XCD by XCD: the x-th eighth of them runs on XCD
+// x (workgroup i goes to XCD i mod 8), so the parents an XCD reads come from a
+// few instances' populations and stay in its L2.
+__global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int gen_off, int fold, int slot_wgs) {
     int wg = blockIdx.x;
     if (fold) {
         if (wg < t.n_inst) {
@@ -655,6 +658,7 @@ __global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int ge
         }
         wg -= t.n_inst;
     }
+    wg = (wg % kXcds) * (slot_wgs / kXcds) + wg / kXcds;  // slot_wgs is a multiple of 8
     const int g = __builtin_amdgcn_readfirstlane(4 * wg + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (g >= t.inds[t.n_inst]) return;                     // the grid may exceed the total (capacity-sized graph)
@@ -689,9 +693,11 @@ __global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int ge
 
 hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
-    if (by_wave)
-        hipLaunchKernelGGL(k_breed_wave, dim3((fold ? t.n_inst : 0) + (total_inds + 3) / 4), dim3(256), 0, s, t,
-                           parity, gen_off, fold);
+    if (by_wave) {
+        const int slot_wgs = ((total_inds + 3) / 4 + kXcds - 1) / kXcds * kXcds;
+        hipLaunchKernelGGL(k_breed_wave, dim3((fold ? t.n_inst : 0) + slot_wgs), dim3(256), 0, s, t, parity, gen_off,
+                           fold, slot_wgs);
+    }
     else
         hipLaunchKernelGGL(k_breed, dim3(total_inds), dim3(256), 0, s, t, parity, gen_off, fold);
     return hipGetLastError();

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstring>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -152,15 +153,35 @@ int pick_variant(int form, int max_n, int total_p) {
     return 0;
 }
 
+// ---- launch sizes of pga_evolve ------------------------------------------------------
+// Counts and totals are rounded up to one of four values per octave (x -> the next
+// multiple of 2^(floor(log2 x) - 2)), and the instance list is padded with empty
+// descriptors (P = 0) to the rounded count: every kernel reads the real totals from
+// the device-side prefix tables and skips the workgroups past them, so a captured
+// graph serves every mix of instances whose sizes round to the same values (the
+// admissions and retirements of a serving loop), with at most a quarter of a launch
+// as padding.
+int bucket(int x) {
+    if (x <= 4) return x;
+    int e = 0;
+    while ((x >> (e + 1)) != 0) ++e;             // floor(log2 x)
+    const int u = 1 << (e - 2);
+    return (x + u - 1) / u * u;
+}
+
 // ---- workspace layout ----------------------------------------------------------
-// [InstDesc x n][prefix tiles n+1][prefix inds n+1]
+// [InstDesc x n][prefix tiles n+1][prefix inds n+1][route list counters kListCounters int32]
+// [route list entries: list_words(ceil(bucket(sum of P) / 4)) int32]
 // then per instance: [wsum P x N doubles][elite PGA_E_MAX int32]
 // and, for the BF16x2 form, [hi * 2^125 ld x ld][lo * 2^125 ld x ld] (bf16),
 // and, for SUS selection, [rank P int32][weight prefix P uint64],
 // then [route P int32][diagonal N + 1 doubles],
 // and, for the BF16x2 form, [labels with n_s >= 2: P x ceil(N / 32) uint32].
+// Everything a kernel argument points to (the head and the list) sits at an
+// offset that depends on n alone, so a captured graph serves every mix of n
+// slots; the per-instance regions are reached through the descriptors.
 struct Layout {
-    size_t desc_off, pre_off, inst_off;
+    size_t desc_off, pre_off, inst_off, list_off;
     std::vector<size_t> wsum_off, elite_off, hs_off, ls_off, rank_off, cum_off, route_off, diag_off, ns2_off;
     size_t total;
 };
@@ -169,8 +190,11 @@ Layout make_layout(const int32_t *Ns, const int32_t *Ps, int n, int form, const 
     Layout L;
     L.desc_off = 0;
     L.pre_off = align_up(sizeof(InstDesc) * (size_t)n, 256);
-    L.inst_off = align_up(L.pre_off + sizeof(int32_t) * 2 * ((size_t)n + 1), 256);
-    size_t off = L.inst_off;
+    L.inst_off = align_up(L.pre_off + sizeof(int32_t) * (2 * ((size_t)n + 1) + (size_t)kListCounters), 256);
+    L.list_off = L.inst_off;
+    int sum_p = 0;
+    for (int k = 0; k < n; ++k) sum_p += Ps[k];
+    size_t off = align_up(L.list_off + sizeof(int32_t) * list_words((bucket(sum_p) + 3) / 4), 256);
     for (int k = 0; k < n; ++k) {
         L.wsum_off.push_back(off);
         off = align_up(off + sizeof(double) * (size_t)Ns[k] * (size_t)Ps[k], 256);
@@ -205,24 +229,10 @@ Tables tables_at(void *ws, const Layout &L, int n) {
     t.desc = (const InstDesc *)(b + L.desc_off);
     t.tiles = (const int32_t *)(b + L.pre_off);
     t.inds = t.tiles + (n + 1);
+    t.sq = (int32_t *)(b + L.pre_off) + 2 * (n + 1);
+    t.sq_list = (int32_t *)(b + L.list_off);
     t.n_inst = n;
     return t;
-}
-
-// ---- launch sizes of pga_evolve ------------------------------------------------------
-// Counts and totals are rounded up to one of four values per octave (x -> the next
-// multiple of 2^(floor(log2 x) - 2)), and the instance list is padded with empty
-// descriptors (P = 0) to the rounded count: every kernel reads the real totals from
-// the device-side prefix tables and skips the workgroups past them, so a captured
-// graph serves every mix of instances whose sizes round to the same values (the
-// admissions and retirements of a serving loop), with at most a quarter of a launch
-// as padding.
-int bucket(int x) {
-    if (x <= 4) return x;
-    int e = 0;
-    while ((x >> (e + 1)) != 0) ++e;             // floor(log2 x)
-    const int u = 1 << (e - 2);
-    return (x + u - 1) / u * u;
 }
 
 // ---- the schedule ----------------------------------------------------------------
@@ -237,8 +247,9 @@ struct Shape {
 hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, int32_t *status,
                        hipStream_t s) {
     hipError_t e;
+    const int listed = sh.frac > 0.0 && sh.inds >= kManyInds ? 1 : 0;
     if (sh.frac > 0.0 &&
-        (e = timed(10, s, [&] { return launch_sparse(t, sh.inds, sh.max_n, parity, sh.frac, status, s); })) !=
+        (e = timed(10, s, [&] { return launch_sparse(t, sh.inds, sh.max_n, parity, sh.frac, listed, status, s); })) !=
             hipSuccess)
         return e;
     if (form == PGA_FORM_FP64) {
@@ -250,7 +261,7 @@ hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, i
         e = timed(1, s, [&] { return launch_pairsum_mfma(t, sh.tiles, parity, sh.v, sh.max_n, s); });
     }
     if (e != hipSuccess) return e;
-    return timed(2, s, [&] { return launch_finish(t, sh.inds, sh.max_n, parity, status, s); });
+    return timed(2, s, [&] { return launch_finish(t, sh.inds, sh.max_n, parity, listed, status, s); });
 }
 
 hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, int32_t *status,
@@ -261,7 +272,7 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
         if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
         // Without SUS or an early stop, breeding needs the ranking only for the elite
         // slots, and the breed kernel does it itself (fold); otherwise rank first.
-        const int by_wave = sh.max_n <= kBreedWaveMaxN ? 1 : 0;
+        const int by_wave = sh.max_n <= kBreedWaveMaxN && sh.inds >= kManyInds ? 1 : 0;
         const int fold = (!sh.sus && !sh.stop) ? 1 : 0;
         if (!fold && (e = timed(3, s, [&] { return launch_rank(t, k, 0, s); })) != hipSuccess) return e;
         if (sh.sus && (e = timed(8, s, [&] { return launch_sus(t, sh.max_p, s); })) != hipSuccess) return e;
@@ -749,6 +760,7 @@ int pga_evolve(pga_ctx *ctx, const pga_instance *inst, int32_t n_inst, int32_t g
     int32_t *pf = (int32_t *)(hb + L.pre_off);
     int32_t *pi = pf + (nb + 1);
     pf[0] = pi[0] = 0;
+    memset(pi + (nb + 1), 0, sizeof(int32_t) * kListCounters);     // the route lists start empty
     Shape sh{nb, 0, 0, 0, Variant{form, 0, 0, 0}, 0, 0, 0, route_frac()};
     int total_p = 0;
     for (int k = 0; k < n_inst; ++k) {

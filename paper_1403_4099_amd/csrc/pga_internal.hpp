@@ -46,8 +46,39 @@ struct Tables {
     const InstDesc *desc;
     const int32_t *tiles;       // prefix of pair-sum tiles (of the kernel variant in use)
     const int32_t *inds;        // prefix of individuals
+    int32_t *sq;                // route list counters (see list_count)
+    int32_t *sq_list;           // route list entries (see list_entry)
     int32_t n_inst;
 };
+
+// Workgroups of one launch are handed to the eight XCDs in turn (workgroup i
+// to XCD i mod 8), each XCD with its own L2.
+constexpr int kXcds = 8;
+
+// Route lists. With the cluster-pair route on, an evaluation of the population
+// of parity q sorts its individuals into two lists: those the cluster-pair
+// kernel evaluates (kListSparse) and those the pair-sum and finish evaluate
+// (kListDense), so that each of those launches has a workgroup per listed
+// individual only. A list is cut into kListSlices slices with a counter each,
+// so that its appends do not all meet on one address; an entry is the pair
+// (index in the instance, instance). The route kernel of parity q fills the
+// lists of q and empties those of 1 - q, which the evaluation before it used.
+constexpr int kListSlices = 1024;
+constexpr int kListSparse = 0, kListDense = 1;
+constexpr int kListCounters = 4 * kListSlices;     // [parity][list][slice]
+// Slices in use for a route launch of n_wg four-individual workgroups (one per
+// workgroup up to kListSlices, so the list launches of a small population are
+// no larger than a workgroup per individual), and entries per slice.
+__host__ __device__ constexpr int list_slices(int n_wg) {
+    return n_wg < 1 ? 1 : (n_wg < kListSlices ? n_wg : kListSlices);
+}
+__host__ __device__ constexpr int list_slice_cap(int n_wg) {
+    return 4 * ((n_wg + list_slices(n_wg) - 1) / list_slices(n_wg));
+}
+// int32 words of both lists' entries
+__host__ __device__ constexpr size_t list_words(int n_wg) {
+    return (size_t)2 * 2 * kListSlices * (size_t)list_slice_cap(n_wg);
+}
 
 // ---- geometry of the pair-sum kernels --------------------------------------
 constexpr int kFp64Waves = 4;                      // waves per workgroup, one column (stock) per lane
@@ -229,6 +260,13 @@ __device__ __forceinline__ bool ranks_before(double fa, int a, double fb, int b)
     return fa > fb || (fa == fb && a < b);
 }
 
+__device__ __forceinline__ int32_t *list_count(const Tables &t, int parity, int list, int slice) {
+    return t.sq + (2 * parity + list) * kListSlices + slice;
+}
+__device__ __forceinline__ int32_t *list_entry(const Tables &t, int list, int slice, int cap, int at) {
+    return t.sq_list + 2 * (((size_t)list * kListSlices + slice) * cap + at);
+}
+
 // ---- launchers (defined in the kernel translation units) ---------------------
 hipError_t launch_row_stats(const double *R, int N, int T, int64_t ld, double *mu, double *ss,
                             int32_t *status, hipStream_t s);
@@ -245,15 +283,23 @@ hipError_t launch_pairsum_mfma(Tables t, int total_tiles, int parity, const Vari
                                hipStream_t s);
 hipError_t launch_scale_split(Tables t, int max_ld, hipStream_t s);
 hipError_t launch_nsmask(Tables t, int total_inds, int max_n, int parity, hipStream_t s);
-hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int32_t *status, hipStream_t s);
+// listed: evaluate the dense route list of this parity (cluster-pair route on), else every individual.
+hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int listed, int32_t *status, hipStream_t s);
 hipError_t launch_diag(Tables t, int max_n, hipStream_t s);
-hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int32_t *status,
+// listed: route kernel and lists (kManyInds individuals or more), else a workgroup per individual.
+hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int listed, int32_t *status,
                          hipStream_t s);
 
 hipError_t launch_init(Tables t, int total_inds, hipStream_t s);
 hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s);
 // by_wave: one wave per slot instead of one workgroup per slot.
 hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, hipStream_t s);
+// Launches of at least kManyInds individuals (more than the chip holds at a
+// workgroup each) take the per-individual kernels' throughput forms: the
+// route lists and one wave per breed slot. Smaller ones (a serving batch, one
+// instance of a few thousand) are latency-bound: there a route launch is a
+// step more on every generation, and a workgroup per slot finishes sooner.
+constexpr int kManyInds = 8192;
 // Largest N bred with one wave per slot: above it a workgroup per slot keeps more
 // genes of one child in flight.
 constexpr int kBreedWaveMaxN = 1024;

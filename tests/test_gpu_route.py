@@ -260,3 +260,73 @@ def test_batch_mixing_an_instance_above_2048_equals_each_alone(form):
         torch.cuda.synchronize()
     for a, b in zip(alone, batch):
         assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness) and torch.equal(a.stats, b.stats)
+
+
+@pytest.mark.parametrize("N,P", [(300, 9000), (600, 8200)], ids=["wave-kernel", "workgroup-kernel"])
+def test_route_lists_of_a_large_launch_equal_the_per_individual_launches(N, P):
+    """A launch of 8192 individuals or more sorts them into route lists (a route kernel, then a
+    workgroup per listed individual); smaller launches take a workgroup per individual. The same
+    population evaluated whole and in small chunks gives the same bits, the pair route agrees with
+    the oracle, and an individual holding an entry above 1 inside a cluster is handed back to the
+    pair-sum route in the list form too."""
+    say(f"route lists N={N} P={P}")
+    C, planted = corr(N, T=64, seed=91)
+    C = C.copy()
+    C[3, 5] = C[5, 3] = 1.5
+    parts = [synth.random_labelings(P // 4, N, seed=92 + i, K=K) for i, K in enumerate((N, N // 4, 40, 9))]
+    pop = np.concatenate(parts)
+    pop[:: 97, 5] = pop[:: 97, 3]                          # pair (3, 5) in one cluster: the bad entry
+    for form in ("fp64", "bf16x2"):
+        Cg = _g(C)
+        hi = lo = None
+        if form == "bf16x2":
+            hi, lo = pga.split(Cg)
+        with pga.route(1.0 / 64):
+            whole = pga.fitness(Cg, _g(pop), form, hi=hi, lo=lo, want_ns=True)
+            parts_g = [pga.fitness(Cg, _g(pop[i:i + 2000]), form, hi=hi, lo=lo, want_ns=True)
+                       for i in range(0, len(pop), 2000)]
+        assert torch.equal(whole[0], torch.cat([f for f, _ in parts_g])), form
+        assert torch.equal(whole[1], torch.cat([n for _, n in parts_g])), form
+    f = whole[0].cpu().numpy()
+    pc = pair_counts(pop, N)
+    bad = pop[:, 3] == pop[:, 5]
+    on = (pc <= limit(1.0 / 64, N)) & ~bad
+    assert on.sum() > 100 and (~on).sum() > 100 and bad.sum() > 50
+    sample = np.flatnonzero(on)[:: 40]
+    Cc = np.clip(C, -1, 1)
+    f_o, mag = O.fitness(Cc, pop[sample], want_mag=True)
+    assert np.all(np.abs(f[sample] - f_o) <= fitness_tol(mag, 1e-10))
+    with pga.route(0.0):
+        dense = pga.fitness(_g(C), _g(pop[bad]), "fp64").cpu().numpy()
+    with pga.route(1.0 / 64):
+        listed_bad = pga.fitness(_g(C), _g(pop), "fp64").cpu().numpy()[bad]
+    assert np.array_equal(listed_bad, dense)
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16x2"])
+def test_batch_of_many_individuals_equals_each_instance_alone(form):
+    """16 instances of 520 individuals (8320 in one launch: route lists, one wave per breed slot)
+    evolve to the same bits as each instance alone (520: a workgroup per individual and slot)."""
+    G = 3
+    specs = [(int(n), 520, i) for i, n in enumerate(np.random.default_rng(5).integers(40, 400, size=16))]
+    say(f"many-individual batch {form}")
+    Cs = [corr(N, T=64, seed=100 + i)[0] for N, _, i in specs]
+
+    def inst(C, P, i):
+        Cg = _g(C)
+        hi = lo = None
+        if form == "bf16x2":
+            hi, lo = pga.split(Cg)
+        return pga.make_instance(Cg, P, hi=hi, lo=lo, stats_rows=G + 1, elites=2, seed=17, instance_id=i)
+
+    ctx = pga.Context()
+    with pga.route(1.0 / 64):
+        batch = [inst(C, P, i) for C, (N, P, i) in zip(Cs, specs)]
+        ctx.evolve(batch, G, form=form, init=True)
+        torch.cuda.synchronize()
+        for C, (N, P, i), b in zip(Cs, specs, batch):
+            a = inst(C, P, i)
+            pga.Context().evolve([a], G, form=form, init=True)
+            torch.cuda.synchronize()
+            assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness), i
+            assert torch.equal(a.stats, b.stats), i
