@@ -128,6 +128,30 @@ def batched_run(n_inst, form, generations=200, reps=2, tune_table=None):
             kern[kname] = {"avg_us": 1e3 * k_ms / n, "launches": n}
     pga.timing_enable(False)
     per_gen_kernels = sum(v["avg_us"] * v["launches"] for k, v in kern.items() if k != "init") / (generations + 1)
+    # ---- roofline of the cluster-pair step (route kernel + cluster-pair kernel, one launch each) on the
+    # generation-0 population: a call with no generations initialises and evaluates it once
+    pga.timing_enable(True)
+    pga.timing_reset()
+    for _ in range(3):
+        ctx.evolve(insts, 0, form=form, init=True)
+    torch.cuda.synchronize()
+    ms_cp, n_cp = pga.timing_read("cluster_pairs")
+    pga.timing_enable(False)
+    t_cp = 1e-3 * ms_cp / n_cp
+    frac_r = pga.route_get()
+    byts, listed = 0.0, 0
+    for I in insts:
+        wp = within_pairs(I.pop)
+        on = (wp <= np.floor(frac_r * 0.5 * I.N * (I.N - 1))) if I.N <= 2048 else np.zeros(len(wp), dtype=bool)
+        listed += int(on.sum())
+        byts += I.P * 4.0 * I.N + 8.0 * float(on.sum()) + 8.0 * float(wp[on].sum()) + 8.0 * I.N
+    ach = byts / t_cp / 1e9
+    roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM, "unit": "GB/s", "frac": ach / PEAK_HBM,
+            "traffic": None, "kernel": "k_route + k_sparse_wave", "avg_launch_us": 1e6 * t_cp,
+            "listed_share": listed / Ps,
+            "work_per_launch": "every individual's labels (4N B), and for those within the pair limit the "
+                               "fitness (8 B) and their within-cluster C entries (8 B each); each instance's "
+                               "diagonal once; generation-0 populations"}
     ctx.close()
     return {"instances": n_inst, "form": form, "generations": generations,
             "seconds_per_run": dt, "gens_per_s": generations / dt,
@@ -138,6 +162,7 @@ def batched_run(n_inst, form, generations=200, reps=2, tune_table=None):
                         "table_entries_saved": saved},
             "kernels_us": kern,
             "generation_us": {"graph_wall": 1e6 * dt / generations, "eager_kernel_sum": per_gen_kernels},
+            "roofline_cluster_pairs": roof,
             "workload": "256 instances, N ~ U{32..512}, T=1024, 2-12 planted clusters, P=512, G=200"}
 
 
