@@ -330,3 +330,40 @@ def test_batch_of_many_individuals_equals_each_instance_alone(form):
             torch.cuda.synchronize()
             assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness), i
             assert torch.equal(a.stats, b.stats), i
+
+
+def test_large_batch_with_sus_and_stopping_instances_equals_each_alone():
+    """A launch of more than 8192 individuals breeds one wave per slot: the SUS parent pick, the
+    elite copies from the rank kernel (no fold: some instances can stop) and stopped instances
+    take that kernel's paths. Every instance equals its own run (a workgroup per slot)."""
+    G = 7
+    rng = np.random.default_rng(12)
+    specs = []                                           # N, P, selection, stall, tol
+    for i in range(17):
+        sel = "sus" if i % 3 == 0 else "tournament"
+        stall, tol = ((3, 1e9) if i % 4 == 1 else (0, 1e-5))
+        specs.append((int(rng.integers(30, 300)), 500, sel, stall, tol))
+    assert sum(s[1] for s in specs) > 8192
+    say("large batch with SUS and stopping instances")
+    Cs = [corr(N, T=64, seed=140 + i)[0] for i, (N, *_r) in enumerate(specs)]
+
+    def inst(i, C, P, sel, stall, tol):
+        I = pga.make_instance(_g(C), P, stats_rows=G + 1, elites=2, seed=23, instance_id=i, selection=sel,
+                              stall_gens=stall, tol=tol)
+        I.stats.fill_(float("nan"))
+        return I
+
+    with pga.route(1.0 / 64):
+        batch = [inst(i, C, *s[1:]) for i, (C, s) in enumerate(zip(Cs, specs))]
+        pga.Context().evolve(batch, G, init=True)
+        torch.cuda.synchronize()
+        for i, (C, s) in enumerate(zip(Cs, specs)):
+            a = inst(i, C, *s[1:])
+            pga.Context().evolve([a], G, init=True)
+            torch.cuda.synchronize()
+            b = batch[i]
+            assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness), i
+            assert torch.equal(torch.nan_to_num(a.stats, nan=7.0), torch.nan_to_num(b.stats, nan=7.0)), i
+            assert a.term_state() == b.term_state(), i
+    stopped = [b.term_state()["stopped"] for b in batch]
+    assert any(stopped) and not all(stopped)
