@@ -200,8 +200,8 @@ int pga_ewma(const double *R, int32_t N, int32_t T, int32_t ld_r, double lambda,
  * C_hi/C_lo may be NULL for PGA_FORM_FP64. P = 0 is a no-op.
  * Route (both forms, also inside pga_evolve): c_s only involves the pairs
  * within each cluster, so an individual whose clusters hold at most
- * frac * N (N - 1) / 2 pairs (frac: pga_route_get) and N <= 2048 is
- * evaluated from those pairs alone: FP64 entries of C (diagonal and i < j)
+ * floor(frac * N (N - 1) / 2) pairs (frac: pga_route_get; every pair when
+ * N <= 64) and N <= 2048 is evaluated from those pairs alone: FP64 entries of C (diagonal and i < j)
  * summed exactly in 64-bit fixed point, in either form. An individual with a
  * larger pair count, or whose cluster pairs meet an entry with |C_ij| > 1 or
  * not finite, takes the O(N^2) pair-sum of the form as described above. */
@@ -235,7 +235,8 @@ int pga_fitness_noalloc(const double *C, const uint16_t *C_hi, const uint16_t *C
 /* Cluster-pair route limit (process-wide, read at each call; pga_evolve's
  * cached graphs are keyed by it): frac in [0, 1]; 0 sends every individual to
  * the pair-sum kernels; 1 sends every individual with N <= 2048 to the
- * cluster-pair kernel. PGA_ERR_ARG outside [0, 1] or NaN. */
+ * cluster-pair kernel; any frac > 0 sends every individual with N <= 64 there.
+ * PGA_ERR_ARG outside [0, 1] or NaN. */
 #define PGA_ROUTE_FRAC_DEFAULT (1.0 / 64.0)
 int pga_route_set(double frac);
 double pga_route_get(void);

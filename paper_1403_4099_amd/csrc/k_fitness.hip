@@ -743,7 +743,7 @@ __global__ __launch_bounds__(256) void k_route(Tables t, int lds_n, int parity, 
             }
 #pragma unroll
             for (int m = 32; m > 0; m >>= 1) pairs += __shfl_xor(pairs, m, 64);
-            const bool sparse = __any(bad) || (double)pairs <= floor(frac * 0.5 * (double)N * (double)(N - 1));
+            const bool sparse = __any(bad) || (double)pairs <= route_limit(N, frac);
             if (lane == 0) gst(d.route + p, sparse ? 0 : 1);
             mine = sparse ? kListSparse : kListDense;
         }
@@ -867,7 +867,7 @@ __device__ void sparse_one(const Tables &t, int k, int p, int slice, int cap, in
     // begin[s]: first position of cluster s; PP[s]: pairs of the clusters below s
     int nmax;
     const int T = block_exscan_cnt_pairs(cnt, begin, PP, N, ired + 4, nmax);   // T == pairs
-    if ((double)T > floor(frac * 0.5 * (double)N * (double)(N - 1))) {
+    if ((double)T > route_limit(N, frac)) {
         if (tid == 0) {
             gst(d.route + p, 1);
             list_dense(t, parity, slice, cap, p, k);
@@ -1078,7 +1078,7 @@ __device__ void sparse_one_wave(const Tables &t, int k, int p, int slice, int ca
         T += __shfl_xor(T, m, 64);
         nmax = max(nmax, __shfl_xor(nmax, m, 64));
     }
-    if ((double)T > floor(frac * 0.5 * (double)N * (double)(N - 1))) {
+    if ((double)T > route_limit(N, frac)) {
         if (lane == 0) {
             gst(d.route + p, 1);
             list_dense(t, parity, slice, cap, p, k);

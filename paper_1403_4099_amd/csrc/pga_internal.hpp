@@ -260,6 +260,16 @@ __device__ __forceinline__ bool ranks_before(double fa, int a, double fb, int b)
     return fa > fb || (fa == fb && a < b);
 }
 
+// Cluster-pair route limit of an instance of N stocks: frac N (N - 1) / 2 pairs,
+// and every pair when N <= 64 (a 64-stock block is the pair-sum's smallest unit
+// of work per individual, and its finish a workgroup per individual, while the
+// cluster-pair evaluation is bounded by the N (N - 1) / 2 <= 2016 pairs).
+constexpr int kRouteAllPairsMaxN = 64;
+__host__ __device__ __forceinline__ double route_limit(int N, double frac) {
+    const double all = 0.5 * (double)N * (double)(N - 1);
+    return N <= kRouteAllPairsMaxN ? all : floor(frac * all);
+}
+
 __device__ __forceinline__ int32_t *list_count(const Tables &t, int parity, int list, int slice) {
     return t.sq + (2 * parity + list) * kListSlices + slice;
 }

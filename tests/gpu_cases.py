@@ -89,8 +89,9 @@ def pair_counts(pop, N):
 
 
 def route_limit(frac, N):
-    """Largest pair count the cluster-pair route takes at limit `frac` (N <= 2048)."""
-    return int(np.floor(frac * 0.5 * N * (N - 1)))
+    """Largest pair count the cluster-pair route takes at limit `frac` (N <= 2048; every pair when
+    N <= 64)."""
+    return N * (N - 1) // 2 if N <= 64 else int(np.floor(frac * 0.5 * N * (N - 1)))
 
 
 def check_bf16x2_fitness(C, hi_bits, lo_bits, pop, f_gpu, frac):

@@ -33,7 +33,7 @@ def pair_counts(pop, N):
 
 
 def limit(frac, N):
-    return math.floor(frac * 0.5 * N * (N - 1))
+    return N * (N - 1) // 2 if N <= 64 else math.floor(frac * 0.5 * N * (N - 1))
 
 
 def _fit(C, pop, form, frac, **kw):
