@@ -723,6 +723,9 @@ __global__ __launch_bounds__(256) void k_route(Tables t, int lds_n, int parity, 
         } else if (N > lds_n) {                      // lds_n <= kSparseMaxN
             if (lane == 0) gst(d.route + p, 1);
             mine = kListDense;
+        } else if (N <= kRouteAllPairsMaxN) {        // within the limit whatever its labels
+            if (lane == 0) gst(d.route + p, 0);
+            mine = kListSparse;
         } else {
             int *cnt = (int *)(smem + (size_t)wave * pad16(4 * (size_t)lds_n));
             for (int s = lane; s < N; s += 64) cnt[s] = 0;

@@ -600,7 +600,7 @@ __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off
 // keeps its termination state and statistics row, and the slot workgroups
 // follow; otherwise the elite slots copy the individuals the rank kernel
 // listed.
-__device__ void fold_rank(const Tables &t, int k, int parity, int gen_off) {
+__device__ __forceinline__ void fold_rank(const Tables &t, int k, int parity, int gen_off) {
     __shared__ RankLds sh;
     const InstDesc &d = t.desc[k];
     const int P = d.P, E = d.E, N = d.N;
@@ -649,7 +649,14 @@ __device__ void fold_rank(const Tables &t, int k, int parity, int gen_off) {
 // The slot workgroups are taken XCD by XCD: the x-th eighth of them runs on XCD
 // x (workgroup i goes to XCD i mod 8), so the parents an XCD reads come from a
 // few instances' populations and stay in its L2.
+// GL lanes per slot: 64 (one wave), or 32 and 16 when the launch's largest N
+// is at most 2 GL genes (a lane makes two genes per pass), so that a wave
+// breeds 64 / GL children at the paper's sizes (N = 18) instead of keeping 55
+// of its 64 lanes idle. The lanes of one slot share its instance and child,
+// so their control flow is the same.
+template <int GL>
 __global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int gen_off, int fold, int slot_wgs) {
+    constexpr int S = 64 / GL;                             // slots per wave
     int wg = blockIdx.x;
     if (fold) {
         if (wg < t.n_inst) {
@@ -659,8 +666,9 @@ __global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int ge
         wg -= t.n_inst;
     }
     wg = (wg % kXcds) * (slot_wgs / kXcds) + wg / kXcds;  // slot_wgs is a multiple of 8
-    const int g = __builtin_amdgcn_readfirstlane(4 * wg + (int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, sub = lane / GL, gl = lane % GL;
+    int g = (4 * wg + (int)(threadIdx.x >> 6)) * S + sub;
+    if constexpr (GL == 64) g = __builtin_amdgcn_readfirstlane(g);
     if (g >= t.inds[t.n_inst]) return;                     // the grid may exceed the total (capacity-sized graph)
     const int k = find_inst(t.inds, t.n_inst, g);
     const InstDesc &d = t.desc[k];
@@ -672,31 +680,44 @@ __global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int ge
     if (c < E) {
         if (fold) return;                                  // copied by the instance's ranking workgroup
         const int32_t *__restrict__ e = src + (size_t)d.elite[c] * N;
-        for (int j = lane; j < N; j += 64) out[j] = e[j];
+        for (int j = gl; j < N; j += GL) out[j] = e[j];
         return;
     }
     const uint32_t gen = d.gen0 + (uint32_t)gen_off;
     int A, B;
     if (d.selection == PGA_SELECT_SUS) {
         int pick = 0;
-        if (lane < 2) pick = sus_parent(d, c, gen, lane);
-        A = __builtin_amdgcn_readlane(pick, 0);
-        B = __builtin_amdgcn_readlane(pick, 1);
+        if (gl < 2) pick = sus_parent(d, c, gen, gl);
+        if constexpr (GL == 64) {
+            A = __builtin_amdgcn_readlane(pick, 0);
+            B = __builtin_amdgcn_readlane(pick, 1);
+        } else {                                           // from the slot's first two lanes
+            A = __shfl(pick, sub * GL, 64);
+            B = __shfl(pick, sub * GL + 1, 64);
+        }
     } else {
         const double *__restrict__ f = d.fitness;
         const U4 sel = draw(0u, (uint32_t)c, gen, kTagSel, d.inst_id, d.seed);
         A = tournament2(f, (int)scale_u32(sel.x, (uint32_t)P), (int)scale_u32(sel.y, (uint32_t)P));
         B = tournament2(f, (int)scale_u32(sel.z, (uint32_t)P), (int)scale_u32(sel.w, (uint32_t)P));
     }
-    breed_genes(d, c, gen, src + (size_t)A * N, src + (size_t)B * N, out, lane, 64);
+    breed_genes(d, c, gen, src + (size_t)A * N, src + (size_t)B * N, out, gl, GL);
 }
 
-hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, hipStream_t s) {
+hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, int max_n,
+                        hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
     if (by_wave) {
-        const int slot_wgs = ((total_inds + 3) / 4 + kXcds - 1) / kXcds * kXcds;
-        hipLaunchKernelGGL(k_breed_wave, dim3((fold ? t.n_inst : 0) + slot_wgs), dim3(256), 0, s, t, parity, gen_off,
-                           fold, slot_wgs);
+        const int gl = max_n <= 32 ? 16 : max_n <= 64 ? 32 : 64;   // lanes per slot
+        const int per_wg = 4 * (64 / gl);                          // slots per workgroup
+        const int slot_wgs = ((total_inds + per_wg - 1) / per_wg + kXcds - 1) / kXcds * kXcds;
+        const dim3 grid((fold ? t.n_inst : 0) + slot_wgs);
+        if (gl == 16)
+            hipLaunchKernelGGL(k_breed_wave<16>, grid, dim3(256), 0, s, t, parity, gen_off, fold, slot_wgs);
+        else if (gl == 32)
+            hipLaunchKernelGGL(k_breed_wave<32>, grid, dim3(256), 0, s, t, parity, gen_off, fold, slot_wgs);
+        else
+            hipLaunchKernelGGL(k_breed_wave<64>, grid, dim3(256), 0, s, t, parity, gen_off, fold, slot_wgs);
     }
     else
         hipLaunchKernelGGL(k_breed, dim3(total_inds), dim3(256), 0, s, t, parity, gen_off, fold);

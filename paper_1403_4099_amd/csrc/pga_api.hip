@@ -276,7 +276,7 @@ hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, in
         const int fold = (!sh.sus && !sh.stop) ? 1 : 0;
         if (!fold && (e = timed(3, s, [&] { return launch_rank(t, k, 0, s); })) != hipSuccess) return e;
         if (sh.sus && (e = timed(8, s, [&] { return launch_sus(t, sh.max_p, s); })) != hipSuccess) return e;
-        if ((e = timed(4, s, [&] { return launch_breed(t, sh.inds, parity, k, fold, by_wave, s); })) != hipSuccess)
+        if ((e = timed(4, s, [&] { return launch_breed(t, sh.inds, parity, k, fold, by_wave, sh.max_n, s); })) != hipSuccess)
             return e;
     }
     const int parity = G & 1;

@@ -303,7 +303,8 @@ hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double
 hipError_t launch_init(Tables t, int total_inds, hipStream_t s);
 hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s);
 // by_wave: one wave per slot instead of one workgroup per slot.
-hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, hipStream_t s);
+hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, int max_n,
+                        hipStream_t s);
 // Launches of at least kManyInds individuals (more than the chip holds at a
 // workgroup each) take the per-individual kernels' throughput forms: the
 // route lists and one wave per breed slot. Smaller ones (a serving batch, one

@@ -367,3 +367,31 @@ def test_large_batch_with_sus_and_stopping_instances_equals_each_alone():
             assert a.term_state() == b.term_state(), i
     stopped = [b.term_state()["stopped"] for b in batch]
     assert any(stopped) and not all(stopped)
+
+
+@pytest.mark.parametrize("nlo,nhi", [(8, 32), (33, 64)], ids=["16-lane-slots", "32-lane-slots"])
+def test_large_batch_of_small_instances_equals_each_alone(nlo, nhi):
+    """Launches of more than 8192 individuals whose largest N is at most 32 (64) breed four (two)
+    children per wave, 16 (32) lanes each; with SUS and tournament instances, every instance
+    equals its own run (a workgroup per slot)."""
+    G = 4
+    rng = np.random.default_rng(nhi)
+    specs = [(int(rng.integers(nlo, nhi + 1)), 450, "sus" if i % 4 == 0 else "tournament") for i in range(20)]
+    specs[0] = (nhi, 450, "sus")
+    say(f"large batch of small instances N in [{nlo}, {nhi}]")
+    Cs = [corr(N, T=64, seed=170 + i)[0] for i, (N, *_r) in enumerate(specs)]
+
+    def inst(i, C, P, sel):
+        return pga.make_instance(_g(C), P, stats_rows=G + 1, elites=3, seed=31, instance_id=i, selection=sel)
+
+    with pga.route(1.0 / 64):
+        batch = [inst(i, C, P, sel) for i, (C, (N, P, sel)) in enumerate(zip(Cs, specs))]
+        pga.Context().evolve(batch, G, init=True)
+        torch.cuda.synchronize()
+        for i, (C, (N, P, sel)) in enumerate(zip(Cs, specs)):
+            a = inst(i, C, P, sel)
+            pga.Context().evolve([a], G, init=True)
+            torch.cuda.synchronize()
+            b = batch[i]
+            assert torch.equal(a.pop, b.pop) and torch.equal(a.fitness, b.fitness), i
+            assert torch.equal(a.stats, b.stats), i
