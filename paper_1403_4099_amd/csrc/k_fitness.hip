@@ -1305,12 +1305,12 @@ __global__ __launch_bounds__(kFinThreads) void k_sparse(Tables t, int lds_n, int
     sparse_one(t, k, p, slice, cap, lds_n, parity, frac, status, smem);
 }
 
-hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int listed, int32_t *status,
-                         hipStream_t s) {
+hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int listed, int lists_ready,
+                         int32_t *status, hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
     const int n = std::min(max_n, kSparseMaxN);
     const int n_wg = (total_inds + 3) / 4, slices = list_slices(n_wg), cap = list_slice_cap(n_wg);
-    if (listed) {
+    if (listed && !lists_ready) {
         hipLaunchKernelGGL(k_route, dim3(n_wg), dim3(256), route_lds_bytes(n), s, t, n, parity, frac, slices, cap);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

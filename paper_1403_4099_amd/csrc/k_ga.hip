@@ -600,7 +600,10 @@ __global__ __launch_bounds__(256) void k_breed(Tables t, int parity, int gen_off
 // keeps its termination state and statistics row, and the slot workgroups
 // follow; otherwise the elite slots copy the individuals the rank kernel
 // listed.
-__device__ __forceinline__ void fold_rank(const Tables &t, int k, int parity, int gen_off) {
+// classify (every N <= 64): also append the elites to the next evaluation's
+// sparse list.
+__device__ __forceinline__ void fold_rank(const Tables &t, int k, int parity, int gen_off, int classify, int slices,
+                                          int cap) {
     __shared__ RankLds sh;
     const InstDesc &d = t.desc[k];
     const int P = d.P, E = d.E, N = d.N;
@@ -644,6 +647,8 @@ __device__ __forceinline__ void fold_rank(const Tables &t, int k, int parity, in
             for (int q = 0; q < kQ; ++q)
                 if (q < E) dst[(size_t)q * N + j] = v[q];
         }
+    if (classify && threadIdx.x == 0)
+        for (int r = 0; r < E; ++r) route_append(t, d, k, r, t.inds[k] + r, parity ^ 1, kListSparse, slices, cap);
 }
 
 // The slot workgroups are taken XCD by XCD: the x-th eighth of them runs on XCD
@@ -654,13 +659,21 @@ __device__ __forceinline__ void fold_rank(const Tables &t, int k, int parity, in
 // breeds 64 / GL children at the paper's sizes (N = 18) instead of keeping 55
 // of its 64 lanes idle. The lanes of one slot share its instance and child,
 // so their control flow is the same.
+// classify (the launch's largest N is at most 64, so every individual takes
+// the cluster-pair route): the writer of each slot (the slot's lanes, or the
+// ranking workgroup for the elites it copies) appends it to the next
+// evaluation's sparse list, and workgroup 0 empties this parity's lists, which
+// the evaluation just done used; that evaluation then needs no route kernel.
 template <int GL>
-__global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int gen_off, int fold, int slot_wgs) {
+__global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int gen_off, int fold, int slot_wgs,
+                                                    int classify, int slices, int cap) {
     constexpr int S = 64 / GL;                             // slots per wave
+    if (classify && blockIdx.x == 0)
+        for (int i = threadIdx.x; i < 2 * kListSlices; i += 256) gst(list_count(t, parity, 0, 0) + i, 0);
     int wg = blockIdx.x;
     if (fold) {
         if (wg < t.n_inst) {
-            fold_rank(t, wg, parity, gen_off);
+            fold_rank(t, wg, parity, gen_off, classify, slices, cap);
             return;
         }
         wg -= t.n_inst;
@@ -677,10 +690,14 @@ __global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int ge
     const int c = g - t.inds[k];
     const int32_t *__restrict__ src = d.pop[parity];
     int32_t *__restrict__ out = d.pop[parity ^ 1] + (size_t)c * N;
+    auto finish_slot = [&]() {
+        if (classify && gl == 0) route_append(t, d, k, c, g, parity ^ 1, kListSparse, slices, cap);
+    };
     if (c < E) {
         if (fold) return;                                  // copied by the instance's ranking workgroup
         const int32_t *__restrict__ e = src + (size_t)d.elite[c] * N;
         for (int j = gl; j < N; j += GL) out[j] = e[j];
+        finish_slot();
         return;
     }
     const uint32_t gen = d.gen0 + (uint32_t)gen_off;
@@ -702,22 +719,27 @@ __global__ __launch_bounds__(256) void k_breed_wave(Tables t, int parity, int ge
         B = tournament2(f, (int)scale_u32(sel.z, (uint32_t)P), (int)scale_u32(sel.w, (uint32_t)P));
     }
     breed_genes(d, c, gen, src + (size_t)A * N, src + (size_t)B * N, out, gl, GL);
+    finish_slot();
 }
 
 hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, int max_n,
-                        hipStream_t s) {
+                        int classify, hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
     if (by_wave) {
         const int gl = max_n <= 32 ? 16 : max_n <= 64 ? 32 : 64;   // lanes per slot
         const int per_wg = 4 * (64 / gl);                          // slots per workgroup
         const int slot_wgs = ((total_inds + per_wg - 1) / per_wg + kXcds - 1) / kXcds * kXcds;
+        const int n_wg = (total_inds + 3) / 4, slices = list_slices(n_wg), cap = list_slice_cap(n_wg);
         const dim3 grid((fold ? t.n_inst : 0) + slot_wgs);
         if (gl == 16)
-            hipLaunchKernelGGL(k_breed_wave<16>, grid, dim3(256), 0, s, t, parity, gen_off, fold, slot_wgs);
+            hipLaunchKernelGGL(k_breed_wave<16>, grid, dim3(256), 0, s, t, parity, gen_off, fold, slot_wgs, classify,
+                               slices, cap);
         else if (gl == 32)
-            hipLaunchKernelGGL(k_breed_wave<32>, grid, dim3(256), 0, s, t, parity, gen_off, fold, slot_wgs);
+            hipLaunchKernelGGL(k_breed_wave<32>, grid, dim3(256), 0, s, t, parity, gen_off, fold, slot_wgs, classify,
+                               slices, cap);
         else
-            hipLaunchKernelGGL(k_breed_wave<64>, grid, dim3(256), 0, s, t, parity, gen_off, fold, slot_wgs);
+            hipLaunchKernelGGL(k_breed_wave<64>, grid, dim3(256), 0, s, t, parity, gen_off, fold, slot_wgs, classify,
+                               slices, cap);
     }
     else
         hipLaunchKernelGGL(k_breed, dim3(total_inds), dim3(256), 0, s, t, parity, gen_off, fold);

@@ -244,13 +244,15 @@ struct Shape {
     double frac;         // cluster-pair route limit (0: off; then every route pointer is null)
 };
 
-hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, int32_t *status,
-                       hipStream_t s) {
+// lists_ready: the breed launch that made this population already filled its route lists.
+hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, int32_t *status, hipStream_t s,
+                       int lists_ready = 0) {
     hipError_t e;
     const int listed = sh.frac > 0.0 && sh.inds >= kManyInds ? 1 : 0;
-    if (sh.frac > 0.0 &&
-        (e = timed(10, s, [&] { return launch_sparse(t, sh.inds, sh.max_n, parity, sh.frac, listed, status, s); })) !=
-            hipSuccess)
+    if (sh.frac > 0.0 && (e = timed(10, s, [&] {
+                              return launch_sparse(t, sh.inds, sh.max_n, parity, sh.frac, listed, lists_ready, status,
+                                                   s);
+                          })) != hipSuccess)
         return e;
     if (form == PGA_FORM_FP64) {
         e = timed(0, s, [&] { return launch_pairsum_fp64(t, sh.tiles, parity, sh.v, s); });
@@ -267,20 +269,27 @@ hipError_t run_fitness(const Tables &t, const Shape &sh, int form, int parity, i
 hipError_t run_generations(const Tables &t, const Shape &sh, int form, int G, int32_t *status,
                            hipStream_t s) {
     hipError_t e;
+    int lists_ready = 0;
     for (int k = 0; k < G; ++k) {
         const int parity = k & 1;
-        if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
+        if ((e = run_fitness(t, sh, form, parity, status, s, lists_ready)) != hipSuccess) return e;
         // Without SUS or an early stop, breeding needs the ranking only for the elite
         // slots, and the breed kernel does it itself (fold); otherwise rank first.
         const int by_wave = sh.max_n <= kBreedWaveMaxN && sh.inds >= kManyInds ? 1 : 0;
         const int fold = (!sh.sus && !sh.stop) ? 1 : 0;
+        // with the route lists in use and every N <= 64 (every individual on the cluster-pair
+        // route), the wave-per-slot breed fills the next evaluation's list itself
+        const int classify = by_wave && sh.frac > 0.0 && sh.max_n <= kRouteAllPairsMaxN ? 1 : 0;
         if (!fold && (e = timed(3, s, [&] { return launch_rank(t, k, 0, s); })) != hipSuccess) return e;
         if (sh.sus && (e = timed(8, s, [&] { return launch_sus(t, sh.max_p, s); })) != hipSuccess) return e;
-        if ((e = timed(4, s, [&] { return launch_breed(t, sh.inds, parity, k, fold, by_wave, sh.max_n, s); })) != hipSuccess)
+        if ((e = timed(4, s, [&] {
+                 return launch_breed(t, sh.inds, parity, k, fold, by_wave, sh.max_n, classify, s);
+             })) != hipSuccess)
             return e;
+        lists_ready = classify;
     }
     const int parity = G & 1;
-    if ((e = run_fitness(t, sh, form, parity, status, s)) != hipSuccess) return e;
+    if ((e = run_fitness(t, sh, form, parity, status, s, lists_ready)) != hipSuccess) return e;
     if ((e = timed(3, s, [&] { return launch_rank(t, G, 1, s); })) != hipSuccess) return e;
     return launch_copy_back(t, sh.inds, G, s);
 }

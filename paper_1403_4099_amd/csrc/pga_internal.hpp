@@ -276,6 +276,18 @@ __device__ __forceinline__ int32_t *list_count(const Tables &t, int parity, int 
 __device__ __forceinline__ int32_t *list_entry(const Tables &t, int list, int slice, int cap, int at) {
     return t.sq_list + 2 * (((size_t)list * kListSlices + slice) * cap + at);
 }
+// Individual p of instance k (global index g) joins list L of `parity` in the
+// slice of its four-individual group, g / 4 mod slices, with its route flag
+// (one thread). A slice then holds at most the list_slice_cap individuals of
+// its groups, whichever kernel classified them.
+__device__ __forceinline__ void route_append(const Tables &t, const InstDesc &d, int k, int p, int g, int parity,
+                                             int L, int slices, int cap) {
+    gst(d.route + p, L == kListSparse ? 0 : 1);
+    const int slice = (g >> 2) % slices;
+    int32_t *e = list_entry(t, L, slice, cap, atomicAdd(list_count(t, parity, L, slice), 1));
+    gst(e, p);
+    gst(e + 1, k);
+}
 
 // ---- launchers (defined in the kernel translation units) ---------------------
 hipError_t launch_row_stats(const double *R, int N, int T, int64_t ld, double *mu, double *ss,
@@ -296,15 +308,19 @@ hipError_t launch_nsmask(Tables t, int total_inds, int max_n, int parity, hipStr
 // listed: evaluate the dense route list of this parity (cluster-pair route on), else every individual.
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int listed, int32_t *status, hipStream_t s);
 hipError_t launch_diag(Tables t, int max_n, hipStream_t s);
-// listed: route kernel and lists (kManyInds individuals or more), else a workgroup per individual.
-hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int listed, int32_t *status,
-                         hipStream_t s);
+// listed: route lists (kManyInds individuals or more), filled by the route kernel unless the breed
+// launch before already did (lists_ready); else a workgroup per individual.
+hipError_t launch_sparse(Tables t, int total_inds, int max_n, int parity, double frac, int listed, int lists_ready,
+                         int32_t *status, hipStream_t s);
 
 hipError_t launch_init(Tables t, int total_inds, hipStream_t s);
 hipError_t launch_rank(Tables t, int gen_off, int final, hipStream_t s);
 // by_wave: one wave per slot instead of one workgroup per slot.
+// classify (wave form, route lists in use, largest N <= 64): each slot's writer
+// appends the new individual to the next evaluation's sparse list, so that
+// evaluation needs no route kernel.
 hipError_t launch_breed(Tables t, int total_inds, int parity, int gen_off, int fold, int by_wave, int max_n,
-                        hipStream_t s);
+                        int classify, hipStream_t s);
 // Launches of at least kManyInds individuals (more than the chip holds at a
 // workgroup each) take the per-individual kernels' throughput forms: the
 // route lists and one wave per breed slot. Smaller ones (a serving batch, one
