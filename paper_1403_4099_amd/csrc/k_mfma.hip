@@ -105,7 +105,8 @@ struct MfmaLdsCols {
 };
 
 // One column block jb (64 stocks, 16 per wave) for the B individuals of batch pb.
-// On entry every code table entry below N holds kCodeNone; it is restored on exit.
+// On entry every code table entry below N holds kCodeNone; the entries it sets
+// stay set (the launching kernel clears the tables before the next block).
 template <int B>
 __device__ __forceinline__ void mfma_block_cols(const InstDesc &d, int jb, int pb, int parity, const MfmaLdsCols &s) {
     constexpr int RC = kMfmaRowCodes / B;                     // rows staged per pass
@@ -325,11 +326,6 @@ __device__ __forceinline__ void mfma_block_cols(const InstDesc &d, int jb, int p
             const int p = pbase + b;
             if (p < P) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[b], cjj));
         }
-    }
-    // Restore the table (every reader passed the barrier that closes the row loop).
-    if (g == 0) {
-#pragma unroll
-        for (int b = 0; b < B; ++b) code(b, (int)lj[b]) = kCodeNone;
     }
 }
 
@@ -662,7 +658,8 @@ __device__ __forceinline__ uint32_t shfl_xor32(uint32_t v, int m) {
 }
 
 // One column block jb (64 stocks, 16 per wave) for the B individuals of batch pb.
-// On entry every code table entry below N holds kCodeNone; it is restored on exit.
+// On entry every code table entry below N holds kCodeNone; the entries it sets
+// stay set (the launching kernel clears the tables before the next block).
 template <int B>
 __device__ __forceinline__ void mfma_block_packed(const InstDesc &d, int jb, int pb, int parity, const MfmaLdsPacked &s) {
     constexpr int RC = mfma_rows(B);                          // rows staged per pass
@@ -929,11 +926,6 @@ __device__ __forceinline__ void mfma_block_packed(const InstDesc &d, int jb, int
             if (mylive[u]) gst(d.wsum + (size_t)p * N + j, fma(2.0, acc64[u], cjj));
         }
     }
-    // Restore the table (every reader passed the barrier that closes the row loop).
-    if (g == 0) {
-#pragma unroll
-        for (int b = 0; b < B; ++b) code(b, (int)lj[b]) = kCodeNone;
-    }
 }
 
 // The triangle is folded: column blocks n_jb-1-jp and jp share a workgroup, so every
@@ -961,13 +953,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
             if (pb * B + b < d.P) any |= gld(d.route + pb * B + b);
         if (!any) return;
     }
+    // Label -> code tables: every entry below N set to kCodeNone (N <= cstride, a
+    // multiple of 16). The column and packed blocks leave their entries set, and
+    // the tables are cleared again between the two blocks of a folded pair (a
+    // block's last reads of them precede the barrier that closes its row loop);
+    // the LUT block restores its own entries.
     uint8_t *code = lds + mfma_lds_code_off(B, KIND);
-    {
-        const int words = (d.N + 3) / 4;                      // N <= cstride, a multiple of 16
+    auto clear_codes = [&]() {
+        const int words = (d.N + 3) / 4;
 #pragma unroll
         for (int b = 0; b < B; ++b)
             for (int w = threadIdx.x; w < words; w += 256) *(uint32_t *)(code + (size_t)b * cstride + 4 * w) = 0xFFFFFFFFu;
-    }
+    };
+    clear_codes();
     if constexpr (KIND == kKindLut) lut_table_init(lds);
     __syncthreads();
     if constexpr (KIND == kKindPacked) {
@@ -975,6 +973,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
                               (uint32_t *)(lds + mfma_lds_scratch_off(B, cstride, KIND)), cstride};
         mfma_block_packed<B>(d, n_jb - 1 - jp, pb, parity, s);
         if (jp != n_jb - 1 - jp) {
+            clear_codes();
             __syncthreads();
             mfma_block_packed<B>(d, jp, pb, parity, s);
         }
@@ -988,6 +987,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
         const MfmaLdsCols s{(uint32_t *)lds, code, lds + mfma_lds_ring_off(B, cstride, KIND), cstride};
         mfma_block_cols<B>(d, n_jb - 1 - jp, pb, parity, s);
         if (jp != n_jb - 1 - jp) {
+            clear_codes();
             __syncthreads();
             mfma_block_cols<B>(d, jp, pb, parity, s);
         }
