@@ -953,17 +953,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
             if (pb * B + b < d.P) any |= gld(d.route + pb * B + b);
         if (!any) return;
     }
-    // Label -> code tables: every entry below N set to kCodeNone (N <= cstride, a
-    // multiple of 16). The column and packed blocks leave their entries set, and
-    // the tables are cleared again between the two blocks of a folded pair (a
-    // block's last reads of them precede the barrier that closes its row loop);
-    // the LUT block restores its own entries.
+    // Label -> code tables: every entry set to kCodeNone (B tables of cstride bytes,
+    // one contiguous, 16-byte aligned region; cstride >= N is a multiple of 16). The
+    // column and packed blocks leave their entries set, and the tables are cleared
+    // again between the two blocks of a folded pair (a block's last reads of them
+    // precede the barrier that closes its row loop); the LUT block restores its own
+    // entries.
     uint8_t *code = lds + mfma_lds_code_off(B, KIND);
     auto clear_codes = [&]() {
-        const int words = (d.N + 3) / 4;
-#pragma unroll
-        for (int b = 0; b < B; ++b)
-            for (int w = threadIdx.x; w < words; w += 256) *(uint32_t *)(code + (size_t)b * cstride + 4 * w) = 0xFFFFFFFFu;
+        const int n16 = B * cstride / 16;
+        for (int i = threadIdx.x; i < n16; i += 256)
+            *(uint4 *)(code + 16 * (size_t)i) = uint4{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
     };
     clear_codes();
     if constexpr (KIND == kKindLut) lut_table_init(lds);
