@@ -65,6 +65,9 @@ constexpr int kCodeShift = 8;
 constexpr uint16_t kOneHot = 0x0100;        // bf16 2^-125
 constexpr uint8_t kCodeNone = 0xFF;         // row label not present in the column block
 constexpr uint32_t kCodeFree = 0xFE;        // column of a group left unused: matches no row
+// Fourth word of a raw buffer descriptor (no swizzle, no stride, 32-bit data
+// format): byte addressing from the base, loads past num_records return zero.
+constexpr int kBufWord3 = 0x00020000;
 
 __device__ __forceinline__ uint32_t onehot2(uint32_t rows2, uint32_t col2) {
     const u16x2 x = __builtin_bit_cast(u16x2, rows2 ^ col2);
@@ -169,17 +172,25 @@ __device__ __forceinline__ void mfma_block_cols(const InstDesc &d, int jb, int p
     // scaled copies are tile-major (a_tile_offset): the wave's 16 x 32 A block is
     // 1 KB of consecutive bytes in lane order.
     // Chunk i0's A goes to ring slot ((i0 - c0) / 32) % kMfmaASlots of this wave:
-    // a direct global-to-LDS load puts lane l's 16 bytes at slot + 16 l, exactly
-    // where the same lane reads them back.
+    // a direct buffer-to-LDS load puts lane l's 16 bytes at slot + 16 l, exactly
+    // where the same lane reads them back. The loads address the scaled copies
+    // through buffer descriptors: the lane's byte offset (16 l) stays in one
+    // register and the chunk's offset is a scalar, so moving to the next chunk
+    // costs no vector instruction.
     const size_t a_row = (size_t)(jt0 >> 4) * (size_t)(ld >> 5);
     unsigned char *const my_ring = s.aring + (size_t)wave * kMfmaASlots * 2048;
     auto slot_of = [&](int i0, int c0) { return my_ring + (size_t)(((i0 - c0) >> 5) % kMfmaASlots) * 2048; };
+    const int a_bytes = 2 * ld * ld;                          // each scaled copy: ld x ld bf16
+    const __amdgpu_buffer_rsrc_t hs_r = __builtin_amdgcn_make_buffer_rsrc((void *)hs, (short)0, a_bytes, kBufWord3);
+    const __amdgpu_buffer_rsrc_t ls_r = __builtin_amdgcn_make_buffer_rsrc((void *)ls, (short)0, a_bytes, kBufWord3);
+    const uint32_t lane_off = 16u * (uint32_t)lane;
     auto load_a = [&](int i0, int c0) {
-        const size_t off = (a_row + (size_t)(i0 >> 5)) * 512 + (size_t)lane * 8;
+        const uint32_t tile_off = (uint32_t)((a_row + (size_t)(i0 >> 5)) * 1024);   // uniform
         unsigned char *sl = slot_of(i0, c0);
-        __builtin_amdgcn_global_load_lds((const void *)(hs + off), (__attribute__((address_space(3))) void *)sl, 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((const void *)(ls + off), (__attribute__((address_space(3))) void *)(sl + 1024), 16,
-                                         0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(hs_r, (__attribute__((address_space(3))) void *)sl, 16, lane_off,
+                                                 tile_off, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ls_r, (__attribute__((address_space(3))) void *)(sl + 1024), 16,
+                                                 lane_off, tile_off, 0, 0);
     };
     auto read_a = [&](int i0, int c0, uint4 &ah, uint4 &al) {
         const unsigned char *sl = slot_of(i0, c0);
