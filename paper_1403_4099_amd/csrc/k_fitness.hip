@@ -187,6 +187,7 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int 
     }
     const int32_t *__restrict__ labels = d.pop[parity];
     const double *__restrict__ C = d.C;
+    const __amdgpu_buffer_rsrc_t c_r = __builtin_amdgcn_make_buffer_rsrc((void *)C, (short)0, 8 * N * N, kBufWord3);   // N <= 4096
 
     auto fetch_labels = [&](int i0, int *v) {
         const int ir = i0 + lane;
@@ -228,12 +229,16 @@ __global__ __launch_bounds__(256) void k_pairsum_fp64(Tables t, int parity, int 
         store_labels(0, nxt);
         // Chunks before the last hold rows i < 64 jb <= j (and i < N) only, so their C
         // loads need no test; lanes past N read column N - 1 and are never stored.
+        // Those loads go through a buffer descriptor over C: the lane's column offset
+        // stays in one register and the row offset is a scalar, so a load costs no
+        // vector address arithmetic.
         const int jc = jok ? j : N - 1;
+        const uint32_t jc_off = 8u * (uint32_t)jc;
         auto chunk = [&](auto checked_tag, int ch) {
             constexpr bool checked = decltype(checked_tag)::value;
             auto cload = [&](int i) -> double {
                 if constexpr (checked) return fp64_c(C, N, i, j);
-                else return gld(C + (size_t)i * N + jc);
+                else return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(c_r, jc_off, 8u * (uint32_t)i * (uint32_t)N, 0));
             };
             const int i0 = ch * 64;
             const int buf = ch & 1;

@@ -65,9 +65,6 @@ constexpr int kCodeShift = 8;
 constexpr uint16_t kOneHot = 0x0100;        // bf16 2^-125
 constexpr uint8_t kCodeNone = 0xFF;         // row label not present in the column block
 constexpr uint32_t kCodeFree = 0xFE;        // column of a group left unused: matches no row
-// Fourth word of a raw buffer descriptor (no swizzle, no stride, 32-bit data
-// format): byte addressing from the base, loads past num_records return zero.
-constexpr int kBufWord3 = 0x00020000;
 
 __device__ __forceinline__ uint32_t onehot2(uint32_t rows2, uint32_t col2) {
     const u16x2 x = __builtin_bit_cast(u16x2, rows2 ^ col2);

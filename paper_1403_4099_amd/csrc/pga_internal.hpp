@@ -88,6 +88,9 @@ constexpr int kMfmaCols = 16 * kMfmaWaves;         // columns per workgroup
 constexpr int kMfmaRowCodes = 8192;                // row codes staged in LDS per workgroup (column kernel)
 constexpr int kMfmaFlushRows = 512;                // FP32 accumulators are flushed to FP64 every 512 rows
 constexpr int kMaxLdsBytes = 65536;                // LDS a workgroup may allocate
+// Fourth word of a raw buffer descriptor (no swizzle, no stride, 32-bit data
+// format): byte addressing from the base, loads past num_records return zero.
+constexpr int kBufWord3 = 0x00020000;
 
 inline int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 // Pair-sum tiles fold the triangle: column blocks jb and n_jb - 1 - jb share a workgroup.
