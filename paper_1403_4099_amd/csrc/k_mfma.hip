@@ -44,8 +44,10 @@
 // exactly the split part, as with a one-hot of 1.0.
 //
 // A is loaded once per (wave, chunk), one chunk ahead, by direct
-// global-to-LDS loads into a two-slot ring per wave (no registers hold it in
-// flight), and reused by every individual or column group. FP32
+// memory-to-LDS loads into a two-slot ring per wave (no registers hold it in
+// flight; the column kernel addresses them through buffer descriptors, the
+// packed kernel through global addresses), and reused by every individual or
+// column group. FP32
 // accumulation is flushed into FP64 at every 512-row boundary (no FP32 partial
 // sum spans more than 512 rows). Both kernels give the same sums bit for bit:
 // a stock's column holds the same one-hot values in either, and its FP32
@@ -96,7 +98,7 @@ __host__ __device__ constexpr int mfma_pos(int b) {
 // rows 2q (low half) and 2q + 1 of individual b; then the label -> code
 // tables [B][cstride] (bytes, cstride >= N); then each wave's ring of
 // kMfmaASlots A slots, 2 KB each (the 16 x 32 hi tile, then the lo tile, in
-// lane order), filled by direct global-to-LDS loads one chunk ahead.
+// lane order), filled by direct buffer-to-LDS loads one chunk ahead.
 struct MfmaLdsCols {
     uint32_t *rows;
     uint8_t *code;
