@@ -439,27 +439,11 @@ __device__ __forceinline__ void finish_terms(const InstDesc &d, int p, int N, co
     }
 }
 
-// Listed (cluster-pair route on): workgroup i takes entry i / slices of
-// slice i mod slices of this parity's dense list, and the workgroups past
-// their slice's length end at once; else workgroup g takes individual g.
-__global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int parity, int listed, int slices,
-                                                        int cap, int32_t *status) {
-    extern __shared__ __align__(16) unsigned char smem[];
+// The finish of individual p of instance k by one kFinThreads workgroup (every
+// thread; the early returns are uniform over the workgroup).
+__device__ __forceinline__ void finish_one(const Tables &t, int k, int p, int max_n, int parity, int32_t *status,
+                                           unsigned char *smem) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
-    int k, p;
-    if (listed) {
-        const int slice = (int)blockIdx.x % slices, at = (int)blockIdx.x / slices;
-        const int32_t *e = list_entry(t, kListDense, slice, cap, at);   // read with the count: in bounds
-        const int n = *list_count(t, parity, kListDense, slice);
-        p = __builtin_amdgcn_readfirstlane(gld(e));
-        k = __builtin_amdgcn_readfirstlane(gld(e + 1));
-        if (at >= n) return;
-    } else {
-        const int g = blockIdx.x;
-        if (g >= t.inds[t.n_inst]) return;           // the grid may exceed the total (capacity-sized graph)
-        k = find_inst(t.inds, t.n_inst, g);
-        p = g - t.inds[k];
-    }
     const InstDesc &d = t.desc[k];
     if (inst_stopped(d)) return;                     // uniform over the workgroup
     const int N = d.N;
@@ -559,12 +543,48 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int
     finish_terms(d, p, N, cnt, csum, sc, lst, finish_quarter(max_n), red, (int *)(red + 2 * kFinWaves), status);
 }
 
+// Workgroup g takes individual g.
+__global__ __launch_bounds__(kFinThreads) void k_finish(Tables t, int max_n, int parity, int32_t *status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int g = blockIdx.x;
+    if (g >= t.inds[t.n_inst]) return;               // the grid may exceed the total (capacity-sized graph)
+    const int k = find_inst(t.inds, t.n_inst, g);
+    finish_one(t, k, g - t.inds[k], max_n, parity, status, smem);
+}
+
+// Listed (cluster-pair route on, large launches): per slice of this parity's
+// dense list, `per` workgroups (gridDim.x = slices * per) take its entries at,
+// at + per, ... below the slice's length, so a list that is nearly empty costs a
+// small launch rather than a workgroup per possible entry. (A kernel of its own:
+// the loop needs more registers than the one-individual form.)
+__global__ __launch_bounds__(kFinThreads) void k_finish_listed(Tables t, int max_n, int parity, int slices, int cap,
+                                                               int32_t *status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int slice = (int)blockIdx.x % slices, per = (int)gridDim.x / slices;
+    const int n = __builtin_amdgcn_readfirstlane(gld(list_count(t, parity, kListDense, slice)));
+    for (int at = (int)blockIdx.x / slices; at < n; at += per) {
+        const int32_t *e = list_entry(t, kListDense, slice, cap, at);
+        const int p = __builtin_amdgcn_readfirstlane(gld(e));
+        const int k = __builtin_amdgcn_readfirstlane(gld(e + 1));
+        finish_one(t, k, p, max_n, parity, status, smem);
+        __syncthreads();                             // the next entry reuses the LDS
+    }
+}
+
+// Workgroups per dense-list slice in a listed finish (at most the slice capacity).
+constexpr int kFinListPerSlice = 8;
+
 hipError_t launch_finish(Tables t, int total_inds, int max_n, int parity, int listed, int32_t *status,
                          hipStream_t s) {
     if (total_inds <= 0) return hipSuccess;
     const int n_wg = (total_inds + 3) / 4, slices = list_slices(n_wg), cap = list_slice_cap(n_wg);
-    hipLaunchKernelGGL(k_finish, dim3(listed ? slices * cap : total_inds), dim3(kFinThreads),
-                       finish_lds_bytes(max_n), s, t, max_n, parity, listed, slices, cap, status);
+    const int per = cap < kFinListPerSlice ? cap : kFinListPerSlice;
+    if (listed)
+        hipLaunchKernelGGL(k_finish_listed, dim3(slices * per), dim3(kFinThreads), finish_lds_bytes(max_n), s, t, max_n,
+                           parity, slices, cap, status);
+    else
+        hipLaunchKernelGGL(k_finish, dim3(total_inds), dim3(kFinThreads), finish_lds_bytes(max_n), s, t, max_n, parity,
+                           status);
     return hipGetLastError();
 }
 
