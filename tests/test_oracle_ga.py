@@ -171,17 +171,24 @@ def _clusters(lab):
 
 def test_recovers_planted_clusters_config2():
     """N=100 with 10 noise stocks, 500 generations: every planted cluster with loading
-    g >= 0.35 is found exactly, and the best labeling reaches 95% of the planted
+    g >= 0.35 is found exactly; no cluster is merged with another (the label held by
+    most of a planted cluster's stocks is held by no stock outside it) and that label
+    holds at least 60% of the cluster; the best labeling reaches 98% of the planted
     likelihood. (The two weakest clusters of this draw, g = 0.22 and 0.28, are still
-    being assembled at generation 500 with tournament-2 / uniform crossover.)"""
+    being assembled at generation 500 with tournament-2 / uniform crossover: 7 of 10
+    and 4 of 6 stocks.)"""
     w = synth.config2()
     C = O.correlate(w.R)
     pop, fit, st = O.evolve(C, P=w.P, G=w.G, E=w.elites, seed=w.seed)
     lab, bf, _ = O.best(fit, pop)
     found = _clusters(lab)
     for k, gk in enumerate(w.g):
+        members = np.nonzero(w.planted == k)[0]
         if gk >= 0.35:
-            members = tuple(int(i) for i in np.nonzero(w.planted == k)[0])
-            assert members in found
-    assert bf >= 0.95 * O.fitness(C, w.planted[None, :])[0]
+            assert tuple(int(i) for i in members) in found
+        vals, cnts = np.unique(lab[members], return_counts=True)
+        top = vals[np.argmax(cnts)]
+        assert cnts.max() >= 0.6 * len(members)
+        assert np.all(np.isin(np.nonzero(lab == top)[0], members))
+    assert bf >= 0.98 * O.fitness(C, w.planted[None, :])[0]
     assert np.all(np.diff(st[:, 0]) >= 0.0)
